@@ -1,0 +1,177 @@
+"""ctypes binding of the CPU FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the HIP product path never does.
+Arrays here are row-major per atom (positions (N, 3), virials (N, 9) with
+component 3*alpha + beta), independent of the HIP library's SoA layout.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from .build import ensure_built
+
+OK, EINVAL, ENEIGH, EBOX, ENOMEM = 0, 1, 2, 3, 4
+_ERR = {EINVAL: "invalid argument", ENEIGH: "neighbour list overflow",
+        EBOX: "box shorter than 2 r_list", ENOMEM: "out of memory"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}: {_ERR.get(code, '?')}")
+        self.code = code
+
+
+class _Tersoff(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("A", "B", "lam", "mu", "beta", "n", "c", "d", "h", "R", "S")]
+
+
+class _SW(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("epsilon", "sigma", "a", "lam", "gamma", "A", "B", "p", "q")]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = C.CDLL(ensure_built())
+        P = C.c_void_p
+        lib.ora_neighbors_brute.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_int, _ip, _ip]
+        lib.ora_neighbors_cells.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_int, _ip, _ip]
+        for name, st in (("ora_tersoff", _Tersoff), ("ora_sw", _SW)):
+            fn = getattr(lib, name)
+            fn.argtypes = [C.c_long, _dp, _dp, P, _ip, _ip, C.c_int, C.POINTER(st),
+                           _dp, _dp, _dp, _dp, P, P, P, P]
+            fn.restype = C.c_int
+        lib.ora_nve.argtypes = [C.c_int, P, C.c_long, _dp, C.c_double, _dp, _dp, C.c_int,
+                                C.c_double, C.c_double, C.c_int, C.c_int,
+                                _dp, _dp, _dp, _dp, P]
+        lib.ora_wrap.argtypes = [C.c_long, _dp, _dp]
+        lib.ora_wrap.restype = None
+        for name in ("ora_tersoff_g", "ora_tersoff_g_literal", "ora_tersoff_b", "ora_tersoff_db"):
+            getattr(lib, name).argtypes = [C.POINTER(_Tersoff), C.c_double]
+            getattr(lib, name).restype = C.c_double
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def tersoff_params(p: dict) -> _Tersoff:
+    return _Tersoff(**{k: float(p[k]) for k in ("A", "B", "lam", "mu", "beta", "n", "c", "d", "h", "R", "S")})
+
+
+def sw_params(p: dict) -> _SW:
+    return _SW(**{k: float(p[k]) for k in ("epsilon", "sigma", "a", "lam", "gamma", "A", "B", "p", "q")})
+
+
+def wrap(pos, box):
+    lib = _load()
+    out = _f64(pos).copy()
+    lib.ora_wrap(out.shape[0], _f64(box), out)
+    return out
+
+
+def neighbors(pos, box, rlist: float, maxnb: int, method: str = "cells", allow_overflow=False):
+    """Sorted neighbour lists: returns (nn (N,), nl (N, maxnb), padded with -1)."""
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    nn = np.zeros(n, dtype=np.int32)
+    nl = np.full((max(n, 1), maxnb), -1, dtype=np.int32)
+    fn = lib.ora_neighbors_brute if method == "brute" else lib.ora_neighbors_cells
+    st = fn(n, _f64(box), pos, float(rlist), int(maxnb), nn, nl)
+    if st and not (allow_overflow and st == ENEIGH):
+        raise OracleError(st)
+    return nn, nl[:n]
+
+
+def _force(name, params, pos, box, nn, nl, vel=None, want_g=False):
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    maxnb = nl.shape[1] if n else 1
+    nl = np.ascontiguousarray(nl, dtype=np.int32)
+    if n == 0:
+        nl = np.zeros((1, maxnb), dtype=np.int32)
+    nn = np.ascontiguousarray(nn, dtype=np.int32)
+    velc = None if vel is None else _f64(vel)
+    U = np.zeros(max(n, 1))
+    F = np.zeros((max(n, 1), 3))
+    W = np.zeros((max(n, 1), 9))
+    J = np.zeros((max(n, 1), 3))
+    Fp = np.zeros((max(n, 1), 3))
+    WL = np.zeros((max(n, 1), 9))
+    JL = np.zeros((max(n, 1), 3))
+    G = np.zeros((max(n, 1), maxnb, 3)) if want_g else None
+    pr = tersoff_params(params) if name == "ora_tersoff" else sw_params(params)
+    st = getattr(lib, name)(n, _f64(box), pos if n else np.zeros((1, 3)), _ptr(velc), nn if n else np.zeros(1, np.int32),
+                            nl, maxnb, C.byref(pr), U, F, W, J, _ptr(Fp), _ptr(WL), _ptr(JL), _ptr(G))
+    if st:
+        raise OracleError(st)
+    out = dict(U=U[:n], F=F[:n], W=W[:n], J=J[:n], Fpair=Fp[:n], WL=WL[:n], JL=JL[:n])
+    if want_g:
+        out["G"] = G[:n]
+    return out
+
+
+def tersoff(params, pos, box, nn, nl, vel=None, want_g=False):
+    """Per-atom U, F (Algorithm 1 scatter), W, J (pairwise), Fpair, WL, JL[, G]."""
+    return _force("ora_tersoff", params, pos, box, nn, nl, vel, want_g)
+
+
+def sw(params, pos, box, nn, nl, vel=None, want_g=False):
+    return _force("ora_sw", params, pos, box, nn, nl, vel, want_g)
+
+
+def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: float,
+        rlist: float, rebuild_every: int, maxnb: int):
+    """Velocity-Verlet NVE.  Returns dict(pos, vel, U, F, W, J, thermo[n_steps+1, 16])."""
+    lib = _load()
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    n = pos.shape[0]
+    U = np.zeros(n)
+    F = np.zeros((n, 3))
+    W = np.zeros((n, 9))
+    J = np.zeros((n, 3))
+    thermo = np.zeros((n_steps + 1, 16))
+    if potential == "tersoff":
+        pr, pid = tersoff_params(params), 0
+    else:
+        pr, pid = sw_params(params), 1
+    st = lib.ora_nve(pid, C.cast(C.byref(pr), C.c_void_p), n, _f64(box), float(mass), pos, vel,
+                     int(n_steps), float(dt), float(rlist), int(rebuild_every), int(maxnb),
+                     U, F, W, J, _ptr(thermo))
+    if st:
+        raise OracleError(st)
+    return dict(pos=pos, vel=vel, U=U, F=F, W=W, J=J, thermo=thermo)
+
+
+def tersoff_g(params, cs: float, literal: bool = False) -> float:
+    lib = _load()
+    fn = lib.ora_tersoff_g_literal if literal else lib.ora_tersoff_g
+    return fn(C.byref(tersoff_params(params)), float(cs))
+
+
+def tersoff_b(params, zeta: float) -> float:
+    return _load().ora_tersoff_b(C.byref(tersoff_params(params)), float(zeta))
+
+
+def tersoff_db(params, zeta: float) -> float:
+    return _load().ora_tersoff_db(C.byref(tersoff_params(params)), float(zeta))

@@ -1,0 +1,653 @@
+/*
+ * CPU FP64 oracle for the many-body force path (Fan, Chen, Vierimaa, Harju,
+ * "Efficient molecular dynamics simulations with many-body potentials on
+ * graphics processing units").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * HIP path is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+ * table or constant with the HIP library.  Build: gcc -O2 -ffp-contract=off
+ * (no fused multiply-add, no fast-math), see build.py beside this file.
+ *
+ * What it computes, in the paper's order:
+ *   - neighbour lists (Section 2.1, the cutoff-function paragraph): every
+ *     j != i with minimum-image |r_j - r_i|^2 < r_list^2, ascending index;
+ *     a brute-force O(N^2) definition and a linked-cell version;
+ *   - the Tersoff energy (Section 2.1, Eqs. for U, U_ij, b_ij, zeta_ij, g_ijk,
+ *     cos theta_ijk) and forces by the conventional three-loop scatter of
+ *     Algorithm 1 with the force terms F^(ij)_i, F^(ij)_j, F^(ijk)_{i,j,k}
+ *     (Section 2.2);
+ *   - a capture of every force the iteration over atom i scatters: all of
+ *     them are minus gradients of U_i, so the capture yields dU_i/dr_j for
+ *     each neighbour j, from which the paper's pairwise quantities follow:
+ *     F_ij = dU_i/dr_ij - dU_j/dr_ji (Section 2.3), the per-atom virial
+ *     W_i = -1/2 sum_j r_ij (x) F_ij and the per-atom heat current
+ *     J_i = sum_j r_ij (dU_j/dr_ji . v_i) (Section 2.3 and Section 2.4);
+ *   - the LAMMPS-form per-atom virial of Algorithm 1 and the stress-based
+ *     heat current J_i = W_i . v_i (Section 2.3), kept for comparison only;
+ *   - the Stillinger-Weber energy with the same scatter-and-capture scheme
+ *     (the paper names SW in Section 2.4 but prints no formula; the form is
+ *     the 1985 one: two-body phi_2 split half/half, three-body h_ijk assigned
+ *     wholly to its vertex atom i);
+ *   - velocity-Verlet NVE integration (Section 3).
+ *
+ * Readings where the paper is silent (all also recorded in the design doc):
+ *   - f_C, f_R, f_A are Tersoff's 1989 forms: f_R = A exp(-lambda r),
+ *     f_A = B exp(-mu r), f_C = 1 (r < R), 1/2 + 1/2 cos(pi (r-R)/(S-R))
+ *     (R <= r < S), 0 (r >= S);
+ *   - g is evaluated in the algebraically identical cancellation-free form
+ *     g = 1 + c^2 t^2 / (d^2 (d^2 + t^2)), t = h - cos theta;
+ *   - db/dzeta is defined as 0 at zeta = 0 (it multiplies a zero gradient
+ *     there);
+ *   - minimum image d <- d - L rint(d / L), boxes with L >= 2 r_list.
+ *
+ * Layout: every array here is row-major per atom, positions pos[i*3 + a],
+ * lists nl[i*maxnb + m], virials w[i*9 + 3*alpha + beta].
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_OK 0
+#define ORA_EINVAL 1
+#define ORA_ENEIGH 2
+#define ORA_EBOX 3
+#define ORA_ENOMEM 4
+
+typedef struct { double A, B, lam, mu, beta, n, c, d, h, R, S; } ora_tersoff_t;
+typedef struct { double epsilon, sigma, a, lam, gamma, A, B, p, q; } ora_sw_t;
+
+static const double ORA_PI = 3.14159265358979323846;
+
+/* ---------------------------------------------------------------- geometry */
+
+static double wrap1(double x, double L)
+{
+    double r = x - L * floor(x / L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    if (r < 0.0 || r >= L) r = 0.0;
+    return r;
+}
+
+/* r_ij = r_j - r_i under the minimum-image convention. */
+static void min_image(const double *box, const double *ri, const double *rj, double *d)
+{
+    for (int a = 0; a < 3; ++a) {
+        double x = rj[a] - ri[a];
+        x = x - box[a] * rint(x / box[a]);
+        d[a] = x;
+    }
+}
+
+static double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static int check_box(const double *box, double rlist)
+{
+    for (int a = 0; a < 3; ++a)
+        if (!(box[a] >= 2.0 * rlist) || !isfinite(box[a])) return ORA_EBOX;
+    return ORA_OK;
+}
+
+void ora_wrap(long n, const double *box, double *pos)
+{
+    for (long i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) pos[i * 3 + a] = wrap1(pos[i * 3 + a], box[a]);
+}
+
+static void sort_ints(int *v, int n)
+{
+    for (int a = 1; a < n; ++a) {
+        int key = v[a], b = a - 1;
+        while (b >= 0 && v[b] > key) { v[b + 1] = v[b]; --b; }
+        v[b + 1] = key;
+    }
+}
+
+/* Neighbour list by definition: all pairs, O(N^2).  Returns ORA_ENEIGH when
+ * some atom has more than maxnb neighbours (nn[] then holds the true counts,
+ * the stored entries are the first maxnb in ascending order). */
+int ora_neighbors_brute(long n, const double *box, const double *pos, double rlist,
+                        int maxnb, int *nn, int *nl)
+{
+    int st = check_box(box, rlist);
+    if (st) return st;
+    double rl2 = rlist * rlist;
+    int overflow = 0;
+    for (long i = 0; i < n; ++i) {
+        int cnt = 0;
+        for (long j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(box, &pos[i * 3], &pos[j * 3], d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 < rl2) {
+                if (cnt < maxnb) nl[i * maxnb + cnt] = (int)j;
+                ++cnt;
+            }
+        }
+        nn[i] = cnt;
+        if (cnt > maxnb) overflow = 1;
+    }
+    return overflow ? ORA_ENEIGH : ORA_OK;
+}
+
+/* Neighbour list through a linked cell list (cells of side >= r_list). */
+int ora_neighbors_cells(long n, const double *box, const double *pos, double rlist,
+                        int maxnb, int *nn, int *nl)
+{
+    int st = check_box(box, rlist);
+    if (st) return st;
+    int nc[3];
+    for (int a = 0; a < 3; ++a) {
+        /* a small margin keeps the cell side above r_list after rounding */
+        nc[a] = (int)floor(box[a] / (rlist * (1.0 + 1e-9)));
+        if (nc[a] < 1) nc[a] = 1;
+    }
+    long ncell = (long)nc[0] * nc[1] * nc[2];
+    long *head = (long *)malloc(sizeof(long) * (size_t)ncell);
+    long *next = (long *)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+    int *cand = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!head || !next || !cand) { free(head); free(next); free(cand); return ORA_ENOMEM; }
+    for (long c = 0; c < ncell; ++c) head[c] = -1;
+    int *cell_of = (int *)malloc(sizeof(int) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!cell_of) { free(head); free(next); free(cand); return ORA_ENOMEM; }
+    for (long i = n - 1; i >= 0; --i) {
+        long c = 0;
+        for (int a = 2; a >= 0; --a) {
+            double x = wrap1(pos[i * 3 + a], box[a]);
+            int ci = (int)floor(x / (box[a] / nc[a]));
+            if (ci < 0) ci = 0;
+            if (ci >= nc[a]) ci = nc[a] - 1;
+            cell_of[i * 3 + a] = ci;
+            c = c * nc[a] + ci;
+        }
+        next[i] = head[c];
+        head[c] = i;
+    }
+    double rl2 = rlist * rlist;
+    int overflow = 0;
+    for (long i = 0; i < n; ++i) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            if (nc[a] >= 3) { lo[a] = -1; hi[a] = 1; }
+            else if (nc[a] == 2) { lo[a] = 0; hi[a] = 1; }
+            else { lo[a] = 0; hi[a] = 0; }
+        }
+        int ncand = 0;
+        for (int oz = lo[2]; oz <= hi[2]; ++oz)
+            for (int oy = lo[1]; oy <= hi[1]; ++oy)
+                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                    int cx = (cell_of[i * 3 + 0] + ox + nc[0]) % nc[0];
+                    int cy = (cell_of[i * 3 + 1] + oy + nc[1]) % nc[1];
+                    int cz = (cell_of[i * 3 + 2] + oz + nc[2]) % nc[2];
+                    long c = ((long)cz * nc[1] + cy) * nc[0] + cx;
+                    for (long j = head[c]; j >= 0; j = next[j]) {
+                        if (j == i) continue;
+                        double d[3];
+                        min_image(box, &pos[i * 3], &pos[j * 3], d);
+                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        if (r2 < rl2) cand[ncand++] = (int)j;
+                    }
+                }
+        sort_ints(cand, ncand);
+        for (int m = 0; m < ncand && m < maxnb; ++m) nl[i * maxnb + m] = cand[m];
+        nn[i] = ncand;
+        if (ncand > maxnb) overflow = 1;
+    }
+    free(head); free(next); free(cand); free(cell_of);
+    return overflow ? ORA_ENEIGH : ORA_OK;
+}
+
+/* ------------------------------------------------- Tersoff scalar functions */
+
+static double t_fc(const ora_tersoff_t *p, double r)
+{
+    if (r < p->R) return 1.0;
+    if (r >= p->S) return 0.0;
+    return 0.5 + 0.5 * cos(ORA_PI * (r - p->R) / (p->S - p->R));
+}
+
+static double t_dfc(const ora_tersoff_t *p, double r)
+{
+    if (r < p->R || r >= p->S) return 0.0;
+    return -0.5 * ORA_PI / (p->S - p->R) * sin(ORA_PI * (r - p->R) / (p->S - p->R));
+}
+
+static double t_fr(const ora_tersoff_t *p, double r) { return p->A * exp(-p->lam * r); }
+static double t_dfr(const ora_tersoff_t *p, double r) { return -p->lam * p->A * exp(-p->lam * r); }
+static double t_fa(const ora_tersoff_t *p, double r) { return p->B * exp(-p->mu * r); }
+static double t_dfa(const ora_tersoff_t *p, double r) { return -p->mu * p->B * exp(-p->mu * r); }
+
+/* g(cos theta) = 1 + c^2/d^2 - c^2/(d^2 + (h - cos theta)^2), written without
+ * the cancellation of the two large terms. */
+static double t_g(const ora_tersoff_t *p, double cs)
+{
+    double t = p->h - cs;
+    double c2 = p->c * p->c, d2 = p->d * p->d;
+    return 1.0 + c2 * t * t / (d2 * (d2 + t * t));
+}
+
+static double t_dg(const ora_tersoff_t *p, double cs)
+{
+    double t = p->h - cs;
+    double c2 = p->c * p->c, d2 = p->d * p->d;
+    double q = d2 + t * t;
+    return -2.0 * c2 * t / (q * q);
+}
+
+/* Public for the tests: the literal printed form of g. */
+double ora_tersoff_g_literal(const ora_tersoff_t *p, double cs)
+{
+    double t = p->h - cs;
+    double c2 = p->c * p->c, d2 = p->d * p->d;
+    return 1.0 + c2 / d2 - c2 / (d2 + t * t);
+}
+
+double ora_tersoff_g(const ora_tersoff_t *p, double cs) { return t_g(p, cs); }
+
+static double t_b(const ora_tersoff_t *p, double zeta)
+{
+    if (zeta <= 0.0) return 1.0;
+    return pow(1.0 + pow(p->beta * zeta, p->n), -1.0 / (2.0 * p->n));
+}
+
+static double t_db(const ora_tersoff_t *p, double zeta)
+{
+    if (zeta <= 0.0) return 0.0;
+    double u = pow(p->beta * zeta, p->n);
+    double b = pow(1.0 + u, -1.0 / (2.0 * p->n));
+    return -b * u / (2.0 * zeta * (1.0 + u));
+}
+
+double ora_tersoff_b(const ora_tersoff_t *p, double zeta) { return t_b(p, zeta); }
+double ora_tersoff_db(const ora_tersoff_t *p, double zeta) { return t_db(p, zeta); }
+
+/* Gradients of f_C(r_ik) g(cos theta_ijk) with respect to the absolute
+ * positions r_i, r_j and r_k (used by F^(ijk)_{i,j,k}). */
+static void t_grad_fcg(const ora_tersoff_t *p, const double *rij, double r_ij,
+                       const double *rik, double r_ik,
+                       double *gi, double *gj, double *gk)
+{
+    double cs = dot3(rij, rik) / (r_ij * r_ik);
+    double fc = t_fc(p, r_ik), dfc = t_dfc(p, r_ik);
+    double g = t_g(p, cs), dg = t_dg(p, cs);
+    for (int a = 0; a < 3; ++a) {
+        double uij = rij[a] / r_ij, uik = rik[a] / r_ik;
+        double dcos_j = (uik - cs * uij) / r_ij;   /* d cos / d r_j */
+        double dcos_k = (uij - cs * uik) / r_ik;   /* d cos / d r_k */
+        double dcos_i = -(dcos_j + dcos_k);        /* d cos / d r_i */
+        gj[a] = fc * dg * dcos_j;
+        gk[a] = dfc * uik * g + fc * dg * dcos_k;
+        gi[a] = -dfc * uik * g + fc * dg * dcos_i;
+    }
+}
+
+static int find_slot(const int *nn, const int *nl, int maxnb, long j, long i)
+{
+    int cnt = nn[j] < maxnb ? nn[j] : maxnb;
+    for (int s = 0; s < cnt; ++s)
+        if (nl[j * maxnb + s] == (int)i) return s;
+    return -1;
+}
+
+/* Pairwise post-pass shared by both potentials: from the captured
+ * G[i][m] = dU_i/dr_{NL_im} build F_ij, W_i, J_i and sum_j F_ij. */
+static int pairwise_post(long n, const double *box, const double *pos, const double *vel,
+                         const int *nn, const int *nl, int maxnb, const double *G,
+                         double *W, double *J, double *Fpair)
+{
+    for (long i = 0; i < n; ++i) {
+        double w[9] = {0}, jj[3] = {0}, fp[3] = {0};
+        int cnt = nn[i];
+        for (int m = 0; m < cnt; ++m) {
+            long j = nl[i * maxnb + m];
+            int s = find_slot(nn, nl, maxnb, j, i);
+            if (s < 0) return ORA_EINVAL;          /* lists must be symmetric */
+            const double *dij = &G[((size_t)i * maxnb + m) * 3];
+            const double *dji = &G[((size_t)j * maxnb + s) * 3];
+            double rij[3];
+            min_image(box, &pos[i * 3], &pos[j * 3], rij);
+            double fij[3];
+            for (int a = 0; a < 3; ++a) fij[a] = dij[a] - dji[a];
+            for (int a = 0; a < 3; ++a) fp[a] += fij[a];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) w[3 * a + b] -= 0.5 * rij[a] * fij[b];
+            if (vel) {
+                double proj = dot3(dji, &vel[i * 3]);
+                for (int a = 0; a < 3; ++a) jj[a] += rij[a] * proj;
+            }
+        }
+        if (W) memcpy(&W[i * 9], w, sizeof w);
+        if (J) memcpy(&J[i * 3], jj, sizeof jj);
+        if (Fpair) memcpy(&Fpair[i * 3], fp, sizeof fp);
+    }
+    return ORA_OK;
+}
+
+static void stress_current(long n, const double *WL, const double *vel, double *JL)
+{
+    for (long i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < 3; ++b) s += WL[i * 9 + 3 * a + b] * (vel ? vel[i * 3 + b] : 0.0);
+            JL[i * 3 + a] = s;
+        }
+}
+
+/* Tersoff, conventional Algorithm 1 with capture.
+ * In:  pos[n*3] (wrapped), vel[n*3] or NULL, nn[n], nl[n*maxnb] (symmetric,
+ *      ascending), p.
+ * Out: U[n], F[n*3] (scatter), W[n*9], J[n*3] (pairwise, the paper's), and
+ *      optionally Fpair[n*3] = sum_j F_ij, WL[n*9] (LAMMPS form), JL[n*3]
+ *      (stress-based), G[n*maxnb*3] = dU_i/dr_{NL_im}.  NULL skips an output. */
+int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
+                const int *nn, const int *nl, int maxnb, const ora_tersoff_t *p,
+                double *U, double *F, double *W, double *J,
+                double *Fpair, double *WL, double *JL, double *Gout)
+{
+    for (long i = 0; i < n; ++i)
+        if (nn[i] > maxnb) return ORA_ENEIGH;
+    size_t gsz = (size_t)(n > 0 ? n : 1) * maxnb * 3;
+    double *G = Gout ? Gout : (double *)malloc(sizeof(double) * gsz);
+    double *wl = (double *)calloc((size_t)(n > 0 ? n : 1) * 9, sizeof(double));
+    if (!G || !wl) { if (!Gout) free(G); free(wl); return ORA_ENOMEM; }
+    memset(G, 0, sizeof(double) * gsz);
+    for (long i = 0; i < n; ++i) {          /* Algorithm 1, lines 1-3 */
+        U[i] = 0.0;
+        F[i * 3 + 0] = F[i * 3 + 1] = F[i * 3 + 2] = 0.0;
+    }
+    for (long i = 0; i < n; ++i) {
+        int cnt = nn[i];
+        for (int m = 0; m < cnt; ++m) {
+            long j = nl[i * maxnb + m];
+            double rij[3];
+            min_image(box, &pos[i * 3], &pos[j * 3], rij);
+            double r = sqrt(dot3(rij, rij));
+            if (r >= p->S) continue;          /* f_C(r_ij) = 0: no contribution */
+            /* zeta_ij and the bond order, recomputed here: the conventional
+             * method has no precompute. */
+            double zeta = 0.0;
+            for (int q = 0; q < cnt; ++q) {
+                if (q == m) continue;
+                long k = nl[i * maxnb + q];
+                double rik[3];
+                min_image(box, &pos[i * 3], &pos[k * 3], rik);
+                double rk = sqrt(dot3(rik, rik));
+                if (rk >= p->S) continue;
+                double cs = dot3(rij, rik) / (r * rk);
+                zeta += t_fc(p, rk) * t_g(p, cs);
+            }
+            double b = t_b(p, zeta), db = t_db(p, zeta);
+            double fc = t_fc(p, r), dfc = t_dfc(p, r);
+            double fr = t_fr(p, r), dfr = t_dfr(p, r);
+            double fa = t_fa(p, r), dfa = t_dfa(p, r);
+            U[i] += 0.5 * fc * (fr - b * fa);                       /* line 7 */
+            /* F^(ij)_i and F^(ij)_j: d/dr_j f(r_ij) = f' u_ij, d/dr_i = -f' u_ij */
+            double d_fcfr = dfc * fr + fc * dfr, d_fcfa = dfc * fa + fc * dfa;
+            double fij_i[3], fij_j[3];
+            for (int a = 0; a < 3; ++a) {
+                double u = rij[a] / r;
+                fij_i[a] = -0.5 * d_fcfr * (-u) + 0.5 * b * d_fcfa * (-u);
+                fij_j[a] = -0.5 * d_fcfr * u + 0.5 * b * d_fcfa * u;
+            }
+            for (int a = 0; a < 3; ++a) {
+                F[i * 3 + a] += fij_i[a];                          /* line 8 */
+                F[j * 3 + a] += fij_j[a];                          /* line 9 */
+                G[((size_t)i * maxnb + m) * 3 + a] -= fij_j[a];
+            }
+            /* Line 10 credits atom i with half the two-body virial of this
+             * term; the other half goes to j, as LAMMPS's per-atom tally does,
+             * so that the LAMMPS-form per-atom virials sum to the total. */
+            for (int a = 0; a < 3; ++a)
+                for (int bb = 0; bb < 3; ++bb) {
+                    wl[i * 9 + 3 * a + bb] -= 0.5 * rij[a] * fij_i[bb];
+                    wl[j * 9 + 3 * a + bb] -= 0.5 * rij[a] * fij_i[bb];
+                }
+            double pref = 0.5 * fc * fa * db;
+            for (int q = 0; q < cnt; ++q) {                        /* lines 11-25 */
+                if (q == m) continue;
+                long k = nl[i * maxnb + q];
+                double rik[3];
+                min_image(box, &pos[i * 3], &pos[k * 3], rik);
+                double rk = sqrt(dot3(rik, rik));
+                if (rk >= p->S) continue;
+                double gi[3], gj[3], gk[3];
+                t_grad_fcg(p, rij, r, rik, rk, gi, gj, gk);
+                double fi[3], fj[3], fk[3];
+                for (int a = 0; a < 3; ++a) {
+                    fi[a] = pref * gi[a];
+                    fj[a] = pref * gj[a];
+                    fk[a] = pref * gk[a];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    F[i * 3 + a] += fi[a];
+                    F[j * 3 + a] += fj[a];
+                    F[k * 3 + a] += fk[a];
+                    G[((size_t)i * maxnb + m) * 3 + a] -= fj[a];
+                    G[((size_t)i * maxnb + q) * 3 + a] -= fk[a];
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int bb = 0; bb < 3; ++bb) {
+                        double w = (rij[a] * fj[bb] + rik[a] * fk[bb]) / 3.0;
+                        wl[i * 9 + 3 * a + bb] += w;
+                        wl[j * 9 + 3 * a + bb] += w;
+                        wl[k * 9 + 3 * a + bb] += w;
+                    }
+            }
+        }
+    }
+    int st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, W, J, Fpair);
+    if (WL) memcpy(WL, wl, sizeof(double) * 9 * (size_t)n);
+    if (JL) stress_current(n, wl, vel, JL);
+    if (!Gout) free(G);
+    free(wl);
+    return st;
+}
+
+/* ----------------------------------------------------- Stillinger-Weber */
+
+static double sw_phi2(const ora_sw_t *p, double r)
+{
+    double rc = p->a * p->sigma;
+    if (r >= rc) return 0.0;
+    double sr = p->sigma / r;
+    return p->epsilon * p->A * (p->B * pow(sr, p->p) - pow(sr, p->q)) *
+           exp(p->sigma / (r - rc));
+}
+
+static double sw_dphi2(const ora_sw_t *p, double r)
+{
+    double rc = p->a * p->sigma;
+    if (r >= rc) return 0.0;
+    double e = exp(p->sigma / (r - rc));
+    double poly = p->B * pow(p->sigma / r, p->p) - pow(p->sigma / r, p->q);
+    double dpoly = (-p->p * p->B * pow(p->sigma / r, p->p) + p->q * pow(p->sigma / r, p->q)) / r;
+    double de = -e * p->sigma / ((r - rc) * (r - rc));
+    return p->epsilon * p->A * (dpoly * e + poly * de);
+}
+
+/* SW per-atom energy U_i = 1/2 sum_j phi_2(r_ij) + sum_{j<k} h_ijk with
+ * h_ijk = eps lambda exp(gamma sigma/(r_ij - a sigma) + gamma sigma/(r_ik - a sigma))
+ *         (cos theta_ijk + 1/3)^2, scattered conventionally with capture. */
+int ora_sw(long n, const double *box, const double *pos, const double *vel,
+           const int *nn, const int *nl, int maxnb, const ora_sw_t *p,
+           double *U, double *F, double *W, double *J,
+           double *Fpair, double *WL, double *JL, double *Gout)
+{
+    for (long i = 0; i < n; ++i)
+        if (nn[i] > maxnb) return ORA_ENEIGH;
+    size_t gsz = (size_t)(n > 0 ? n : 1) * maxnb * 3;
+    double *G = Gout ? Gout : (double *)malloc(sizeof(double) * gsz);
+    double *wl = (double *)calloc((size_t)(n > 0 ? n : 1) * 9, sizeof(double));
+    if (!G || !wl) { if (!Gout) free(G); free(wl); return ORA_ENOMEM; }
+    memset(G, 0, sizeof(double) * gsz);
+    double rc = p->a * p->sigma;
+    for (long i = 0; i < n; ++i) {
+        U[i] = 0.0;
+        F[i * 3 + 0] = F[i * 3 + 1] = F[i * 3 + 2] = 0.0;
+    }
+    for (long i = 0; i < n; ++i) {
+        int cnt = nn[i];
+        for (int m = 0; m < cnt; ++m) {
+            long j = nl[i * maxnb + m];
+            double rij[3];
+            min_image(box, &pos[i * 3], &pos[j * 3], rij);
+            double r = sqrt(dot3(rij, rij));
+            if (r >= rc) continue;
+            U[i] += 0.5 * sw_phi2(p, r);
+            double dp = sw_dphi2(p, r);
+            double fj[3], fi[3];
+            for (int a = 0; a < 3; ++a) {
+                double u = rij[a] / r;
+                fj[a] = -0.5 * dp * u;     /* -d(phi_2/2)/dr_j */
+                fi[a] = 0.5 * dp * u;      /* -d(phi_2/2)/dr_i */
+            }
+            for (int a = 0; a < 3; ++a) {
+                F[i * 3 + a] += fi[a];
+                F[j * 3 + a] += fj[a];
+                G[((size_t)i * maxnb + m) * 3 + a] -= fj[a];
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int bb = 0; bb < 3; ++bb) {
+                    wl[i * 9 + 3 * a + bb] -= 0.5 * rij[a] * fi[bb];
+                    wl[j * 9 + 3 * a + bb] -= 0.5 * rij[a] * fi[bb];
+                }
+            for (int q = m + 1; q < cnt; ++q) {
+                long k = nl[i * maxnb + q];
+                double rik[3];
+                min_image(box, &pos[i * 3], &pos[k * 3], rik);
+                double rk = sqrt(dot3(rik, rik));
+                if (rk >= rc) continue;
+                double cs = dot3(rij, rik) / (r * rk);
+                double ex = p->epsilon * p->lam *
+                            exp(p->gamma * p->sigma / (r - rc) + p->gamma * p->sigma / (rk - rc));
+                double ang = cs + 1.0 / 3.0;
+                double h = ex * ang * ang;
+                U[i] += h;
+                double dh_drij = -h * p->gamma * p->sigma / ((r - rc) * (r - rc));
+                double dh_drik = -h * p->gamma * p->sigma / ((rk - rc) * (rk - rc));
+                double dh_dcos = 2.0 * ex * ang;
+                double gj[3], gk[3], gi[3];
+                for (int a = 0; a < 3; ++a) {
+                    double uij = rij[a] / r, uik = rik[a] / rk;
+                    double dcos_j = (uik - cs * uij) / r;
+                    double dcos_k = (uij - cs * uik) / rk;
+                    gj[a] = dh_drij * uij + dh_dcos * dcos_j;    /* dh/dr_j */
+                    gk[a] = dh_drik * uik + dh_dcos * dcos_k;    /* dh/dr_k */
+                    gi[a] = -(gj[a] + gk[a]);                    /* dh/dr_i */
+                }
+                double f3i[3], f3j[3], f3k[3];
+                for (int a = 0; a < 3; ++a) {
+                    f3i[a] = -gi[a]; f3j[a] = -gj[a]; f3k[a] = -gk[a];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    F[i * 3 + a] += f3i[a];
+                    F[j * 3 + a] += f3j[a];
+                    F[k * 3 + a] += f3k[a];
+                    G[((size_t)i * maxnb + m) * 3 + a] -= f3j[a];
+                    G[((size_t)i * maxnb + q) * 3 + a] -= f3k[a];
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int bb = 0; bb < 3; ++bb) {
+                        double w = (rij[a] * f3j[bb] + rik[a] * f3k[bb]) / 3.0;
+                        wl[i * 9 + 3 * a + bb] += w;
+                        wl[j * 9 + 3 * a + bb] += w;
+                        wl[k * 9 + 3 * a + bb] += w;
+                    }
+            }
+        }
+    }
+    int st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, W, J, Fpair);
+    if (WL) memcpy(WL, wl, sizeof(double) * 9 * (size_t)n);
+    if (JL) stress_current(n, wl, vel, JL);
+    if (!Gout) free(G);
+    free(wl);
+    return st;
+}
+
+/* ------------------------------------------------------------------- NVE */
+
+#define ORA_KAPPA 9.64853321567e-3     /* eV/(A amu) in A/fs^2 */
+#define ORA_KB 8.617333262e-5          /* eV/K */
+
+static int evaluate(int potential, const void *params, long n, const double *box,
+                    const double *pos, const double *vel, const int *nn, const int *nl,
+                    int maxnb, double *U, double *F, double *W, double *J, double *G)
+{
+    if (potential == 0)
+        return ora_tersoff(n, box, pos, vel, nn, nl, maxnb, (const ora_tersoff_t *)params,
+                           U, F, W, J, NULL, NULL, NULL, G);
+    return ora_sw(n, box, pos, vel, nn, nl, maxnb, (const ora_sw_t *)params,
+                  U, F, W, J, NULL, NULL, NULL, G);
+}
+
+static void thermo_row(long n, double mass, const double *U, const double *vel,
+                       const double *W, const double *J, double *row)
+{
+    memset(row, 0, sizeof(double) * 16);
+    double ep = 0.0, ek = 0.0;
+    for (long i = 0; i < n; ++i) {
+        ep += U[i];
+        ek += 0.5 * mass * dot3(&vel[i * 3], &vel[i * 3]) / ORA_KAPPA;
+        for (int c = 0; c < 9; ++c) row[2 + c] += W[i * 9 + c];
+        for (int c = 0; c < 3; ++c) row[11 + c] += J[i * 3 + c];
+    }
+    row[0] = ep;
+    row[1] = ek;
+    row[14] = ep + ek;
+    row[15] = n > 1 ? 2.0 * ek / ((3.0 * n - 3.0) * ORA_KB) : 0.0;
+}
+
+/* Velocity-Verlet NVE.  pos/vel are advanced in place; the lists are rebuilt
+ * (cell method) before the force evaluation of every step s with
+ * s % rebuild_every == 0 (s = 0 is the evaluation at the start).  thermo is
+ * [n_steps + 1][16]: 0 E_pot, 1 E_kin, 2..10 W (row-major), 11..13 J,
+ * 14 E_pot + E_kin, 15 kinetic temperature (3N - 3 degrees of freedom).
+ * U, F, W, J hold the final step's per-atom values. */
+int ora_nve(int potential, const void *params, long n, const double *box, double mass,
+            double *pos, double *vel, int n_steps, double dt, double rlist,
+            int rebuild_every, int maxnb, double *U, double *F, double *W, double *J,
+            double *thermo)
+{
+    if (n < 1 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !(mass > 0.0))
+        return ORA_EINVAL;
+    int st = check_box(box, rlist);
+    if (st) return st;
+    int *nn = (int *)malloc(sizeof(int) * (size_t)n);
+    int *nl = (int *)malloc(sizeof(int) * (size_t)n * maxnb);
+    double *G = (double *)malloc(sizeof(double) * (size_t)n * maxnb * 3);
+    if (!nn || !nl || !G) { free(nn); free(nl); free(G); return ORA_ENOMEM; }
+    ora_wrap(n, box, pos);
+    st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
+    if (!st) st = evaluate(potential, params, n, box, pos, vel, nn, nl, maxnb, U, F, W, J, G);
+    if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[0]);
+    double half = 0.5 * dt * ORA_KAPPA / mass;
+    for (int s = 1; s <= n_steps && !st; ++s) {
+        for (long i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                vel[i * 3 + a] += half * F[i * 3 + a];
+                pos[i * 3 + a] += dt * vel[i * 3 + a];
+            }
+        ora_wrap(n, box, pos);
+        if (s % rebuild_every == 0) {
+            st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
+            if (st) break;
+        }
+        /* Forces at the new positions.  J needs the full-step velocity, so it
+         * is formed from the captured partials after the second half-kick. */
+        st = evaluate(potential, params, n, box, pos, NULL, nn, nl, maxnb, U, F, W, J, G);
+        if (st) break;
+        for (long i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) vel[i * 3 + a] += half * F[i * 3 + a];
+        st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, NULL, J, NULL);
+        if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[(size_t)s * 16]);
+    }
+    free(G);
+    free(nn);
+    free(nl);
+    return st;
+}
