@@ -1,0 +1,161 @@
+/*
+ * mbmd.h -- C ABI of libmbmd: write-conflict-free force evaluation for
+ * many-body potentials (Tersoff, Stillinger-Weber) on one MI355X (gfx950).
+ *
+ * Method: Fan, Chen, Vierimaa, Harju, "Efficient molecular dynamics
+ * simulations with many-body potentials on graphics processing units".
+ * The force on atom i is the sum of explicit pairwise forces
+ * F_ij = dU_i/dr_ij - dU_j/dr_ji (Section 2.3, general form Section 2.4); the
+ * per-atom virial W_i = -1/2 sum_j r_ij (x) F_ij and the per-atom heat current
+ * J_i = sum_j r_ij (dU_j/dr_ji . v_i) (Section 2.3) are accumulated by the
+ * thread that owns atom i, so no result is written by two threads and no
+ * atomic operation touches a result.
+ *
+ * Conventions for every call:
+ *  - Units: Angstrom, eV, amu, fs.  W_i is in eV (not divided by a volume),
+ *    J_i in eV*Angstrom/fs.
+ *  - r_ij = r_j - r_i under the minimum-image convention (Section 2.1).
+ *  - Device arrays are structure-of-arrays, FP64, caller-owned: positions and
+ *    velocities [3][n], forces [3][n], heat current [3][n], energy [n],
+ *    virial [9][n] with component 3*alpha + beta holding
+ *    W^{alpha beta} = -1/2 sum_j r_ij^alpha F_ij^beta.
+ *  - Boxes are orthorhombic and periodic in all three directions; box[3]
+ *    is a HOST array of edge lengths, each at least 2 * (cutoff + skin).
+ *  - Positions may be given unwrapped; positions returned are wrapped into
+ *    [0, L).
+ *  - types may be NULL (all atoms of the one species); otherwise every entry
+ *    must be 0 (single-element potentials).
+ *  - Every call enqueues its work on the context's stream and returns after
+ *    synchronising that stream, with the device status folded into the
+ *    return code.  Outputs are unspecified when a call fails.
+ *  - A context is not thread-safe; use one context per host thread and
+ *    stream.  The library never frees caller memory.
+ *  - Results are bitwise reproducible from run to run (fixed summation
+ *    orders, sorted neighbour lists).
+ */
+#ifndef MBMD_H
+#define MBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MBMD_OK = 0,
+    MBMD_EINVAL = 1,      /* invalid argument (null pointer, bad size, type != 0) */
+    MBMD_ENOMEM = 2,      /* device allocation failed or bound workspace too small */
+    MBMD_EDEVICE = 3,     /* HIP runtime error or internal consistency failure */
+    MBMD_EBOX = 4,        /* a box edge is shorter than 2 (cutoff + skin) or not finite */
+    MBMD_ENEIGH = 5,      /* a neighbour list needed more than max_neighbors slots */
+    MBMD_ESKIN = 6,       /* an atom moved more than skin/2 between list builds */
+    MBMD_ENONFINITE = 7,  /* a non-finite position */
+    MBMD_ENOPOT = 8       /* no potential set on the context */
+} mbmd_status;
+
+typedef enum {
+    MBMD_FP64 = 0,        /* all arithmetic in FP64 */
+    MBMD_MIXED = 1        /* bond-order and force arithmetic in FP32; positions,
+                             integrator and the per-atom U, F, W, J accumulators
+                             in FP64 */
+} mbmd_precision;
+
+/* Tersoff potential in the single-element form of Section 2.1: U = 1/2 sum
+ * U_ij, U_ij = f_C (f_R - b_ij f_A), b_ij = (1 + beta^n zeta_ij^n)^(-1/(2n)),
+ * zeta_ij = sum_k f_C(r_ik) g_ijk, g = 1 + c^2/d^2 - c^2/(d^2 + (h - cos)^2),
+ * with f_R = A exp(-lambda r), f_A = B exp(-mu r) and
+ * f_C = 1 (r < R), 1/2 + 1/2 cos(pi (r - R)/(S - R)) (R <= r < S), 0 beyond. */
+typedef struct {
+    double A, B, lambda, mu, beta, n, c, d, h, R, S;
+} mbmd_tersoff_params;
+
+/* Stillinger-Weber potential (the paper's second many-body potential,
+ * Section 2.4): U_i = 1/2 sum_j phi2(r_ij) + sum_{j<k} h_ijk with
+ * phi2 = epsilon A (B (sigma/r)^p - (sigma/r)^q) exp(sigma/(r - a sigma)),
+ * h_ijk = epsilon lambda exp(gamma sigma/(r_ij - a sigma)
+ *         + gamma sigma/(r_ik - a sigma)) (cos theta_jik + 1/3)^2, cutoff a sigma. */
+typedef struct {
+    double epsilon, sigma, a, lambda, gamma, A, B, p, q;
+} mbmd_sw_params;
+
+typedef struct mbmd_ctx mbmd_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL means the default stream).  The stream is borrowed,
+ * not owned.  *out receives the context.  The context starts with no
+ * potential, skin 0.5 A and an automatic list capacity. */
+mbmd_status mbmd_create(mbmd_ctx **out, int device, void *hip_stream);
+
+/* Destroy a context and free the device memory it allocated itself. */
+void mbmd_destroy(mbmd_ctx *ctx);
+
+/* Text of the last error on this context (owned by the context; valid until
+ * the next call on it). */
+const char *mbmd_last_error(const mbmd_ctx *ctx);
+
+/* Select the Tersoff potential with parameters *p (copied). */
+mbmd_status mbmd_set_tersoff(mbmd_ctx *ctx, const mbmd_tersoff_params *p);
+
+/* Select the Stillinger-Weber potential with parameters *p (copied). */
+mbmd_status mbmd_set_sw(mbmd_ctx *ctx, const mbmd_sw_params *p);
+
+/* Neighbour-list settings (Section 2.1: Verlet list built with a cell list).
+ * The list radius is the potential cutoff plus `skin` (>= 0).
+ * `max_neighbors` is the list capacity per atom, 1..64, or 0 for the default
+ * (16 for Tersoff, 32 for Stillinger-Weber). */
+mbmd_status mbmd_set_neighbor(mbmd_ctx *ctx, double skin, int max_neighbors);
+
+/* Current list capacity per atom (resolved default) in *out. */
+mbmd_status mbmd_get_max_neighbors(const mbmd_ctx *ctx, int *out);
+
+/* Device bytes of workspace needed for up to n_atoms atoms with the current
+ * potential and neighbour settings. */
+mbmd_status mbmd_workspace_size(const mbmd_ctx *ctx, int64_t n_atoms, size_t *bytes);
+
+/* Use caller-owned device memory [dev_ptr, dev_ptr + bytes) as workspace
+ * (256-byte aligned).  The caller keeps ownership and must keep it alive
+ * while the context uses it; NULL unbinds.  Without a bound workspace the
+ * context allocates (and grows) its own. */
+mbmd_status mbmd_bind_workspace(mbmd_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Build the neighbour list of n atoms at device positions pos[3][n] and copy
+ * it out: nn[n] (device, true count per atom) and nl[max_neighbors][n]
+ * (device, slot-major, ascending atom index in each list; unused slots are
+ * left untouched).  Atom j is listed for atom i iff j != i and the
+ * minimum-image squared distance, evaluated in FP64 as
+ * (dx*dx + dy*dy) + dz*dz with d <- d - L rint(d/L) and no fused multiply-add,
+ * is below (cutoff + skin)^2. */
+mbmd_status mbmd_neighbors(mbmd_ctx *ctx, int64_t n, const double box[3], const double *pos,
+                           int32_t *nn, int32_t *nl);
+
+/* Single point (the force-evaluation kernel of Section 2.3 with the
+ * bond-order precompute for Tersoff): per-atom energy U[n], force F[3][n],
+ * virial W[9][n] and heat current J[3][n] (all device, caller-owned) for
+ * positions pos[3][n] and velocities vel[3][n] (vel may be NULL: J = 0). */
+mbmd_status mbmd_compute(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const double box[3],
+                         const double *pos, const double *vel, const int32_t *types,
+                         double *U, double *F, double *W, double *J);
+
+/* n_steps of NVE velocity-Verlet integration (the integrator of Section 3,
+ * without thermostat or barostat) at time step dt_fs for atoms of mass
+ * mass_amu.  pos[3][n] and vel[3][n] (device) are advanced in place.  The
+ * forces are evaluated at the start and after every drift; the list is
+ * rebuilt before the evaluation of every step s with s % rebuild_every == 0
+ * (s = 0 included).  U, F, W, J receive the last step's values, J_i formed
+ * with the full-step velocity.  thermo (device, or NULL) receives
+ * [n_steps + 1][16] rows: 0 E_pot, 1 E_kin, 2..10 total W, 11..13 total J,
+ * 14 E_pot + E_kin, 15 kinetic temperature with 3n - 3 degrees of freedom.
+ * Returns MBMD_ESKIN if some atom moved more than skin/2 between builds
+ * (the run then used a list that may have missed pairs). */
+mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const double box[3],
+                         double mass_amu, double *pos, double *vel, const int32_t *types,
+                         double dt_fs, int n_steps, int rebuild_every, double *U, double *F,
+                         double *W, double *J, double *thermo);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBMD_H */

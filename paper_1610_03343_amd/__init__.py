@@ -1,0 +1,234 @@
+"""Python binding of libmbmd (include/mbmd.h): argument marshalling only.
+
+Every step of the force path runs in the HIP kernels of libmbmd.so; this
+module only checks tensor shapes/dtypes/devices, passes raw device pointers
+and the current torch stream, and turns status codes into exceptions.  It
+raises at import time if the library has not been built: there is no CPU
+fallback.
+
+Device arrays are torch tensors of dtype float64 on a HIP device, in the
+library's structure-of-arrays layout: positions/velocities/forces/heat
+current (3, n), energy (n,), virial (9, n) with row 3*alpha + beta.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbmd.so")
+
+MBMD_OK, MBMD_EINVAL, MBMD_ENOMEM, MBMD_EDEVICE, MBMD_EBOX = 0, 1, 2, 3, 4
+MBMD_ENEIGH, MBMD_ESKIN, MBMD_ENONFINITE, MBMD_ENOPOT = 5, 6, 7, 8
+MBMD_FP64, MBMD_MIXED = 0, 1
+STATUS_NAMES = {0: "MBMD_OK", 1: "MBMD_EINVAL", 2: "MBMD_ENOMEM", 3: "MBMD_EDEVICE",
+                4: "MBMD_EBOX", 5: "MBMD_ENEIGH", 6: "MBMD_ESKIN", 7: "MBMD_ENONFINITE",
+                8: "MBMD_ENOPOT"}
+THERMO_COLS = 16
+
+
+class MbmdError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class mbmd_tersoff_params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("A", "B", "lambda_", "mu", "beta", "n", "c", "d", "h", "R", "S")]
+
+
+class mbmd_sw_params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("epsilon", "sigma", "a", "lambda_", "gamma", "A", "B", "p", "q")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_1610_03343_amd/build.py` (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    P, I64, D, I = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    sig = {
+        "mbmd_create": ([C.POINTER(P), I, P], I),
+        "mbmd_destroy": ([P], None),
+        "mbmd_last_error": ([P], C.c_char_p),
+        "mbmd_set_tersoff": ([P, C.POINTER(mbmd_tersoff_params)], I),
+        "mbmd_set_sw": ([P, C.POINTER(mbmd_sw_params)], I),
+        "mbmd_set_neighbor": ([P, D, I], I),
+        "mbmd_get_max_neighbors": ([P, C.POINTER(I)], I),
+        "mbmd_workspace_size": ([P, I64, C.POINTER(C.c_size_t)], I),
+        "mbmd_bind_workspace": ([P, P, C.c_size_t], I),
+        "mbmd_neighbors": ([P, I64, P, P, P, P], I),
+        "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
+        "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _dptr(t, shape, name, dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda:
+        raise TypeError(f"{name} must be a {dtype} tensor on a HIP device")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _box(box):
+    b = (C.c_double * 3)(*[float(x) for x in box])
+    return b
+
+
+def tersoff_struct(p: dict) -> mbmd_tersoff_params:
+    return mbmd_tersoff_params(p["A"], p["B"], p["lam"], p["mu"], p["beta"], p["n"], p["c"],
+                               p["d"], p["h"], p["R"], p["S"])
+
+
+def sw_struct(p: dict) -> mbmd_sw_params:
+    return mbmd_sw_params(p["epsilon"], p["sigma"], p["a"], p["lam"], p["gamma"], p["A"], p["B"],
+                          p["p"], p["q"])
+
+
+def _prec(precision) -> int:
+    if precision in ("fp64", MBMD_FP64):
+        return MBMD_FP64
+    if precision in ("mixed", MBMD_MIXED):
+        return MBMD_MIXED
+    raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
+
+
+class Context:
+    """One mbmd_ctx on a device, enqueuing on a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self._check(_lib.mbmd_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)),
+                    "mbmd_create", ctx=None)
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mbmd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, code, what, ctx="self"):
+        if code != MBMD_OK:
+            msg = what
+            if ctx is not None and getattr(self, "_h", None):
+                msg = f"{what}: {_lib.mbmd_last_error(self._h).decode()}"
+            raise MbmdError(code, msg)
+
+    # -- configuration ------------------------------------------------------
+    def set_tersoff(self, params: dict):
+        st = tersoff_struct(params)
+        self._check(_lib.mbmd_set_tersoff(self._h, C.byref(st)), "mbmd_set_tersoff")
+
+    def set_sw(self, params: dict):
+        st = sw_struct(params)
+        self._check(_lib.mbmd_set_sw(self._h, C.byref(st)), "mbmd_set_sw")
+
+    def set_neighbor(self, skin: float = 0.5, max_neighbors: int = 0):
+        self._check(_lib.mbmd_set_neighbor(self._h, float(skin), int(max_neighbors)),
+                    "mbmd_set_neighbor")
+
+    @property
+    def max_neighbors(self) -> int:
+        v = C.c_int()
+        self._check(_lib.mbmd_get_max_neighbors(self._h, C.byref(v)), "mbmd_get_max_neighbors")
+        return v.value
+
+    def workspace_size(self, n: int) -> int:
+        v = C.c_size_t()
+        self._check(_lib.mbmd_workspace_size(self._h, int(n), C.byref(v)), "mbmd_workspace_size")
+        return v.value
+
+    def bind_workspace(self, buf: torch.Tensor | None):
+        """Bind a caller-owned uint8 device tensor as workspace (None unbinds)."""
+        if buf is None:
+            self._check(_lib.mbmd_bind_workspace(self._h, None, 0), "mbmd_bind_workspace")
+            self._ws = None
+            return
+        if buf.dtype != torch.uint8 or not buf.is_cuda or not buf.is_contiguous():
+            raise TypeError("workspace must be a contiguous uint8 tensor on a HIP device")
+        self._check(_lib.mbmd_bind_workspace(self._h, C.c_void_p(buf.data_ptr()), buf.numel()),
+                    "mbmd_bind_workspace")
+        self._ws = buf
+
+    # -- calls --------------------------------------------------------------
+    def neighbors(self, pos: torch.Tensor, box):
+        n = pos.shape[1]
+        M = self.max_neighbors
+        nn = torch.zeros(n, dtype=torch.int32, device=self.device)
+        nl = torch.full((M, n), -1, dtype=torch.int32, device=self.device)
+        self._check(_lib.mbmd_neighbors(self._h, n, _box(box), _dptr(pos, (3, n), "pos"),
+                                        _dptr(nn, (n,), "nn", torch.int32),
+                                        _dptr(nl, (M, n), "nl", torch.int32)),
+                    "mbmd_neighbors")
+        return nn, nl
+
+    def _outputs(self, n, out):
+        if out is None:
+            z = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
+            out = dict(U=z(n), F=z(3, n), W=z(9, n), J=z(3, n))
+        return out
+
+    def compute(self, pos, box, vel=None, types=None, precision="fp64", out=None):
+        n = pos.shape[1]
+        out = self._outputs(n, out)
+        self._check(_lib.mbmd_compute(
+            self._h, _prec(precision), n, _box(box), _dptr(pos, (3, n), "pos"),
+            _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32),
+            _dptr(out["U"], (n,), "U"), _dptr(out["F"], (3, n), "F"),
+            _dptr(out["W"], (9, n), "W"), _dptr(out["J"], (3, n), "J")), "mbmd_compute")
+        return out
+
+    def nve_run(self, pos, vel, box, mass, dt, n_steps, rebuild_every=20, types=None,
+                precision="fp64", thermo=True, out=None):
+        """Advances pos/vel in place; returns dict(U, F, W, J[, thermo])."""
+        n = pos.shape[1]
+        out = self._outputs(n, out)
+        th = None
+        if thermo is True:
+            th = torch.empty(n_steps + 1, THERMO_COLS, dtype=torch.float64, device=self.device)
+        elif isinstance(thermo, torch.Tensor):
+            th = thermo
+        self._check(_lib.mbmd_nve_run(
+            self._h, _prec(precision), n, _box(box), float(mass), _dptr(pos, (3, n), "pos"),
+            _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32), float(dt),
+            int(n_steps), int(rebuild_every), _dptr(out["U"], (n,), "U"),
+            _dptr(out["F"], (3, n), "F"), _dptr(out["W"], (9, n), "W"),
+            _dptr(out["J"], (3, n), "J"),
+            _dptr(th, (n_steps + 1, THERMO_COLS), "thermo") if th is not None else None),
+            "mbmd_nve_run")
+        if th is not None:
+            out["thermo"] = th
+        return out

@@ -1,0 +1,432 @@
+// C ABI of libmbmd (declared in include/mbmd.h): contexts, workspace, and the
+// host-side step loop that sequences the neighbour build, the site-local
+// partials pass and the pairwise-force pass on one HIP stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/mbmd.h"
+#include "mbmd_internal.h"
+
+using namespace mbmd;
+
+struct mbmd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int potential = -1;          // 0 Tersoff, 1 SW
+    TersoffParams tp{};
+    SWParams sp{};
+    double skin = 0.5;
+    int max_nb = 0;              // 0: potential default
+    void* ws = nullptr;          // workspace base
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    Buffers buf{};
+    int64_t laid_n = -1;         // layout currently held by buf
+    int laid_M = 0;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t cell_cap(int64_t n) { return n * 4 > 64 ? n * 4 : 64; }
+
+int resolved_M(const mbmd_ctx* c)
+{
+    if (c->max_nb > 0) return c->max_nb;
+    return c->potential == 1 ? 32 : 16;
+}
+
+double cutoff_of(const mbmd_ctx* c)
+{
+    return c->potential == 1 ? c->sp.a * c->sp.sigma : c->tp.S;
+}
+
+// Lays out every device array for n atoms and M slots from `base` (or only
+// sizes it when base is null); returns the total byte count.
+size_t layout(int64_t n, int M, char* base, Buffers* b)
+{
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t ncap = cell_cap(nn);
+    const int64_t nscan = (ncap + kBlock * 4 - 1) / (kBlock * 4);
+    const int64_t nblk = blocks_for(nn);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    Buffers t{};
+    t.n = n;
+    t.M = M;
+    t.xw[0] = (double4*)take(sizeof(double4) * nn);
+    t.xw[1] = (double4*)take(sizeof(double4) * nn);
+    t.xbuild = (double4*)take(sizeof(double4) * nn);
+    t.nn = (int*)take(sizeof(int) * nn);
+    t.nl = (int*)take(sizeof(int) * nn * M);
+    t.rev = (int*)take(sizeof(int) * nn * M);
+    t.mask = (unsigned long long*)take(sizeof(unsigned long long) * nn);
+    t.dpart = take(sizeof(double) * 3 * nn * M);
+    t.cell_of = (int*)take(sizeof(int) * nn);
+    t.cell_count = (int*)take(sizeof(int) * ncap);
+    t.cell_start = (int*)take(sizeof(int) * (ncap + 1));
+    t.cell_fill = (int*)take(sizeof(int) * (ncap + 1 + nscan));
+    t.cell_atoms = (int*)take(sizeof(int) * nn);
+    t.part_b = (double*)take(sizeof(double) * kPartialCols * nblk);
+    t.ovf_count = (int*)take(sizeof(int));
+    t.ovf_list = (int*)take(sizeof(int) * nn);
+    t.status = (unsigned*)take(sizeof(unsigned));
+    t.thermo_scratch = (double*)take(sizeof(double) * kThermoCols);
+    if (b) *b = t;
+    return off;
+}
+
+mbmd_status fail(mbmd_ctx* c, mbmd_status s, const char* fmt, const char* what = "")
+{
+    char msg[512];
+    snprintf(msg, sizeof msg, fmt, what);
+    c->err = msg;
+    return s;
+}
+
+mbmd_status hip_fail(mbmd_ctx* c, hipError_t e, const char* where)
+{
+    char msg[512];
+    snprintf(msg, sizeof msg, "%s: %s", where, hipGetErrorString(e));
+    c->err = msg;
+    return MBMD_EDEVICE;
+}
+
+// Makes the workspace hold a layout for n atoms.
+mbmd_status ensure_workspace(mbmd_ctx* c, int64_t n)
+{
+    const int M = resolved_M(c);
+    const size_t need = layout(n, M, nullptr, nullptr);
+    if (c->ws && !c->ws_owned) {
+        if (c->ws_bytes < need)
+            return fail(c, MBMD_ENOMEM, "bound workspace too small for this call%s");
+    } else if (c->ws_bytes < need) {
+        if (c->ws) hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        hipError_t e = hipMalloc(&c->ws, need);
+        if (e != hipSuccess) {
+            c->ws = nullptr;
+            return fail(c, MBMD_ENOMEM, "hipMalloc of the workspace failed%s");
+        }
+        c->ws_bytes = need;
+        c->ws_owned = true;
+    }
+    if (c->laid_n != n || c->laid_M != M) {
+        layout(n, M, (char*)c->ws, &c->buf);
+        c->laid_n = n;
+        c->laid_M = M;
+    }
+    return MBMD_OK;
+}
+
+mbmd_status check_box(mbmd_ctx* c, const double* box, Box* out)
+{
+    if (!box) return fail(c, MBMD_EINVAL, "box is NULL%s");
+    const double rl = cutoff_of(c) + c->skin;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(box[a]) || !(box[a] >= 2.0 * rl))
+            return fail(c, MBMD_EBOX, "box edge shorter than 2 (cutoff + skin)%s");
+        out->L[a] = box[a];
+        out->inv[a] = 1.0 / box[a];
+    }
+    return MBMD_OK;
+}
+
+CellGrid make_grid(const Box& box, double rlist, int64_t n)
+{
+    CellGrid g{};
+    const int64_t cap = cell_cap(n > 0 ? n : 1);
+    for (int a = 0; a < 3; ++a) {
+        int k = (int)std::floor(box.L[a] / (rlist * (1.0 + 1e-9)));
+        g.nc[a] = k < 1 ? 1 : k;
+    }
+    while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cap) {
+        int a = 0;
+        if (g.nc[1] > g.nc[a]) a = 1;
+        if (g.nc[2] > g.nc[a]) a = 2;
+        g.nc[a] = g.nc[a] / 2 > 0 ? g.nc[a] / 2 : 1;
+    }
+    for (int a = 0; a < 3; ++a) g.inv_lc[a] = g.nc[a] / box.L[a];
+    g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+    return g;
+}
+
+mbmd_status status_to_code(mbmd_ctx* c, unsigned st)
+{
+    if (st & ST_TYPES) return fail(c, MBMD_EINVAL, "atom type other than 0%s");
+    if (st & ST_NONFINITE) return fail(c, MBMD_ENONFINITE, "non-finite position%s");
+    if (st & ST_NEIGH_OVERFLOW)
+        return fail(c, MBMD_ENEIGH, "neighbour list capacity exceeded; raise max_neighbors%s");
+    if (st & ST_ASYMMETRIC) return fail(c, MBMD_EDEVICE, "internal: asymmetric neighbour data%s");
+    if (st & ST_SKIN)
+        return fail(c, MBMD_ESKIN, "an atom moved more than skin/2 between list builds%s");
+    return MBMD_OK;
+}
+
+// Reads the status word after draining the stream.
+mbmd_status finish(mbmd_ctx* c)
+{
+    unsigned st = 0;
+    hipError_t e = hipMemcpyAsync(&st, c->buf.status, sizeof st, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+    return status_to_code(c, st);
+}
+
+// Stages positions, clears status and overflow counters, builds the list.
+mbmd_status begin(mbmd_ctx* c, int64_t n, const Box& box, const double* pos, const int32_t* types)
+{
+    mbmd_status s = ensure_workspace(c, n);
+    if (s != MBMD_OK) return s;
+    const Buffers& b = c->buf;
+    hipError_t e = launch_fill_int((int*)b.status, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(b.ovf_count, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_load_positions(pos, types, n, box, b.xw[0], b.status, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "staging positions");
+    return MBMD_OK;
+}
+
+hipError_t build(mbmd_ctx* c, int cur, const Box& box)
+{
+    const double rl = cutoff_of(c) + c->skin;
+    return launch_build_neighbors(c->buf, cur, box, make_grid(box, rl, c->buf.n), rl, c->stream);
+}
+
+template <class T>
+hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
+{
+    if (c->potential == 1) return launch_sw_partials<T>(c->buf, cur, box, c->sp, U, c->stream);
+    return launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, c->stream);
+}
+
+template <class T>
+mbmd_status compute_impl(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
+                         const double* vel, const int32_t* types, double* U, double* F,
+                         double* W, double* J)
+{
+    mbmd_status s = begin(c, n, box, pos, types);
+    if (s != MBMD_OK) return s;
+    hipError_t e = build(c, 0, box);
+    if (e == hipSuccess) e = partials<T>(c, 0, box, U);
+    StepArgs a{};
+    a.cur = 0;
+    if (e == hipSuccess)
+        e = launch_pair_gather<T>(c->buf, box, a, U, const_cast<double*>(vel), F, W, J, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "compute launch");
+    return finish(c);
+}
+
+template <class T>
+mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double* pos,
+                     double* vel, const int32_t* types, double dt, int n_steps, int rebuild_every,
+                     double* U, double* F, double* W, double* J, double* thermo)
+{
+    mbmd_status s = begin(c, n, box, pos, types);
+    if (s != MBMD_OK) return s;
+    const double kappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
+    StepArgs a{};
+    a.half_dt_acc = 0.5 * dt * kappa / mass;
+    a.dt = dt;
+    a.skin_half2 = 0.25 * c->skin * c->skin;
+    a.kin_scale = 0.5 * mass / kappa;
+    int cur = 0;
+    hipError_t e = build(c, cur, box);
+    for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
+        if (step > 0 && step % rebuild_every == 0) e = build(c, cur, box);
+        if (e == hipSuccess) e = partials<T>(c, cur, box, U);
+        a.cur = cur;
+        a.kick_before = step > 0;
+        a.advance = step < n_steps;
+        a.check_skin = a.advance && ((step + 1) % rebuild_every != 0);
+        if (e == hipSuccess) e = launch_pair_gather<T>(c->buf, box, a, U, vel, F, W, J, c->stream);
+        if (e == hipSuccess && thermo)
+            e = launch_thermo_reduce(c->buf, n, thermo + (size_t)step * kThermoCols, c->stream);
+        if (a.advance) cur ^= 1;
+    }
+    if (e == hipSuccess) e = launch_store_positions(c->buf.xw[cur], n, pos, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nve launch");
+    return finish(c);
+}
+
+mbmd_status common_checks(mbmd_ctx* c, int64_t n, const double* box, Box* b)
+{
+    if (c->potential < 0) return fail(c, MBMD_ENOPOT, "no potential set%s");
+    if (n < 0 || n > (int64_t)0x7fffffff) return fail(c, MBMD_EINVAL, "atom count out of range%s");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    return check_box(c, box, b);
+}
+
+}  // namespace
+
+extern "C" {
+
+mbmd_status mbmd_create(mbmd_ctx** out, int device, void* hip_stream)
+{
+    if (!out) return MBMD_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return MBMD_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return MBMD_EDEVICE;
+    mbmd_ctx* c = new (std::nothrow) mbmd_ctx();
+    if (!c) return MBMD_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return MBMD_OK;
+}
+
+void mbmd_destroy(mbmd_ctx* c)
+{
+    if (!c) return;
+    if (c->ws && c->ws_owned) {
+        hipSetDevice(c->device);
+        hipFree(c->ws);
+    }
+    delete c;
+}
+
+const char* mbmd_last_error(const mbmd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
+{
+    if (!c || !p) return MBMD_EINVAL;
+    const double v[] = {p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(c, MBMD_EINVAL, "non-finite Tersoff parameter%s");
+    if (!(p->R > 0.0) || !(p->S > p->R) || !(p->n > 0.0) || !(p->beta > 0.0) || p->d == 0.0)
+        return fail(c, MBMD_EINVAL, "Tersoff parameters need 0 < R < S, n > 0, beta > 0, d != 0%s");
+    c->tp = TersoffParams{p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
+    c->potential = 0;
+    c->laid_n = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_set_sw(mbmd_ctx* c, const mbmd_sw_params* p)
+{
+    if (!c || !p) return MBMD_EINVAL;
+    const double v[] = {p->epsilon, p->sigma, p->a, p->lambda, p->gamma, p->A, p->B, p->p, p->q};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(c, MBMD_EINVAL, "non-finite SW parameter%s");
+    if (!(p->sigma > 0.0) || !(p->a > 0.0))
+        return fail(c, MBMD_EINVAL, "SW parameters need sigma > 0 and a > 0%s");
+    c->sp = SWParams{p->epsilon, p->sigma, p->a, p->lambda, p->gamma, p->A, p->B, p->p, p->q};
+    c->potential = 1;
+    c->laid_n = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_set_neighbor(mbmd_ctx* c, double skin, int max_neighbors)
+{
+    if (!c) return MBMD_EINVAL;
+    if (!std::isfinite(skin) || skin < 0.0) return fail(c, MBMD_EINVAL, "skin must be >= 0%s");
+    if (max_neighbors < 0 || max_neighbors > kMaxSlots)
+        return fail(c, MBMD_EINVAL, "max_neighbors must be in 0..64%s");
+    c->skin = skin;
+    c->max_nb = max_neighbors;
+    c->laid_n = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_get_max_neighbors(const mbmd_ctx* c, int* out)
+{
+    if (!c || !out) return MBMD_EINVAL;
+    *out = resolved_M(c);
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_workspace_size(const mbmd_ctx* c, int64_t n_atoms, size_t* bytes)
+{
+    if (!c || !bytes || n_atoms < 0) return MBMD_EINVAL;
+    *bytes = layout(n_atoms, resolved_M(c), nullptr, nullptr);
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_bind_workspace(mbmd_ctx* c, void* dev_ptr, size_t bytes)
+{
+    if (!c) return MBMD_EINVAL;
+    if (dev_ptr && ((uintptr_t)dev_ptr % kAlign) != 0)
+        return fail(c, MBMD_EINVAL, "workspace must be 256-byte aligned%s");
+    if (c->ws && c->ws_owned) {
+        hipSetDevice(c->device);
+        hipFree(c->ws);
+    }
+    c->ws = dev_ptr;
+    c->ws_bytes = dev_ptr ? bytes : 0;
+    c->ws_owned = false;
+    c->laid_n = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_neighbors(mbmd_ctx* c, int64_t n, const double box[3], const double* pos,
+                           int32_t* nn, int32_t* nl)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (n == 0) return MBMD_OK;
+    if (!pos || !nn || !nl) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    s = begin(c, n, b, pos, nullptr);
+    if (s != MBMD_OK) return s;
+    hipError_t e = build(c, 0, b);
+    const int M = c->buf.M;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(nn, c->buf.nn, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(nl, c->buf.nl, sizeof(int32_t) * n * M, hipMemcpyDeviceToDevice,
+                           c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "neighbour build");
+    return finish(c);
+}
+
+mbmd_status mbmd_compute(mbmd_ctx* c, mbmd_precision prec, int64_t n, const double box[3],
+                         const double* pos, const double* vel, const int32_t* types, double* U,
+                         double* F, double* W, double* J)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
+    if (n == 0) return MBMD_OK;
+    if (!pos || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    if (prec == MBMD_MIXED) return compute_impl<float>(c, n, b, pos, vel, types, U, F, W, J);
+    return compute_impl<double>(c, n, b, pos, vel, types, U, F, W, J);
+}
+
+mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const double box[3],
+                         double mass_amu, double* pos, double* vel, const int32_t* types,
+                         double dt_fs, int n_steps, int rebuild_every, double* U, double* F,
+                         double* W, double* J, double* thermo)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
+    if (!std::isfinite(mass_amu) || !(mass_amu > 0.0) || !std::isfinite(dt_fs) || n_steps < 0 ||
+        rebuild_every < 1)
+        return fail(c, MBMD_EINVAL, "need mass > 0, finite dt, n_steps >= 0, rebuild_every >= 1%s");
+    if (n == 0) return MBMD_OK;
+    if (!pos || !vel || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    if (prec == MBMD_MIXED)
+        return nve_impl<float>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
+                               U, F, W, J, thermo);
+    return nve_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every, U,
+                            F, W, J, thermo);
+}
+
+}  // extern "C"

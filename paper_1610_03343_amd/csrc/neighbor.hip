@@ -1,0 +1,325 @@
+// Position staging and the cell-list neighbour build.
+//
+// The neighbour list of atom i holds every j != i whose minimum-image squared
+// distance is below r_list^2 = (cutoff + skin)^2 (the Verlet list over a cell
+// list that the paper uses because f_C vanishes beyond the cutoff; Section
+// 2.1).  Entries are sorted by ascending index, so the list - and every sum
+// that runs over it - does not depend on the order in which atoms were
+// binned, which is the only place integer atomics appear.
+//
+// The inclusion test d = x_j - x_i, d <- d - L rint(d / L),
+// r^2 = (dx*dx + dy*dy) + dz*dz < r_list^2 is evaluated in FP64 with no
+// contraction to fused multiply-add, so the list is reproducible bit for bit
+// by any IEEE evaluation of the same expression.
+#include "mbmd_internal.h"
+
+namespace mbmd {
+
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+#pragma clang fp contract(off)
+    double r = x - L * floor(x / L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    if (r < 0.0 || r >= L) r = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ double list_r2(const double4& a, const double4& b, const Box& box)
+{
+#pragma clang fp contract(off)
+    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+    dx = dx - box.L[0] * rint(dx / box.L[0]);
+    dy = dy - box.L[1] * rint(dy / box.L[1]);
+    dz = dz - box.L[2] * rint(dz / box.L[2]);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t count, int value)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = value;
+}
+
+hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t nb = (count + kBlock - 1) / kBlock;
+    int grid = (int)(nb < 65536 ? nb : 65536);
+    k_fill_int<<<grid, kBlock, 0, s>>>(p, count, value);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ types, int64_t n,
+                 Box box, double4* __restrict__ xw, unsigned* __restrict__ status)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        atomicOr(status, ST_NONFINITE);
+        x = y = z = 0.0;
+    }
+    if (types && types[i] != 0) atomicOr(status, ST_TYPES);
+    xw[i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
+                         wrap_coord(z, box.L[2]), 0.0);
+}
+
+hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
+                                 Box box, double4* xw, unsigned* status, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_load_positions<<<blocks_for(n), kBlock, 0, s>>>(pos_soa, types, n, box, xw, status);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_store_positions(const double4* __restrict__ xw, int64_t n, double* __restrict__ pos)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double4 p = xw[i];
+    pos[i] = p.x;
+    pos[n + i] = p.y;
+    pos[2 * n + i] = p.z;
+}
+
+hipError_t launch_store_positions(const double4* xw, int64_t n, double* pos_soa, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_store_positions<<<blocks_for(n), kBlock, 0, s>>>(xw, n, pos_soa);
+    return hipGetLastError();
+}
+
+// ---- cell binning ---------------------------------------------------------
+
+__device__ __forceinline__ int cell_coord(double x, double inv_lc, int nc)
+{
+    int c = (int)(x * inv_lc);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cell_count(const double4* __restrict__ xw, int64_t n, CellGrid g, int* __restrict__ cell_of,
+             int* __restrict__ count, double4* __restrict__ xbuild)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double4 p = xw[i];
+    const int cx = cell_coord(p.x, g.inv_lc[0], g.nc[0]);
+    const int cy = cell_coord(p.y, g.inv_lc[1], g.nc[1]);
+    const int cz = cell_coord(p.z, g.inv_lc[2], g.nc[2]);
+    const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    cell_of[i] = c;
+    atomicAdd(&count[c], 1);
+    xbuild[i] = p;
+}
+
+// Three-pass exclusive scan of the cell counts: per-block sums, a scan of the
+// block sums in one block, then the per-block scan with its offset.
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds_waves, int& total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) lds_waves[wave] = inc;
+    __syncthreads();
+    int wave_off = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int t = lds_waves[w];
+        if (w < wave) wave_off += t;
+        total += t;
+    }
+    __syncthreads();
+    return wave_off + inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_block_sums(const int* __restrict__ count, int ncell, int* __restrict__ bsum)
+{
+    __shared__ int lds[kBlock / 64];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < ncell) s += count[base + k];
+    int total;
+    block_exclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_bsums(int* __restrict__ bsum, int nblocks)
+{
+    __shared__ int lds[kBlock / 64];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const int v = i < nblocks ? bsum[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, lds, total);
+        if (i < nblocks) bsum[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ bsum,
+             int* __restrict__ start, int* __restrict__ fill)
+{
+    __shared__ int lds[kBlock / 64];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < ncell ? count[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = bsum[blockIdx.x] + block_exclusive_scan(s, lds, total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < ncell) {
+            start[base + k] = run;
+            fill[base + k] = 0;
+        }
+        run += v[k];
+    }
+    if (base + kScanItems >= ncell && base < ncell) start[ncell] = run;
+    if (ncell == 0 && blockIdx.x == 0 && threadIdx.x == 0) start[0] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cell_fill(const int* __restrict__ cell_of, int64_t n, const int* __restrict__ start,
+            int* __restrict__ fill, int* __restrict__ cell_atoms)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_of[i];
+    const int slot = atomicAdd(&fill[c], 1);
+    cell_atoms[start[c] + slot] = (int)i;
+}
+
+// ---- neighbour search -----------------------------------------------------
+
+constexpr int kSearchBlock = 128;
+
+// One thread per atom; its sorted list is kept in LDS (column-major over the
+// block so that neighbouring threads hit distinct banks), then written out
+// slot-major.
+__global__ void __launch_bounds__(kSearchBlock)
+k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double rl2, int M,
+         const int* __restrict__ cell_of, const int* __restrict__ start,
+         const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
+         unsigned* __restrict__ status)
+{
+    extern __shared__ int lbuf[];
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kSearchBlock + threadIdx.x;
+    if (i >= n) return;
+    int* buf = lbuf + threadIdx.x;
+    const double4 xi = xw[i];
+    const int c = cell_of[i];
+    const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.nc[a] >= 3 ? -1 : 0;
+        hi[a] = g.nc[a] >= 2 ? 1 : 0;
+    }
+    int cnt = 0;
+    for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+        const int zz = (cz + oz + g.nc[2]) % g.nc[2];
+        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+            const int yy = (cy + oy + g.nc[1]) % g.nc[1];
+            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                const int xx = (cx + ox + g.nc[0]) % g.nc[0];
+                const int cc = (zz * g.nc[1] + yy) * g.nc[0] + xx;
+                const int e = start[cc + 1];
+                for (int p = start[cc]; p < e; ++p) {
+                    const int j = cell_atoms[p];
+                    if (j == (int)i) continue;
+                    if (list_r2(xi, xw[j], box) < rl2) {
+                        // insertion into the sorted LDS list (capacity M)
+                        int q = cnt < M ? cnt : M;
+                        while (q > 0 && buf[(q - 1) * kSearchBlock] > j) {
+                            if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
+                            --q;
+                        }
+                        if (q < M) buf[q * kSearchBlock] = j;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    // On overflow the stored entries are not the M smallest indices; the
+    // status bit turns the call into an error.
+    if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
+    nn[i] = cnt;
+    const int w = cnt < M ? cnt : M;
+    for (int m = 0; m < w; ++m) nl[(int64_t)m * n + i] = buf[m * kSearchBlock];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reverse(const int* __restrict__ nn, const int* __restrict__ nl, int64_t n, int M,
+          int* __restrict__ rev, unsigned* __restrict__ status)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int cnt = min(nn[i], M);
+    for (int m = 0; m < cnt; ++m) {
+        const int j = nl[(int64_t)m * n + i];
+        const int cj = min(nn[j], M);
+        int s = -1;
+        for (int q = 0; q < cj; ++q)
+            if (nl[(int64_t)q * n + j] == (int)i) { s = q; break; }
+        if (s < 0) atomicOr(status, ST_ASYMMETRIC);
+        rev[(int64_t)m * n + i] = s < 0 ? 0 : s;
+    }
+}
+
+hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid grid,
+                                  double rlist, hipStream_t s)
+{
+    const int64_t n = b.n;
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill_int(b.cell_count, grid.ncell, 0, s);
+    if (e != hipSuccess) return e;
+    k_cell_count<<<blocks_for(n), kBlock, 0, s>>>(b.xw[cur], n, grid, b.cell_of, b.cell_count,
+                                                  b.xbuild);
+    const int nscan = (grid.ncell + kScanTile - 1) / kScanTile;
+    // The block sums live in the fill array's tail region (cells + 1 .. ), see
+    // workspace layout: cell_fill has room for ncell + nscan + 1 ints.
+    int* bsum = b.cell_fill + grid.ncell + 1;
+    k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, grid.ncell, bsum);
+    k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
+    k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, grid.ncell, bsum, b.cell_start,
+                                          b.cell_fill);
+    k_cell_fill<<<blocks_for(n), kBlock, 0, s>>>(b.cell_of, n, b.cell_start, b.cell_fill,
+                                                 b.cell_atoms);
+    const int sb = (int)((n + kSearchBlock - 1) / kSearchBlock);
+    const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
+    k_search<<<sb, kSearchBlock, lds, s>>>(b.xw[cur], n, box, grid, rlist * rlist, b.M,
+                                           b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl,
+                                           b.status);
+    k_reverse<<<blocks_for(n), kBlock, 0, s>>>(b.nn, b.nl, n, b.M, b.rev, b.status);
+    return hipGetLastError();
+}
+
+}  // namespace mbmd

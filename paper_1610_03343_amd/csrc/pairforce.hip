@@ -1,0 +1,232 @@
+// Pairwise-force pass with the fused velocity-Verlet update.
+//
+// One thread owns atom i and, over the in-cutoff neighbours j of its list,
+// forms the paper's explicit pairwise force (Sections 2.3 and 2.4)
+//   F_ij = dU_i/dr_ij - dU_j/dr_ji
+// from the partials the site-local pass stored for i and for j, and
+// accumulates in FP64 registers
+//   F_i = sum_j F_ij,   W_i = -1/2 sum_j r_ij (x) F_ij,
+//   M_i = sum_j r_ij (x) dU_j/dr_ji   so that   J_i = M_i v_i
+//       = sum_j r_ij (dU_j/dr_ji . v_i).
+// Every output of atom i is written once, by its own thread: no write
+// conflict and no atomics, the property the paper builds its GPU algorithm
+// on.  J_i is formed after the second half-kick, so it pairs r(t) with v(t).
+// Optionally the thread then performs the next step's first half-kick and
+// drift into the other position buffer (the neighbours' positions of the
+// current buffer are still being read by other threads).
+#include "mbmd_internal.h"
+
+namespace mbmd {
+
+__device__ __forceinline__ double wrap_coord_pf(double x, double L)
+{
+#pragma clang fp contract(off)
+    double r = x - L * floor(x / L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    if (r < 0.0 || r >= L) r = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__ xw,
+              double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
+              const int* __restrict__ nn, const int* __restrict__ nl,
+              const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
+              const T* __restrict__ dpart, const double* __restrict__ U,
+              double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
+              double* __restrict__ J, double* __restrict__ part_b, int* __restrict__ ovf_count,
+              unsigned* __restrict__ status)
+{
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;   // consumed by the partials pass
+
+    double f[3] = {0, 0, 0}, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, mm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double v[3] = {0, 0, 0}, jj[3] = {0, 0, 0}, ekin = 0.0, ui = 0.0;
+    if (i < n) {
+        const double4 xi = xw[i];
+        const unsigned long long msk = mask[i];
+        const int nnb = min(nn[i], M);
+        int ci = 0;
+        for (int m = 0; m < nnb; ++m) {
+            if (!((msk >> m) & 1ull)) continue;
+            const int j = nl[(int64_t)m * n + i];
+            const int rs = rev[(int64_t)m * n + i];
+            const unsigned long long mj = mask[j];
+            if (!((mj >> rs) & 1ull)) {
+                atomicOr(status, ST_ASYMMETRIC);
+                ++ci;
+                continue;
+            }
+            const int cj = __popcll(mj & ((1ull << rs) - 1ull));
+            const T* pij = dpart + ((int64_t)ci * n + i) * 3;
+            const T* pji = dpart + ((int64_t)cj * n + j) * 3;
+            ++ci;
+            const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
+            const double fij0 = (double)pij[0] - dji0;
+            const double fij1 = (double)pij[1] - dji1;
+            const double fij2 = (double)pij[2] - dji2;
+            const double4 xj = xw[j];
+            double r[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[c] -= box.L[c] * rint(r[c] * box.inv[c]);
+            f[0] += fij0;
+            f[1] += fij1;
+            f[2] += fij2;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                w[3 * c + 0] -= 0.5 * r[c] * fij0;
+                w[3 * c + 1] -= 0.5 * r[c] * fij1;
+                w[3 * c + 2] -= 0.5 * r[c] * fij2;
+                mm[3 * c + 0] += r[c] * dji0;
+                mm[3 * c + 1] += r[c] * dji1;
+                mm[3 * c + 2] += r[c] * dji2;
+            }
+        }
+        ui = U[i];
+        // The integrator arithmetic is kept unfused so that it rounds exactly
+        // like a plain IEEE evaluation of v += (dt/2) a and x += dt v.
+        if (vel) {
+#pragma clang fp contract(off)
+            v[0] = vel[i];
+            v[1] = vel[n + i];
+            v[2] = vel[2 * n + i];
+            if (a.kick_before) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] += a.half_dt_acc * f[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                jj[c] = mm[3 * c + 0] * v[0] + mm[3 * c + 1] * v[1] + mm[3 * c + 2] * v[2];
+            ekin = a.kin_scale * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        }
+        F[i] = f[0];
+        F[n + i] = f[1];
+        F[2 * n + i] = f[2];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) W[(int64_t)c * n + i] = w[c];
+        J[i] = jj[0];
+        J[n + i] = jj[1];
+        J[2 * n + i] = jj[2];
+        if (vel) {
+#pragma clang fp contract(off)
+            if (a.advance) {
+                double vn[3], x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    vn[c] = v[c] + a.half_dt_acc * f[c];
+                    x[c] = wrap_coord_pf(x[c] + a.dt * vn[c], box.L[c]);
+                }
+                vel[i] = vn[0];
+                vel[n + i] = vn[1];
+                vel[2 * n + i] = vn[2];
+                xw_next[i] = make_double4(x[0], x[1], x[2], 0.0);
+                if (a.check_skin) {
+                    const double4 xb = xbuild[i];
+                    double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
+                        d2 += d[c] * d[c];
+                    }
+                    if (d2 > a.skin_half2) atomicOr(status, ST_SKIN);
+                }
+            } else {
+                vel[i] = v[0];
+                vel[n + i] = v[1];
+                vel[2 * n + i] = v[2];
+            }
+        }
+    }
+    // deterministic per-block partial sums: U, E_kin, W (9), J (3)
+    if (part_b) {
+        double vals[kPartialCols];
+        vals[0] = ui;
+        vals[1] = ekin;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) vals[2 + c] = w[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vals[11 + c] = jj[c];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) {
+            const double s = wave_sum(vals[c]);
+            if (lane == 0) lds[wave][c] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < kPartialCols) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBlock / 64; ++k) s += lds[k][threadIdx.x];
+            part_b[(int64_t)lb * (kPartialCols) + threadIdx.x] = s;
+        }
+    }
+}
+
+template <class T>
+hipError_t launch_pair_gather(const Buffers& b, Box box, const StepArgs& a, const double* U,
+                              double* vel_soa, double* F, double* W, double* J, hipStream_t s)
+{
+    const int64_t n = b.n;
+    if (n <= 0) return hipSuccess;
+    k_pair_gather<T><<<blocks_for(n), kBlock, 0, s>>>(
+        box, n, b.M, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nn, b.nl, b.rev, b.mask,
+        static_cast<const T*>(b.dpart), U, vel_soa, F, W, J, b.part_b, b.ovf_count,
+        b.status);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pair_gather<double>(const Buffers&, Box, const StepArgs&,
+                                               const double*, double*, double*, double*, double*,
+                                               hipStream_t);
+template hipError_t launch_pair_gather<float>(const Buffers&, Box, const StepArgs&, const double*,
+                                              double*, double*, double*, double*, hipStream_t);
+
+// One block folds the per-block partials in a fixed order into a thermo row:
+// 0 E_pot, 1 E_kin, 2..10 W, 11..13 J, 14 E_pot + E_kin, 15 kinetic
+// temperature (k_B in eV/K, 3N - 3 degrees of freedom).
+__global__ void __launch_bounds__(kBlock)
+k_thermo_reduce(const double* __restrict__ part_b, int nblocks, int64_t n,
+                double* __restrict__ row)
+{
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < kPartialCols; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += part_b[(int64_t)b * (kPartialCols) + c];
+        s = wave_sum(s);
+        if (lane == 0) lds[wave][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[kPartialCols];
+        for (int c = 0; c < kPartialCols; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < kBlock / 64; ++k) s += lds[k][c];
+            t[c] = s;
+        }
+        for (int c = 0; c < 14; ++c) row[c] = t[c];
+        row[14] = t[0] + t[1];
+        row[15] = n > 1 ? 2.0 * t[1] / ((3.0 * (double)n - 3.0) * 8.617333262e-5) : 0.0;
+    }
+}
+
+hipError_t launch_thermo_reduce(const Buffers& b, int64_t n, double* row, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_thermo_reduce<<<1, kBlock, 0, s>>>(b.part_b, blocks_for(n), n, row);
+    return hipGetLastError();
+}
+
+}  // namespace mbmd

@@ -1,0 +1,245 @@
+// Tersoff site-local pass: bond order and per-atom partials.
+//
+// For atom i with in-cutoff neighbours c = 0..K-1 (unit vectors u_c, lengths
+// r_c), the Tersoff site energy (Section 2.1) is
+//   U_i = 1/2 sum_c f_C(r_c) [f_R(r_c) - b_c f_A(r_c)],
+//   b_c = (1 + (beta zeta_c)^n)^(-1/(2n)),  zeta_c = sum_{e != c} f_C(r_e) g(cos_ce),
+// with f_R = A exp(-lambda r), f_A = B exp(-mu r) and the 1989 cutoff f_C.
+// Every term depends on atom i's neighbours only, so one thread computes
+// all zeta_c and b_c (the bond-order pass of the paper's Section 2.3 two-kernel
+// approach) and, in the same registers, the partials
+//   dU_i/dr_c = 1/2 [f_C'(f_R - b f_A) + f_C (f_R' - b f_A')] u_c
+//             - 1/2 sum_{e != c} (P_c f_C(r_e) + P_e f_C(r_c)) g'(cos_ce) (u_e - cos_ce u_c) / r_c
+//             - 1/2 sum_{e != c} P_e f_C'(r_c) g(cos_ce) u_c,
+//   P_c = f_C(r_c) f_A(r_c) db_c/dzeta_c,
+// i.e. the derivative of U_i through r_c's own bond and through the bond
+// orders of all other bonds of atom i.  The partials are stored per compacted
+// in-cutoff neighbour for the pairwise-force pass.
+//
+// g is evaluated as 1 + c^2 t^2 / (d^2 (d^2 + t^2)), t = h - cos (identical to
+// the printed 1 + c^2/d^2 - c^2/(d^2 + t^2) without its large cancellation);
+// db/dzeta is 0 at zeta = 0, where it multiplies an empty sum.
+#include "partials_common.h"
+
+namespace mbmd {
+
+template <class T>
+struct TersoffK {
+    T A, B, lam, mu, beta, n, inv2n, c2, c2_d2, d2, h, R, pi_sr;
+};
+
+template <class T>
+TersoffK<T> tersoff_constants(const TersoffParams& p)
+{
+    TersoffK<T> k;
+    k.A = (T)p.A;
+    k.B = (T)p.B;
+    k.lam = (T)p.lam;
+    k.mu = (T)p.mu;
+    k.beta = (T)p.beta;
+    k.n = (T)p.n;
+    k.inv2n = (T)(1.0 / (2.0 * p.n));
+    k.c2 = (T)(p.c * p.c);
+    k.c2_d2 = (T)(p.c * p.c / (p.d * p.d));
+    k.d2 = (T)(p.d * p.d);
+    k.h = (T)p.h;
+    k.R = (T)p.R;
+    k.pi_sr = (T)(3.14159265358979323846 / (p.S - p.R));
+    return k;
+}
+
+__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+__device__ __forceinline__ float t_exp(float x) { return expf(x); }
+__device__ __forceinline__ double t_log(double x) { return log(x); }
+__device__ __forceinline__ float t_log(float x) { return logf(x); }
+__device__ __forceinline__ double t_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float t_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ void t_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
+
+// f_C and f_C' for r below S (the caller only passes in-cutoff bonds).
+template <class T>
+__device__ __forceinline__ void cutoff_fc(const TersoffK<T>& p, T r, T& fc, T& dfc)
+{
+    if (r < p.R) {
+        fc = T(1);
+        dfc = T(0);
+    } else {
+        T s, c;
+        t_sincos(p.pi_sr * (r - p.R), &s, &c);
+        fc = T(0.5) + T(0.5) * c;
+        dfc = T(-0.5) * p.pi_sr * s;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void angular_g(const TersoffK<T>& p, T cs, T& g, T& dg)
+{
+    const T t = p.h - cs;
+    const T iq = T(1) / (p.d2 + t * t);
+    g = T(1) + p.c2_d2 * t * t * iq;
+    dg = T(-2) * p.c2 * t * iq * iq;
+}
+
+template <class T>
+__device__ __forceinline__ T angular_g_only(const TersoffK<T>& p, T cs)
+{
+    const T t = p.h - cs;
+    return T(1) + p.c2_d2 * t * t / (p.d2 + t * t);
+}
+
+template <class T, int MAXC, bool FIXED>
+__device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, int64_t n,
+                                             const double4& xi, unsigned long long msk, int cnt,
+                                             const int* __restrict__ nl,
+                                             const double4* __restrict__ xw, const Box& box,
+                                             double* __restrict__ U, T* __restrict__ dpart)
+{
+    T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], fc[MAXC], dfc[MAXC], zp[MAXC], pd[MAXC];
+    unsigned long long rem = msk;
+#pragma unroll
+    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+        ux[c] = uy[c] = uz[c] = rr[c] = fc[c] = dfc[c] = zp[c] = pd[c] = T(0);
+        if (c < cnt) {
+            const int m = __builtin_ctzll(rem);
+            rem &= rem - 1;
+            const int j = nl[(int64_t)m * n + i];
+            const Disp d = cut_disp(xi, xw[j], box);
+            const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
+            const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
+            const T ir = T(1) / r;
+            ux[c] = dx * ir;
+            uy[c] = dy * ir;
+            uz[c] = dz * ir;
+            rr[c] = r;
+            cutoff_fc(p, r, fc[c], dfc[c]);
+        }
+    }
+    // zeta_c over unordered pairs: g(cos_ce) is shared by zeta_c and zeta_e.
+#pragma unroll
+    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+#pragma unroll
+        for (int e = c + 1; e < (FIXED ? MAXC : cnt); ++e) {
+            if (e < cnt) {
+                const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
+                const T g = angular_g_only(p, cs);
+                zp[c] += fc[e] * g;
+                zp[e] += fc[c] * g;
+            }
+        }
+    }
+    // bond orders, site energy (accumulated in FP64), pair-derivative factor
+    // pd_c and P_c
+    double u_i = 0.0;
+#pragma unroll
+    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+        if (c < cnt) {
+            const T zeta = zp[c];
+            T b = T(1), db = T(0);
+            if (zeta > T(0)) {
+                const T u = t_exp(p.n * t_log(p.beta * zeta));
+                b = t_exp(-t_log1p(u) * p.inv2n);
+                db = -b * u / (T(2) * zeta * (T(1) + u));
+            }
+            const T fr = p.A * t_exp(-p.lam * rr[c]);
+            const T fa = p.B * t_exp(-p.mu * rr[c]);
+            u_i += (double)(fc[c] * (fr - b * fa));
+            pd[c] = dfc[c] * (fr - b * fa) + fc[c] * (-p.lam * fr + b * p.mu * fa);
+            zp[c] = fc[c] * fa * db;
+        }
+    }
+    U[i] = 0.5 * u_i;
+    // partials dU_i/dr_c
+#pragma unroll
+    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+        if (c < cnt) {
+            const T ir = T(1) / rr[c];
+            T dx = T(0.5) * pd[c] * ux[c], dy = T(0.5) * pd[c] * uy[c], dz = T(0.5) * pd[c] * uz[c];
+#pragma unroll
+            for (int e = 0; e < (FIXED ? MAXC : cnt); ++e) {
+                if (e != c && e < cnt) {
+                    const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
+                    T g, dg;
+                    angular_g(p, cs, g, dg);
+                    const T a = T(-0.5) * (zp[c] * fc[e] + zp[e] * fc[c]) * dg * ir;
+                    const T bb = T(-0.5) * zp[e] * dfc[c] * g;
+                    dx += a * (ux[e] - cs * ux[c]) + bb * ux[c];
+                    dy += a * (uy[e] - cs * uy[c]) + bb * uy[c];
+                    dz += a * (uz[e] - cs * uz[c]) + bb * uz[c];
+                }
+            }
+            T* o = dpart + ((int64_t)c * n + i) * 3;
+            o[0] = dx;
+            o[1] = dy;
+            o[2] = dz;
+        }
+    }
+}
+
+template <class T, int MAXC>
+__global__ void __launch_bounds__(kBlock)
+k_tersoff_partials(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
+                   const double4* __restrict__ xw, const int* __restrict__ nn,
+                   const int* __restrict__ nl, unsigned long long* __restrict__ mask,
+                   double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
+                   int* __restrict__ ovf_list)
+{
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double4 xi = xw[i];
+    const int nnb = min(nn[i], M);
+    const unsigned long long msk = cutoff_mask(xi, i, n, nnb, nl, xw, box, rc2);
+    mask[i] = msk;
+    const int cnt = __popcll(msk);
+    if (cnt > MAXC) {
+        ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
+        return;
+    }
+    tersoff_site<T, MAXC, true>(p, i, n, xi, msk, cnt, nl, xw, box, U, dpart);
+}
+
+// Atoms whose in-cutoff count exceeded the main tile; the tile here covers
+// the whole list capacity.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_tersoff_partials_ovf(TersoffK<T> p, Box box, int64_t n, const double4* __restrict__ xw,
+                       const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
+                       double* __restrict__ U, T* __restrict__ dpart,
+                       const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
+{
+    const int total = *ovf_count;
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
+        const int64_t i = ovf_list[k];
+        const unsigned long long msk = mask[i];
+        tersoff_site<T, kMaxSlots, false>(p, i, n, xw[i], msk, __popcll(msk), nl, xw, box, U, dpart);
+    }
+}
+
+constexpr int kTersoffTile = 8;
+constexpr int kOvfGrid = 64;
+
+template <class T>
+hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
+                                   double* U, hipStream_t s)
+{
+    const int64_t n = b.n;
+    if (n <= 0) return hipSuccess;
+    const TersoffK<T> k = tersoff_constants<T>(p);
+    const double rc2 = p.S * p.S;
+    T* dp = static_cast<T*>(b.dpart);
+    k_tersoff_partials<T, kTersoffTile><<<blocks_for(n), kBlock, 0, s>>>(
+        k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
+    if (b.M > kTersoffTile)
+        k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
+                                              b.ovf_count, b.ovf_list);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tersoff_partials<double>(const Buffers&, int, Box, const TersoffParams&,
+                                                    double*, hipStream_t);
+template hipError_t launch_tersoff_partials<float>(const Buffers&, int, Box, const TersoffParams&,
+                                                   double*, hipStream_t);
+
+}  // namespace mbmd

@@ -1,0 +1,309 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64: every per-atom output within 1e-12 of the oracle in the norm-wise
+sense max|gpu - oracle| <= 1e-12 max|oracle| (per output array).  Neighbour
+lists: bit-exact as sorted index sets.  Mixed precision: forces within
+1e-4 eV/A.  Sizes span several 256-atom tiles with ragged tails; the full
+512,000-atom Tersoff and 1,000,000-atom SW workloads are compared at every
+atom.
+"""
+import numpy as np
+import pytest
+
+import workload as wl
+from gpu_util import (RLIST, TOL_FP64, TOL_MIXED_F, context, gpu_compute, min_image,
+                      oracle_compute, rel, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems():
+    return {
+        "c1_512": wl.tersoff_small(),
+        "crystal_64": wl.silicon_crystal(2, seed=11, sigma=0.1),
+        "ragged_480": wl.silicon_crystal((3, 4, 5), seed=31, sigma=0.08),
+        "taper_expanded": wl.silicon_crystal(2, seed=12, sigma=0.08, a=6.45),
+        "vacancies_hot": wl.silicon_crystal(4, seed=14, sigma=0.15, vacancy_fraction=0.05),
+        "cluster_18": wl.cluster(18, seed=13, min_dist=2.1, box_side=40.0),
+        "multi_tile_4096": wl.silicon_crystal(8, seed=33, sigma=0.1),
+    }
+
+
+SYSTEMS = _systems()
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_neighbor_lists_bitexact(pot, name):
+    import oracle
+    import torch
+    s = SYSTEMS[name]
+    with context(pot) as ctx:
+        M = ctx.max_neighbors
+        nn, nl = ctx.neighbors(to_dev(s.pos), s.box)
+        torch.cuda.synchronize()
+        nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
+    onn, onl = oracle.neighbors(s.pos, s.box, RLIST[pot], M, method="brute")
+    assert np.array_equal(nn, onn)
+    for i in range(s.n):
+        assert np.array_equal(nl[:nn[i], i], onl[i, :onn[i]]), i
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_compute_fp64_parity(pot, name):
+    s = SYSTEMS[name]
+    ref = oracle_compute(pot, s)
+    with context(pot) as ctx:
+        got = gpu_compute(ctx, s)
+    for k in ("U", "F", "W", "J"):
+        assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("pot,cells,a,M", [("tersoff", 2, 4.2, 32), ("sw", 3, 4.2, 64)])
+def test_compressed_lattice_overflow_path(pot, cells, a, M):
+    """A compressed lattice puts 16 (Tersoff) or 28 (SW) neighbours inside
+    the cutoff, beyond the 8-neighbour register tile: every atom takes the
+    overflow kernel."""
+    s = wl.silicon_crystal(cells, seed=41, sigma=0.05, a=a)
+    ref = oracle_compute(pot, s)
+    with context(pot, max_neighbors=M) as ctx:
+        got = gpu_compute(ctx, s)
+    for k in ("U", "F", "W", "J"):
+        assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("name", ["c1_512", "vacancies_hot", "taper_expanded", "cluster_18"])
+def test_mixed_precision_error(pot, name):
+    s = SYSTEMS[name]
+    ref = oracle_compute(pot, s)
+    with context(pot) as ctx:
+        got = gpu_compute(ctx, s, precision="mixed")
+    assert np.max(np.abs(got["F"] - ref["F"])) <= TOL_MIXED_F
+    assert np.max(np.abs(got["U"] - ref["U"])) <= 1e-5
+    assert rel(got["W"], ref["W"]) <= 1e-5
+    assert rel(got["J"], ref["J"]) <= 1e-4
+
+
+def test_without_velocities_heat_current_is_zero():
+    s = SYSTEMS["c1_512"]
+    ref = oracle_compute("tersoff", s, with_vel=False)
+    with context("tersoff") as ctx:
+        got = gpu_compute(ctx, s, with_vel=False)
+    assert np.all(got["J"] == 0.0)
+    assert rel(got["F"], ref["F"]) <= TOL_FP64
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_bitwise_reproducible(pot):
+    s = SYSTEMS["multi_tile_4096"]
+    with context(pot) as ctx:
+        a = gpu_compute(ctx, s)
+        b = gpu_compute(ctx, s)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def _full(pot):
+    return wl.tersoff_512k() if pot == "tersoff" else wl.sw_1m()
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_full_size_fp64_parity(pot):
+    """512,000-atom Tersoff and 1,000,000-atom SW crystals at 300 K: every
+    atom's U, F, W, J against the oracle."""
+    s = _full(pot)
+    ref = oracle_compute(pot, s, maxnb=32)
+    with context(pot) as ctx:
+        got = gpu_compute(ctx, s)
+    for k in ("U", "F", "W", "J"):
+        assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+
+
+def test_full_size_mixed_force_error():
+    s = _full("tersoff")
+    ref = oracle_compute("tersoff", s, maxnb=32)
+    with context("tersoff") as ctx:
+        got = gpu_compute(ctx, s, precision="mixed")
+    df = np.max(np.abs(got["F"] - ref["F"]))
+    du = np.max(np.abs(got["U"] - ref["U"]))
+    print(f"mixed 512k: max|dF| = {df:.3e} eV/A, max|dU_i| = {du:.3e} eV")
+    assert df <= TOL_MIXED_F
+
+
+# ---------------------------------------------------------------- dynamics
+
+def _chaos_tolerance(pot, s, n_steps, dt, rebuild):
+    """Ten times the oracle's own divergence when every coordinate and every
+    velocity component is moved by one ulp: trajectories of a chaotic system
+    cannot be expected to agree more closely than that."""
+    import oracle
+    from gpu_util import PARAMS
+    run = lambda p, v: oracle.nve(pot, PARAMS[pot], p, v, s.box, wl.M_SI, n_steps, dt,
+                                  RLIST[pot], rebuild, 64)
+    a = run(s.pos, s.vel)
+    rng = np.random.default_rng(99)
+    p2 = np.nextafter(s.pos, np.where(rng.uniform(size=s.pos.shape) < 0.5, -np.inf, np.inf))
+    v2 = np.nextafter(s.vel, np.where(rng.uniform(size=s.vel.shape) < 0.5, -np.inf, np.inf))
+    b = run(p2, v2)
+    tol = dict(
+        x=max(10 * np.max(np.abs(min_image(a["pos"] - b["pos"], s.box))), 1e-13),
+        v=max(10 * np.max(np.abs(a["vel"] - b["vel"])), 1e-15),
+        th=np.maximum(10 * np.max(np.abs(a["thermo"] - b["thermo"]), axis=0),
+                      1e-12 * np.max(np.abs(a["thermo"]), axis=0)),
+    )
+    return a, tol
+
+
+@pytest.mark.parametrize("pot,cells,steps", [("tersoff", 4, 100), ("sw", 3, 60)])
+def test_nve_trajectory_parity(pot, cells, steps):
+    import torch
+    s = wl.tersoff_small() if cells == 4 else wl.silicon_crystal(cells, seed=21)
+    ref, tol = _chaos_tolerance(pot, s, steps, 1.0, 20)
+    with context(pot) as ctx:
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        out = ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, steps, rebuild_every=20)
+        torch.cuda.synchronize()
+        gp, gv = pos.cpu().numpy().T, vel.cpu().numpy().T
+        th = out["thermo"].cpu().numpy()
+    print(f"trajectory tolerances: x {tol['x']:.2e} A, v {tol['v']:.2e} A/fs")
+    assert np.max(np.abs(min_image(gp - ref["pos"], s.box))) <= tol["x"]
+    assert np.max(np.abs(gv - ref["vel"])) <= tol["v"]
+    assert np.all(np.abs(th - ref["thermo"]) <= tol["th"][None, :])
+    # step 0 is a single point: FP64 parity
+    assert rel(th[0], ref["thermo"][0]) <= 1e-12
+    e = th[:, 14]
+    assert np.max(np.abs(e - e[0])) / s.n < 1e-4
+
+
+def test_nve_final_outputs_match_single_point():
+    """U, F, W, J returned by a run equal a single-point call at the final
+    phase-space point (J uses the full-step velocity)."""
+    import torch
+    s = wl.tersoff_small()
+    with context("tersoff") as ctx:
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        out = ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, 7, rebuild_every=3)
+        sp = ctx.compute(pos, s.box, vel=vel)
+        torch.cuda.synchronize()
+        for k in ("U", "F", "W", "J"):
+            assert torch.equal(out[k], sp[k]), k
+
+
+def test_nve_reproducible_and_reversible():
+    import torch
+    s = wl.tersoff_small()
+    with context("tersoff") as ctx:
+        runs = []
+        for _ in range(2):
+            pos, vel = to_dev(s.pos), to_dev(s.vel)
+            ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, 30, rebuild_every=10)
+            runs.append((pos.clone(), vel.clone()))
+        assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+        pos, vel = runs[0]
+        vel.neg_()
+        ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, 30, rebuild_every=10)
+        torch.cuda.synchronize()
+        d = min_image(pos.cpu().numpy().T - s.pos, s.box)
+        assert np.max(np.abs(d)) < 1e-9
+        assert np.max(np.abs(-vel.cpu().numpy().T - s.vel)) < 1e-11
+
+
+def test_full_size_nve_steps_against_oracle():
+    """The benchmark's configuration (512,000 atoms, rebuild every 20 steps,
+    0.5 A skin) for 3 steps: positions and forces against the oracle."""
+    import oracle
+    import torch
+    from gpu_util import PARAMS
+    s = wl.tersoff_512k()
+    ref = oracle.nve("tersoff", PARAMS["tersoff"], s.pos, s.vel, s.box, wl.M_SI, 3, 1.0,
+                     RLIST["tersoff"], 20, 16)
+    with context("tersoff") as ctx:
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        out = ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, 3, rebuild_every=20)
+        torch.cuda.synchronize()
+        gp = pos.cpu().numpy().T
+        gf = out["F"].cpu().numpy().T
+    assert np.max(np.abs(min_image(gp - ref["pos"], s.box))) < 1e-12
+    assert rel(gf, ref["F"]) < 1e-11
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_empty_and_single_atom():
+    import paper_1610_03343_amd as mb
+    import torch
+    with context("tersoff") as ctx:
+        box = np.array([20.0, 20.0, 20.0])
+        z = torch.zeros(3, 0, dtype=torch.float64, device="cuda:0")
+        out = ctx.compute(z, box)
+        assert out["U"].numel() == 0
+        one = torch.tensor([[1.0], [2.0], [3.0]], dtype=torch.float64, device="cuda:0")
+        v1 = torch.tensor([[1e-3], [0.0], [0.0]], dtype=torch.float64, device="cuda:0")
+        out = ctx.compute(one, box, vel=v1)
+        torch.cuda.synchronize()
+        for k in ("U", "F", "W", "J"):
+            assert torch.count_nonzero(out[k]).item() == 0
+        out = ctx.nve_run(one, v1, box, wl.M_SI, 1.0, 5)
+        torch.cuda.synchronize()
+        assert abs(one[0, 0].item() - 1.005) < 1e-15
+    assert mb.MBMD_OK == 0
+
+
+def test_error_paths():
+    import paper_1610_03343_amd as mb
+    import torch
+    s = SYSTEMS["crystal_64"]
+    with context("tersoff") as ctx:
+        pos = to_dev(s.pos)
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.compute(pos, np.array([6.0, 20.0, 20.0]))
+        assert e.value.code == mb.MBMD_EBOX
+        bad = pos.clone()
+        bad[1, 5] = float("nan")
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.compute(bad, s.box)
+        assert e.value.code == mb.MBMD_ENONFINITE
+        types = torch.zeros(s.n, dtype=torch.int32, device="cuda:0")
+        types[3] = 1
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.compute(pos, s.box, types=types)
+        assert e.value.code == mb.MBMD_EINVAL
+        ctx.set_neighbor(0.5, 2)
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.compute(pos, s.box)
+        assert e.value.code == mb.MBMD_ENEIGH
+        ctx.set_neighbor(0.5, 16)
+        # huge velocities with no rebuild: the skin check must fire
+        vel = torch.full((3, s.n), 0.05, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
+        assert e.value.code == mb.MBMD_ESKIN
+        # and the same run with a rebuild every step is fine
+        vel = torch.full((3, s.n), 0.05, dtype=torch.float64, device="cuda:0")
+        ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 4, rebuild_every=1)
+    with mb.Context(0) as bare:
+        with pytest.raises(mb.MbmdError) as e:
+            bare.compute(to_dev(s.pos), s.box)
+        assert e.value.code == mb.MBMD_ENOPOT
+
+
+def test_bound_workspace_and_unaligned_rejection():
+    import paper_1610_03343_amd as mb
+    import torch
+    s = SYSTEMS["c1_512"]
+    ref = oracle_compute("tersoff", s)
+    with context("tersoff") as ctx:
+        nbytes = ctx.workspace_size(s.n)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:0")
+        ctx.bind_workspace(ws[:nbytes])
+        got = gpu_compute(ctx, s)
+        for k in ("U", "F", "W", "J"):
+            assert rel(got[k], ref[k]) <= TOL_FP64
+        with pytest.raises(mb.MbmdError):
+            ctx.bind_workspace(ws[1:nbytes + 1])
+        ctx.bind_workspace(ws[:nbytes // 2])
+        with pytest.raises(mb.MbmdError) as e:
+            gpu_compute(ctx, s)
+        assert e.value.code == mb.MBMD_ENOMEM
