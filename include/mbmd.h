@@ -50,7 +50,7 @@ typedef enum {
     MBMD_EDEVICE = 3,     /* HIP runtime error or internal consistency failure */
     MBMD_EBOX = 4,        /* a box edge is shorter than 2 (cutoff + skin) or not finite */
     MBMD_ENEIGH = 5,      /* a neighbour list needed more than max_neighbors slots */
-    MBMD_ESKIN = 6,       /* an atom moved more than skin/2 between list builds */
+    MBMD_ESKIN = 6,       /* reserved (skin violations are handled by the rebuild policy) */
     MBMD_ENONFINITE = 7,  /* a non-finite position */
     MBMD_ENOPOT = 8       /* no potential set on the context */
 } mbmd_status;
@@ -80,6 +80,34 @@ typedef struct {
     double epsilon, sigma, a, lambda, gamma, A, B, p, q;
 } mbmd_sw_params;
 
+/* When nve_run rebuilds the neighbour list (the paper builds it once or on a
+ * fixed schedule; Section 3). */
+typedef enum {
+    MBMD_REBUILD_FIXED = 0,    /* every rebuild_every steps, nothing else; the
+                                  largest displacement between builds is only
+                                  reported in the run statistics */
+    MBMD_REBUILD_ON_SKIN = 1   /* also before any step whose positions moved
+                                  more than skin/2 from the last build
+                                  (default) */
+} mbmd_rebuild_policy;
+
+/* Statistics of the last mbmd_nve_run on a context. */
+typedef struct {
+    int64_t steps;             /* steps integrated */
+    int64_t rebuilds;          /* list builds, the initial one included */
+    int64_t rollbacks;         /* chunks replayed to insert an early rebuild */
+    double max_displacement;   /* largest distance (A) any atom moved from its
+                                  position at the build of the list it was
+                                  evaluated with */
+} mbmd_run_stats;
+
+/* Accumulated device time of one class of kernel launches (profiling). */
+typedef struct {
+    const char *name;          /* static string owned by the library */
+    int64_t launches;
+    double total_ms;
+} mbmd_kernel_time;
+
 typedef struct mbmd_ctx mbmd_ctx;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -106,6 +134,26 @@ mbmd_status mbmd_set_sw(mbmd_ctx *ctx, const mbmd_sw_params *p);
  * `max_neighbors` is the list capacity per atom, 1..64, or 0 for the default
  * (16 for Tersoff, 32 for Stillinger-Weber). */
 mbmd_status mbmd_set_neighbor(mbmd_ctx *ctx, double skin, int max_neighbors);
+
+/* Rebuild policy of mbmd_nve_run (default MBMD_REBUILD_ON_SKIN). */
+mbmd_status mbmd_set_rebuild_policy(mbmd_ctx *ctx, mbmd_rebuild_policy policy);
+
+/* Statistics of the last mbmd_nve_run on this context, copied to *out. */
+mbmd_status mbmd_get_run_stats(const mbmd_ctx *ctx, mbmd_run_stats *out);
+
+/* Profiling: with enable != 0 every later call records a pair of HIP events
+ * on the context's stream around each kernel launch class and accumulates
+ * the elapsed device time (adds a little launch overhead). */
+mbmd_status mbmd_set_profiling(mbmd_ctx *ctx, int enable);
+
+/* Zero the accumulated profile. */
+mbmd_status mbmd_reset_profile(mbmd_ctx *ctx);
+
+/* Copy up to `capacity` entries of the profile to out[] and store the number
+ * of kernel classes in *count (stage_positions, neighbor_build,
+ * site_partials, site_partials_overflow, pair_gather, thermo_reduce). */
+mbmd_status mbmd_get_profile(const mbmd_ctx *ctx, mbmd_kernel_time *out, int capacity,
+                             int *count);
 
 /* Current list capacity per atom (resolved default) in *out. */
 mbmd_status mbmd_get_max_neighbors(const mbmd_ctx *ctx, int *out);
@@ -141,14 +189,14 @@ mbmd_status mbmd_compute(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
 /* n_steps of NVE velocity-Verlet integration (the integrator of Section 3,
  * without thermostat or barostat) at time step dt_fs for atoms of mass
  * mass_amu.  pos[3][n] and vel[3][n] (device) are advanced in place.  The
- * forces are evaluated at the start and after every drift; the list is
- * rebuilt before the evaluation of every step s with s % rebuild_every == 0
- * (s = 0 included).  U, F, W, J receive the last step's values, J_i formed
- * with the full-step velocity.  thermo (device, or NULL) receives
- * [n_steps + 1][16] rows: 0 E_pot, 1 E_kin, 2..10 total W, 11..13 total J,
- * 14 E_pot + E_kin, 15 kinetic temperature with 3n - 3 degrees of freedom.
- * Returns MBMD_ESKIN if some atom moved more than skin/2 between builds
- * (the run then used a list that may have missed pairs). */
+ * forces are evaluated at the start (step 0) and after every drift; the list
+ * is built before step 0 and rebuilt before step s when s - (step of the last
+ * build) == rebuild_every, or, under MBMD_REBUILD_ON_SKIN, when the
+ * positions of step s moved more than skin/2 from those of the last build.
+ * U, F, W, J receive the last step's values, J_i formed with the full-step
+ * velocity.  thermo (device, or NULL) receives [n_steps + 1][16] rows:
+ * 0 E_pot, 1 E_kin, 2..10 total W, 11..13 total J, 14 E_pot + E_kin,
+ * 15 kinetic temperature with 3n - 3 degrees of freedom. */
 mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const double box[3],
                          double mass_amu, double *pos, double *vel, const int32_t *types,
                          double dt_fs, int n_steps, int rebuild_every, double *U, double *F,

@@ -50,8 +50,8 @@ def _load():
                            _dp, _dp, _dp, _dp, P, P, P, P]
             fn.restype = C.c_int
         lib.ora_nve.argtypes = [C.c_int, P, C.c_long, _dp, C.c_double, _dp, _dp, C.c_int,
-                                C.c_double, C.c_double, C.c_int, C.c_int,
-                                _dp, _dp, _dp, _dp, P]
+                                C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                _dp, _dp, _dp, _dp, P, C.POINTER(C.c_long)]
         lib.ora_wrap.argtypes = [C.c_long, _dp, _dp]
         lib.ora_wrap.restype = None
         for name in ("ora_tersoff_g", "ora_tersoff_g_literal", "ora_tersoff_b", "ora_tersoff_db"):
@@ -140,8 +140,12 @@ def sw(params, pos, box, nn, nl, vel=None, want_g=False):
 
 
 def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: float,
-        rlist: float, rebuild_every: int, maxnb: int):
-    """Velocity-Verlet NVE.  Returns dict(pos, vel, U, F, W, J, thermo[n_steps+1, 16])."""
+        rlist: float, rebuild_every: int, maxnb: int, skin: float = 0.5,
+        check_skin: bool = True):
+    """Velocity-Verlet NVE.  Returns dict(pos, vel, U, F, W, J,
+    thermo[n_steps+1, 16], builds).  The list is rebuilt every rebuild_every
+    steps and, with check_skin, before any step whose positions moved more
+    than skin/2 from the last build."""
     lib = _load()
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
@@ -155,12 +159,14 @@ def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: fl
         pr, pid = tersoff_params(params), 0
     else:
         pr, pid = sw_params(params), 1
+    builds = C.c_long(0)
     st = lib.ora_nve(pid, C.cast(C.byref(pr), C.c_void_p), n, _f64(box), float(mass), pos, vel,
-                     int(n_steps), float(dt), float(rlist), int(rebuild_every), int(maxnb),
-                     U, F, W, J, _ptr(thermo))
+                     int(n_steps), float(dt), float(rlist), float(skin), int(rebuild_every),
+                     int(bool(check_skin)), int(maxnb), U, F, W, J, _ptr(thermo),
+                     C.byref(builds))
     if st:
         raise OracleError(st)
-    return dict(pos=pos, vel=vel, U=U, F=F, W=W, J=J, thermo=thermo)
+    return dict(pos=pos, vel=vel, U=U, F=F, W=W, J=J, thermo=thermo, builds=builds.value)
 
 
 def tersoff_g(params, cs: float, literal: bool = False) -> float:

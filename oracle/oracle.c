@@ -602,16 +602,30 @@ static void thermo_row(long n, double mass, const double *U, const double *vel,
     row[15] = n > 1 ? 2.0 * ek / ((3.0 * n - 3.0) * ORA_KB) : 0.0;
 }
 
-/* Velocity-Verlet NVE.  pos/vel are advanced in place; the lists are rebuilt
- * (cell method) before the force evaluation of every step s with
- * s % rebuild_every == 0 (s = 0 is the evaluation at the start).  thermo is
- * [n_steps + 1][16]: 0 E_pot, 1 E_kin, 2..10 W (row-major), 11..13 J,
- * 14 E_pot + E_kin, 15 kinetic temperature (3N - 3 degrees of freedom).
- * U, F, W, J hold the final step's per-atom values. */
+/* Velocity-Verlet NVE.  pos/vel are advanced in place.  The list (cell
+ * method, radius rlist) is built before the evaluation of step 0 and rebuilt
+ * before step s when s - (step of the last build) == rebuild_every, or, with
+ * check_skin, when some atom of step s moved more than skin/2 from its
+ * position at the last build.  thermo is [n_steps + 1][16]: 0 E_pot,
+ * 1 E_kin, 2..10 W (row-major), 11..13 J, 14 E_pot + E_kin, 15 kinetic
+ * temperature (3N - 3 degrees of freedom).  U, F, W, J hold the final step's
+ * per-atom values; *n_builds (may be NULL) the number of list builds. */
+static double max_disp2(long n, const double *box, const double *pos, const double *ref)
+{
+    double worst = 0.0;
+    for (long i = 0; i < n; ++i) {
+        double d[3];
+        min_image(box, &ref[i * 3], &pos[i * 3], d);
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (d2 > worst) worst = d2;
+    }
+    return worst;
+}
+
 int ora_nve(int potential, const void *params, long n, const double *box, double mass,
-            double *pos, double *vel, int n_steps, double dt, double rlist,
-            int rebuild_every, int maxnb, double *U, double *F, double *W, double *J,
-            double *thermo)
+            double *pos, double *vel, int n_steps, double dt, double rlist, double skin,
+            int rebuild_every, int check_skin, int maxnb, double *U, double *F, double *W,
+            double *J, double *thermo, long *n_builds)
 {
     if (n < 1 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !(mass > 0.0))
         return ORA_EINVAL;
@@ -620,9 +634,14 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
     int *nn = (int *)malloc(sizeof(int) * (size_t)n);
     int *nl = (int *)malloc(sizeof(int) * (size_t)n * maxnb);
     double *G = (double *)malloc(sizeof(double) * (size_t)n * maxnb * 3);
-    if (!nn || !nl || !G) { free(nn); free(nl); free(G); return ORA_ENOMEM; }
+    double *xb = (double *)malloc(sizeof(double) * (size_t)n * 3);
+    if (!nn || !nl || !G || !xb) { free(nn); free(nl); free(G); free(xb); return ORA_ENOMEM; }
     ora_wrap(n, box, pos);
     st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
+    memcpy(xb, pos, sizeof(double) * (size_t)n * 3);
+    long builds = 1;
+    int last_build = 0;
+    double lim = 0.25 * skin * skin;
     if (!st) st = evaluate(potential, params, n, box, pos, vel, nn, nl, maxnb, U, F, W, J, G);
     if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[0]);
     double half = 0.5 * dt * ORA_KAPPA / mass;
@@ -633,9 +652,13 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
                 pos[i * 3 + a] += dt * vel[i * 3 + a];
             }
         ora_wrap(n, box, pos);
-        if (s % rebuild_every == 0) {
+        if (s - last_build == rebuild_every ||
+            (check_skin && max_disp2(n, box, pos, xb) > lim)) {
             st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
             if (st) break;
+            memcpy(xb, pos, sizeof(double) * (size_t)n * 3);
+            last_build = s;
+            ++builds;
         }
         /* Forces at the new positions.  J needs the full-step velocity, so it
          * is formed from the captured partials after the second half-kick. */
@@ -647,7 +670,9 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
         if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[(size_t)s * 16]);
     }
     free(G);
+    free(xb);
     free(nn);
     free(nl);
+    if (n_builds) *n_builds = builds;
     return st;
 }

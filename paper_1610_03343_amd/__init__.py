@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "MBMD_OK", 1: "MBMD_EINVAL", 2: "MBMD_ENOMEM", 3: "MBMD_EDEVI
                 4: "MBMD_EBOX", 5: "MBMD_ENEIGH", 6: "MBMD_ESKIN", 7: "MBMD_ENONFINITE",
                 8: "MBMD_ENOPOT"}
 THERMO_COLS = 16
+MBMD_REBUILD_FIXED, MBMD_REBUILD_ON_SKIN = 0, 1
 
 
 class MbmdError(RuntimeError):
@@ -45,6 +46,15 @@ class mbmd_sw_params(C.Structure):
                 ("epsilon", "sigma", "a", "lambda_", "gamma", "A", "B", "p", "q")]
 
 
+class mbmd_run_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("rollbacks", C.c_int64),
+                ("max_displacement", C.c_double)]
+
+
+class mbmd_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -59,6 +69,11 @@ def _load():
         "mbmd_set_sw": ([P, C.POINTER(mbmd_sw_params)], I),
         "mbmd_set_neighbor": ([P, D, I], I),
         "mbmd_get_max_neighbors": ([P, C.POINTER(I)], I),
+        "mbmd_set_rebuild_policy": ([P, I], I),
+        "mbmd_get_run_stats": ([P, C.POINTER(mbmd_run_stats)], I),
+        "mbmd_set_profiling": ([P, I], I),
+        "mbmd_reset_profile": ([P], I),
+        "mbmd_get_profile": ([P, C.POINTER(mbmd_kernel_time), I, C.POINTER(I)], I),
         "mbmd_workspace_size": ([P, I64, C.POINTER(C.c_size_t)], I),
         "mbmd_bind_workspace": ([P, P, C.c_size_t], I),
         "mbmd_neighbors": ([P, I64, P, P, P, P], I),
@@ -159,6 +174,32 @@ class Context:
     def set_neighbor(self, skin: float = 0.5, max_neighbors: int = 0):
         self._check(_lib.mbmd_set_neighbor(self._h, float(skin), int(max_neighbors)),
                     "mbmd_set_neighbor")
+
+    def set_rebuild_policy(self, policy):
+        """'fixed' (every rebuild_every steps only) or 'skin' (also when an
+        atom moved more than skin/2 since the last build)."""
+        code = {"fixed": MBMD_REBUILD_FIXED, "skin": MBMD_REBUILD_ON_SKIN}.get(policy, policy)
+        self._check(_lib.mbmd_set_rebuild_policy(self._h, int(code)), "mbmd_set_rebuild_policy")
+
+    def run_stats(self) -> dict:
+        st = mbmd_run_stats()
+        self._check(_lib.mbmd_get_run_stats(self._h, C.byref(st)), "mbmd_get_run_stats")
+        return dict(steps=st.steps, rebuilds=st.rebuilds, rollbacks=st.rollbacks,
+                    max_displacement=st.max_displacement)
+
+    def set_profiling(self, enable: bool = True):
+        self._check(_lib.mbmd_set_profiling(self._h, int(bool(enable))), "mbmd_set_profiling")
+
+    def reset_profile(self):
+        self._check(_lib.mbmd_reset_profile(self._h), "mbmd_reset_profile")
+
+    def profile(self) -> dict:
+        """{kernel class: (launches, total device ms)} from HIP events."""
+        arr = (mbmd_kernel_time * 16)()
+        cnt = C.c_int()
+        self._check(_lib.mbmd_get_profile(self._h, arr, 16, C.byref(cnt)), "mbmd_get_profile")
+        return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms)
+                for k in range(min(cnt.value, 16))}
 
     @property
     def max_neighbors(self) -> int:

@@ -5,11 +5,24 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/mbmd.h"
 #include "mbmd_internal.h"
 
 using namespace mbmd;
+
+namespace {
+// Kernel classes timed by the optional HIP-event profile.
+enum ProfKind { P_STAGE, P_BUILD, P_PARTIALS, P_PARTIALS_OVF, P_GATHER, P_THERMO, P_KINDS };
+const char* const kProfNames[P_KINDS] = {"stage_positions", "neighbor_build", "site_partials",
+                                         "site_partials_overflow", "pair_gather",
+                                         "thermo_reduce"};
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+}  // namespace
 
 struct mbmd_ctx {
     int device = 0;
@@ -19,6 +32,8 @@ struct mbmd_ctx {
     SWParams sp{};
     double skin = 0.5;
     int max_nb = 0;              // 0: potential default
+    int policy = MBMD_REBUILD_ON_SKIN;
+    mbmd_run_stats stats{};
     void* ws = nullptr;          // workspace base
     size_t ws_bytes = 0;
     bool ws_owned = false;
@@ -26,11 +41,53 @@ struct mbmd_ctx {
     int64_t laid_n = -1;         // layout currently held by buf
     int laid_M = 0;
     std::string err;
+    bool profiling = false;
+    std::vector<ProfRec> prof_pending;
+    double prof_ms[P_KINDS] = {};
+    int64_t prof_launches[P_KINDS] = {};
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Records a pair of HIP events on the context's stream around the launches
+// made while it is alive (only when profiling is on).
+struct ProfScope {
+    mbmd_ctx* c;
+    int kind;
+    hipEvent_t a = nullptr;
+    ProfScope(mbmd_ctx* ctx, int k) : c(ctx), kind(k)
+    {
+        if (c->profiling && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, c->stream);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) == hipSuccess) {
+            hipEventRecord(b, c->stream);
+            c->prof_pending.push_back(ProfRec{kind, a, b});
+        } else {
+            hipEventDestroy(a);
+        }
+    }
+};
+
+// Folds the completed event pairs into the per-kind totals (after a sync).
+void collect_profile(mbmd_ctx* c)
+{
+    for (const ProfRec& r : c->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            c->prof_ms[r.kind] += ms;
+            c->prof_launches[r.kind] += 1;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    c->prof_pending.clear();
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -82,6 +139,10 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
     t.ovf_list = (int*)take(sizeof(int) * nn);
     t.status = (unsigned*)take(sizeof(unsigned));
     t.thermo_scratch = (double*)take(sizeof(double) * kThermoCols);
+    t.xsnap = (double4*)take(sizeof(double4) * nn);
+    t.vsnap = (double*)take(sizeof(double) * 3 * nn);
+    t.step_disp2 = (unsigned long long*)take(sizeof(unsigned long long) * kMaxChunk);
+    t.maxdisp2 = (unsigned long long*)take(sizeof(unsigned long long));
     if (b) *b = t;
     return off;
 }
@@ -169,8 +230,6 @@ mbmd_status status_to_code(mbmd_ctx* c, unsigned st)
     if (st & ST_NEIGH_OVERFLOW)
         return fail(c, MBMD_ENEIGH, "neighbour list capacity exceeded; raise max_neighbors%s");
     if (st & ST_ASYMMETRIC) return fail(c, MBMD_EDEVICE, "internal: asymmetric neighbour data%s");
-    if (st & ST_SKIN)
-        return fail(c, MBMD_ESKIN, "an atom moved more than skin/2 between list builds%s");
     return MBMD_OK;
 }
 
@@ -181,6 +240,7 @@ mbmd_status finish(mbmd_ctx* c)
     hipError_t e = hipMemcpyAsync(&st, c->buf.status, sizeof st, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+    collect_profile(c);
     return status_to_code(c, st);
 }
 
@@ -192,13 +252,17 @@ mbmd_status begin(mbmd_ctx* c, int64_t n, const Box& box, const double* pos, con
     const Buffers& b = c->buf;
     hipError_t e = launch_fill_int((int*)b.status, 1, 0, c->stream);
     if (e == hipSuccess) e = launch_fill_int(b.ovf_count, 1, 0, c->stream);
-    if (e == hipSuccess) e = launch_load_positions(pos, types, n, box, b.xw[0], b.status, c->stream);
+    if (e == hipSuccess) {
+        ProfScope ps(c, P_STAGE);
+        e = launch_load_positions(pos, types, n, box, b.xw[0], b.status, c->stream);
+    }
     if (e != hipSuccess) return hip_fail(c, e, "staging positions");
     return MBMD_OK;
 }
 
 hipError_t build(mbmd_ctx* c, int cur, const Box& box)
 {
+    ProfScope ps(c, P_BUILD);
     const double rl = cutoff_of(c) + c->skin;
     return launch_build_neighbors(c->buf, cur, box, make_grid(box, rl, c->buf.n), rl, c->stream);
 }
@@ -206,8 +270,30 @@ hipError_t build(mbmd_ctx* c, int cur, const Box& box)
 template <class T>
 hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
 {
-    if (c->potential == 1) return launch_sw_partials<T>(c->buf, cur, box, c->sp, U, c->stream);
-    return launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, c->stream);
+    hipError_t e;
+    for (int pass = 0; pass < 2; ++pass) {
+        ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
+        if (c->potential == 1)
+            e = launch_sw_partials<T>(c->buf, cur, box, c->sp, U, pass == 1, c->stream);
+        else
+            e = launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, pass == 1, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class T>
+hipError_t gather(mbmd_ctx* c, const Box& box, const StepArgs& a, const double* U, double* vel,
+                  double* F, double* W, double* J)
+{
+    ProfScope ps(c, P_GATHER);
+    return launch_pair_gather<T>(c->buf, box, a, U, vel, F, W, J, c->stream);
+}
+
+hipError_t thermo_row(mbmd_ctx* c, double* row)
+{
+    ProfScope ps(c, P_THERMO);
+    return launch_thermo_reduce(c->buf, c->buf.n, row, c->stream);
 }
 
 template <class T>
@@ -221,42 +307,160 @@ mbmd_status compute_impl(mbmd_ctx* c, int64_t n, const Box& box, const double* p
     if (e == hipSuccess) e = partials<T>(c, 0, box, U);
     StepArgs a{};
     a.cur = 0;
-    if (e == hipSuccess)
-        e = launch_pair_gather<T>(c->buf, box, a, U, const_cast<double*>(vel), F, W, J, c->stream);
+    if (e == hipSuccess) e = gather<T>(c, box, a, U, const_cast<double*>(vel), F, W, J);
     if (e != hipSuccess) return hip_fail(c, e, "compute launch");
     return finish(c);
 }
 
+double disp_of(unsigned long long bits)
+{
+    double d2;
+    std::memcpy(&d2, &bits, sizeof d2);
+    return std::sqrt(d2);
+}
+
+// One MD step: force evaluation at the current positions, second half-kick,
+// heat current and thermo row, then (unless last) first half-kick and drift.
+template <class T>
+hipError_t md_step(mbmd_ctx* c, const Box& box, StepArgs& a, int step, int n_steps, int cur,
+                   bool check, unsigned long long* slot, double* U, double* vel, double* F,
+                   double* W, double* J, double* thermo)
+{
+    hipError_t e = partials<T>(c, cur, box, U);
+    a.cur = cur;
+    a.kick_before = step > 0;
+    a.advance = step < n_steps;
+    a.check_skin = a.advance && check;
+    a.disp_slot = slot;
+    if (e == hipSuccess) e = gather<T>(c, box, a, U, vel, F, W, J);
+    if (e == hipSuccess && thermo) e = thermo_row(c, thermo + (size_t)step * kThermoCols);
+    return e;
+}
+
 template <class T>
 mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double* pos,
-                     double* vel, const int32_t* types, double dt, int n_steps, int rebuild_every,
+                     double* vel, const int32_t* types, double dt, int n_steps, int every,
                      double* U, double* F, double* W, double* J, double* thermo)
 {
     mbmd_status s = begin(c, n, box, pos, types);
     if (s != MBMD_OK) return s;
+    const Buffers& b = c->buf;
     const double kappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
     StepArgs a{};
     a.half_dt_acc = 0.5 * dt * kappa / mass;
     a.dt = dt;
     a.skin_half2 = 0.25 * c->skin * c->skin;
     a.kin_scale = 0.5 * mass / kappa;
-    int cur = 0;
-    hipError_t e = build(c, cur, box);
-    for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
-        if (step > 0 && step % rebuild_every == 0) e = build(c, cur, box);
-        if (e == hipSuccess) e = partials<T>(c, cur, box, U);
-        a.cur = cur;
-        a.kick_before = step > 0;
-        a.advance = step < n_steps;
-        a.check_skin = a.advance && ((step + 1) % rebuild_every != 0);
-        if (e == hipSuccess) e = launch_pair_gather<T>(c->buf, box, a, U, vel, F, W, J, c->stream);
-        if (e == hipSuccess && thermo)
-            e = launch_thermo_reduce(c->buf, n, thermo + (size_t)step * kThermoCols, c->stream);
-        if (a.advance) cur ^= 1;
+    mbmd_run_stats st{};
+    st.steps = n_steps;
+    int cur = 0, last_build = 0;
+    hipError_t e = launch_fill_int((int*)b.maxdisp2, 2, 0, c->stream);
+    if (e == hipSuccess) e = build(c, cur, box);
+    st.rebuilds = 1;
+
+    if (c->policy == MBMD_REBUILD_FIXED) {
+        // The list is rebuilt every `every` steps whatever the atoms do; the
+        // largest displacement between builds is only measured.
+        for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
+            if (step - last_build == every) {
+                e = build(c, cur, box);
+                last_build = step;
+                ++st.rebuilds;
+            }
+            if (e != hipSuccess) break;
+            const bool check = (step + 1 - last_build) != every;
+            e = md_step<T>(c, box, a, step, n_steps, cur, check, b.maxdisp2, U, vel, F, W, J,
+                           thermo);
+            if (step < n_steps) cur ^= 1;
+        }
+        if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
+        unsigned long long bits = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bits, b.maxdisp2, sizeof bits, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "nve launch");
+        s = finish(c);
+        st.max_displacement = disp_of(bits);
+        c->stats = st;
+        return s;
     }
-    if (e == hipSuccess) e = launch_store_positions(c->buf.xw[cur], n, pos, c->stream);
+
+    // Rebuild on skin: chunks of steps are enqueued from a snapshot of the
+    // state; after each chunk the per-step largest displacement is read
+    // back.  If the positions of some step moved more than skin/2 from the
+    // last build, the chunk is replayed from the snapshot (bit-identically)
+    // up to that step and the list is rebuilt there.
+    int step = 0;
+    int chunk = every < kMaxChunk ? every : kMaxChunk;
+    std::vector<unsigned long long> disp(kMaxChunk);
+    double committed_max2 = 0.0;
+    while (step <= n_steps && e == hipSuccess) {
+        const int cs = step;
+        int cend = last_build + every;
+        if (cend > n_steps + 1) cend = n_steps + 1;
+        if (cend > cs + chunk) cend = cs + chunk;
+        const int len = cend - cs;
+        const int cur_snap = cur;
+        e = hipMemcpyAsync(b.xsnap, b.xw[cur], sizeof(double4) * n, hipMemcpyDeviceToDevice,
+                           c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b.vsnap, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice,
+                               c->stream);
+        if (e == hipSuccess) e = launch_fill_int((int*)b.step_disp2, 2 * len, 0, c->stream);
+        for (int k = 0; k < len && e == hipSuccess; ++k) {
+            const int sk = cs + k;
+            const bool check = (sk + 1 - last_build) != every;
+            e = md_step<T>(c, box, a, sk, n_steps, cur, check, b.step_disp2 + k, U, vel, F, W, J,
+                           thermo);
+            if (sk < n_steps) cur ^= 1;
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(disp.data(), b.step_disp2, sizeof(unsigned long long) * len,
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) break;
+        int bad = -1;   // first step whose positions violate the skin
+        for (int k = 0; k < len; ++k) {
+            double d2;
+            std::memcpy(&d2, &disp[k], sizeof d2);
+            if (d2 > a.skin_half2) {
+                bad = cs + k + 1;
+                break;
+            }
+            if (d2 > committed_max2) committed_max2 = d2;
+        }
+        if (bad < 0) {
+            step = cend;
+            if (step <= n_steps && step - last_build == every) {
+                e = build(c, cur, box);
+                last_build = step;
+                ++st.rebuilds;
+            }
+            continue;
+        }
+        // replay [cs, bad) from the snapshot, then rebuild at `bad`
+        cur = cur_snap;
+        e = hipMemcpyAsync(b.xw[cur], b.xsnap, sizeof(double4) * n, hipMemcpyDeviceToDevice,
+                           c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(vel, b.vsnap, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice,
+                               c->stream);
+        for (int sk = cs; sk < bad && e == hipSuccess; ++sk) {
+            e = md_step<T>(c, box, a, sk, n_steps, cur, false, nullptr, U, vel, F, W, J, thermo);
+            if (sk < n_steps) cur ^= 1;
+        }
+        if (e == hipSuccess) e = build(c, cur, box);
+        last_build = bad;
+        step = bad;
+        ++st.rebuilds;
+        ++st.rollbacks;
+        chunk = bad - cs > 0 ? bad - cs : 1;
+    }
+    if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nve launch");
-    return finish(c);
+    s = finish(c);
+    st.max_displacement = std::sqrt(committed_max2);
+    c->stats = st;
+    return s;
 }
 
 mbmd_status common_checks(mbmd_ctx* c, int64_t n, const double* box, Box* b)
@@ -291,6 +495,10 @@ mbmd_status mbmd_create(mbmd_ctx** out, int device, void* hip_stream)
 void mbmd_destroy(mbmd_ctx* c)
 {
     if (!c) return;
+    for (const ProfRec& r : c->prof_pending) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
     if (c->ws && c->ws_owned) {
         hipSetDevice(c->device);
         hipFree(c->ws);
@@ -337,6 +545,52 @@ mbmd_status mbmd_set_neighbor(mbmd_ctx* c, double skin, int max_neighbors)
     c->skin = skin;
     c->max_nb = max_neighbors;
     c->laid_n = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_set_rebuild_policy(mbmd_ctx* c, mbmd_rebuild_policy policy)
+{
+    if (!c) return MBMD_EINVAL;
+    if (policy != MBMD_REBUILD_FIXED && policy != MBMD_REBUILD_ON_SKIN)
+        return fail(c, MBMD_EINVAL, "unknown rebuild policy%s");
+    c->policy = policy;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_get_run_stats(const mbmd_ctx* c, mbmd_run_stats* out)
+{
+    if (!c || !out) return MBMD_EINVAL;
+    *out = c->stats;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_set_profiling(mbmd_ctx* c, int enable)
+{
+    if (!c) return MBMD_EINVAL;
+    c->profiling = enable != 0;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_reset_profile(mbmd_ctx* c)
+{
+    if (!c) return MBMD_EINVAL;
+    collect_profile(c);
+    for (int k = 0; k < P_KINDS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_launches[k] = 0;
+    }
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_get_profile(const mbmd_ctx* c, mbmd_kernel_time* out, int capacity, int* count)
+{
+    if (!c || !count || capacity < 0 || (capacity > 0 && !out)) return MBMD_EINVAL;
+    *count = P_KINDS;
+    for (int k = 0; k < P_KINDS && k < capacity; ++k) {
+        out[k].name = kProfNames[k];
+        out[k].launches = c->prof_launches[k];
+        out[k].total_ms = c->prof_ms[k];
+    }
     return MBMD_OK;
 }
 

@@ -20,7 +20,6 @@ namespace mbmd {
 // Device status bits (OR-ed by any thread; results never use atomics).
 enum : unsigned {
     ST_NEIGH_OVERFLOW = 1u << 0,   // a neighbour list needed more than M slots
-    ST_SKIN = 1u << 1,             // an atom moved more than skin/2 since the build
     ST_NONFINITE = 1u << 2,        // non-finite position
     ST_ASYMMETRIC = 1u << 3,       // list or cutoff mask not symmetric (internal)
     ST_TYPES = 1u << 4,            // an atom type other than 0
@@ -30,6 +29,7 @@ constexpr int kBlock = 256;          // threads per block of every per-atom kern
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
 constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
+constexpr int kMaxChunk = 1024;      // steps enqueued between two checks of the skin
 
 struct Box {
     double L[3];
@@ -71,6 +71,10 @@ struct Buffers {
     int* ovf_list;           // [N]
     unsigned* status;
     double* thermo_scratch;  // [kThermoCols]
+    double4* xsnap;          // [N] positions at the start of a checked chunk
+    double* vsnap;           // [3][N] velocities at the start of a checked chunk
+    unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
+    unsigned long long* maxdisp2;    // largest squared displacement over a run
 };
 
 // Mapping of a hardware block index to a logical block so that each XCD
@@ -93,18 +97,21 @@ hipError_t launch_store_positions(const double4* xw, int64_t n, double* pos_soa,
 hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid grid,
                                   double rlist, hipStream_t s);
 
+// overflow_pass = false launches the register-tile kernel over all atoms;
+// true launches the kernel for the atoms the first pass left over.
 template <class T>
 hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, hipStream_t s);
+                                   double* U, bool overflow_pass, hipStream_t s);
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p,
-                              double* U, hipStream_t s);
+                              double* U, bool overflow_pass, hipStream_t s);
 
 struct StepArgs {
     int cur;                 // position buffer read this step
     bool kick_before;        // v += dt/2 a before forming J (second half-kick)
     bool advance;            // then v += dt/2 a, x_next = wrap(x + dt v)
-    bool check_skin;         // flag atoms whose x_next moved > skin/2 since the build
+    bool check_skin;         // measure how far x_next moved since the list build
+    unsigned long long* disp_slot;  // receives (atomic max) the squared displacement, as bits
     double half_dt_acc;      // dt/2 * kappa / m
     double dt;
     double skin_half2;       // (skin/2)^2

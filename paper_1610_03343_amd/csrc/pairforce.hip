@@ -47,12 +47,13 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
               unsigned* __restrict__ status)
 {
     __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_max[kBlock / 64];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;   // consumed by the partials pass
 
     double f[3] = {0, 0, 0}, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, mm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double v[3] = {0, 0, 0}, jj[3] = {0, 0, 0}, ekin = 0.0, ui = 0.0;
+    double v[3] = {0, 0, 0}, jj[3] = {0, 0, 0}, ekin = 0.0, ui = 0.0, disp2 = 0.0;
     if (i < n) {
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
@@ -134,13 +135,11 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
                 if (a.check_skin) {
                     const double4 xb = xbuild[i];
                     double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
-                    double d2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
-                        d2 += d[c] * d[c];
+                        disp2 += d[c] * d[c];
                     }
-                    if (d2 > a.skin_half2) atomicOr(status, ST_SKIN);
                 }
             } else {
                 vel[i] = v[0];
@@ -170,6 +169,21 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
 #pragma unroll
             for (int k = 0; k < kBlock / 64; ++k) s += lds[k][threadIdx.x];
             part_b[(int64_t)lb * (kPartialCols) + threadIdx.x] = s;
+        }
+    }
+    // largest squared displacement since the list build: one atomic per block
+    if (a.check_skin) {
+        double m = disp2;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double bm = lds_max[0];
+#pragma unroll
+            for (int k = 1; k < kBlock / 64; ++k) bm = fmax(bm, lds_max[k]);
+            // non-negative doubles order like their bit patterns
+            atomicMax(a.disp_slot, (unsigned long long)__double_as_longlong(bm));
         }
     }
 }

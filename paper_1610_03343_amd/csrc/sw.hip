@@ -161,24 +161,27 @@ constexpr int kSWOvfGrid = 64;
 
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p, double* U,
-                              hipStream_t s)
+                              bool overflow_pass, hipStream_t s)
 {
     const int64_t n = b.n;
     if (n <= 0) return hipSuccess;
     const SWK<T> k = sw_constants<T>(p);
     const double rc = p.a * p.sigma;
     T* dp = static_cast<T*>(b.dpart);
-    k_sw_partials<T, kSWTile><<<blocks_for(n), kBlock, 0, s>>>(
+    if (!overflow_pass) {
+        k_sw_partials<T, kSWTile><<<blocks_for(n), kBlock, 0, s>>>(
         k, rc * rc, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
+        return hipGetLastError();
+    }
     if (b.M > kSWTile)
         k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
-template hipError_t launch_sw_partials<double>(const Buffers&, int, Box, const SWParams&, double*,
+template hipError_t launch_sw_partials<double>(const Buffers&, int, Box, const SWParams&, double*, bool,
                                                hipStream_t);
-template hipError_t launch_sw_partials<float>(const Buffers&, int, Box, const SWParams&, double*,
+template hipError_t launch_sw_partials<float>(const Buffers&, int, Box, const SWParams&, double*, bool,
                                               hipStream_t);
 
 }  // namespace mbmd

@@ -222,15 +222,18 @@ constexpr int kOvfGrid = 64;
 
 template <class T>
 hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, hipStream_t s)
+                                   double* U, bool overflow_pass, hipStream_t s)
 {
     const int64_t n = b.n;
     if (n <= 0) return hipSuccess;
     const TersoffK<T> k = tersoff_constants<T>(p);
     const double rc2 = p.S * p.S;
     T* dp = static_cast<T*>(b.dpart);
-    k_tersoff_partials<T, kTersoffTile><<<blocks_for(n), kBlock, 0, s>>>(
+    if (!overflow_pass) {
+        k_tersoff_partials<T, kTersoffTile><<<blocks_for(n), kBlock, 0, s>>>(
         k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
+        return hipGetLastError();
+    }
     if (b.M > kTersoffTile)
         k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
@@ -238,8 +241,8 @@ hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const Ter
 }
 
 template hipError_t launch_tersoff_partials<double>(const Buffers&, int, Box, const TersoffParams&,
-                                                    double*, hipStream_t);
+                                                    double*, bool, hipStream_t);
 template hipError_t launch_tersoff_partials<float>(const Buffers&, int, Box, const TersoffParams&,
-                                                   double*, hipStream_t);
+                                                   double*, bool, hipStream_t);
 
 }  // namespace mbmd

@@ -134,14 +134,14 @@ def test_full_size_mixed_force_error():
 
 # ---------------------------------------------------------------- dynamics
 
-def _chaos_tolerance(pot, s, n_steps, dt, rebuild):
+def _chaos_tolerance(pot, s, n_steps, dt, rebuild, check_skin=True):
     """Ten times the oracle's own divergence when every coordinate and every
     velocity component is moved by one ulp: trajectories of a chaotic system
     cannot be expected to agree more closely than that."""
     import oracle
     from gpu_util import PARAMS
     run = lambda p, v: oracle.nve(pot, PARAMS[pot], p, v, s.box, wl.M_SI, n_steps, dt,
-                                  RLIST[pot], rebuild, 64)
+                                  RLIST[pot], rebuild, 64, check_skin=check_skin)
     a = run(s.pos, s.vel)
     rng = np.random.default_rng(99)
     p2 = np.nextafter(s.pos, np.where(rng.uniform(size=s.pos.shape) < 0.5, -np.inf, np.inf))
@@ -156,17 +156,27 @@ def _chaos_tolerance(pot, s, n_steps, dt, rebuild):
     return a, tol
 
 
+@pytest.mark.parametrize("policy", ["skin", "fixed"])
 @pytest.mark.parametrize("pot,cells,steps", [("tersoff", 4, 100), ("sw", 3, 60)])
-def test_nve_trajectory_parity(pot, cells, steps):
+def test_nve_trajectory_parity(pot, cells, steps, policy):
+    """NVE trajectories against the oracle under both rebuild policies; the
+    skin policy must rebuild at the same steps as the oracle's."""
     import torch
     s = wl.tersoff_small() if cells == 4 else wl.silicon_crystal(cells, seed=21)
-    ref, tol = _chaos_tolerance(pot, s, steps, 1.0, 20)
+    ref, tol = _chaos_tolerance(pot, s, steps, 1.0, 20, check_skin=(policy == "skin"))
     with context(pot) as ctx:
+        ctx.set_rebuild_policy(policy)
         pos, vel = to_dev(s.pos), to_dev(s.vel)
         out = ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, steps, rebuild_every=20)
         torch.cuda.synchronize()
         gp, gv = pos.cpu().numpy().T, vel.cpu().numpy().T
         th = out["thermo"].cpu().numpy()
+        stats = ctx.run_stats()
+    print(f"{policy}: gpu builds {stats['rebuilds']} (rollbacks {stats['rollbacks']}), "
+          f"oracle builds {ref['builds']}, max displacement {stats['max_displacement']:.3f} A")
+    assert stats["rebuilds"] == ref["builds"]
+    if policy == "skin":
+        assert stats["max_displacement"] <= 0.25
     print(f"trajectory tolerances: x {tol['x']:.2e} A, v {tol['v']:.2e} A/fs")
     assert np.max(np.abs(min_image(gp - ref["pos"], s.box))) <= tol["x"]
     assert np.max(np.abs(gv - ref["vel"])) <= tol["v"]
@@ -218,8 +228,9 @@ def test_full_size_nve_steps_against_oracle():
     from gpu_util import PARAMS
     s = wl.tersoff_512k()
     ref = oracle.nve("tersoff", PARAMS["tersoff"], s.pos, s.vel, s.box, wl.M_SI, 3, 1.0,
-                     RLIST["tersoff"], 20, 16)
+                     RLIST["tersoff"], 20, 16, check_skin=False)
     with context("tersoff") as ctx:
+        ctx.set_rebuild_policy("fixed")
         pos, vel = to_dev(s.pos), to_dev(s.vel)
         out = ctx.nve_run(pos, vel, s.box, wl.M_SI, 1.0, 3, rebuild_every=20)
         torch.cuda.synchronize()
@@ -275,14 +286,18 @@ def test_error_paths():
             ctx.compute(pos, s.box)
         assert e.value.code == mb.MBMD_ENEIGH
         ctx.set_neighbor(0.5, 16)
-        # huge velocities with no rebuild: the skin check must fire
+        # a uniform drift of 0.087 A per step: the fixed schedule only reports
+        # the displacement, the skin policy rebuilds every third step
         vel = torch.full((3, s.n), 0.05, dtype=torch.float64, device="cuda:0")
-        with pytest.raises(mb.MbmdError) as e:
-            ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
-        assert e.value.code == mb.MBMD_ESKIN
-        # and the same run with a rebuild every step is fine
+        ctx.set_rebuild_policy("fixed")
+        ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
+        st = ctx.run_stats()
+        assert st["rebuilds"] == 1 and st["max_displacement"] > 0.8
         vel = torch.full((3, s.n), 0.05, dtype=torch.float64, device="cuda:0")
-        ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 4, rebuild_every=1)
+        ctx.set_rebuild_policy("skin")
+        ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
+        st = ctx.run_stats()
+        assert st["rebuilds"] == 4 and st["max_displacement"] <= 0.25
     with mb.Context(0) as bare:
         with pytest.raises(mb.MbmdError) as e:
             bare.compute(to_dev(s.pos), s.box)
