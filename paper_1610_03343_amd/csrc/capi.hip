@@ -16,8 +16,7 @@ namespace {
 // Kernel classes timed by the optional HIP-event profile.
 enum ProfKind { P_STAGE, P_BUILD, P_PARTIALS, P_PARTIALS_OVF, P_GATHER, P_THERMO, P_KINDS };
 const char* const kProfNames[P_KINDS] = {"stage_positions", "neighbor_build", "site_partials",
-                                         "site_partials_overflow", "pair_gather",
-                                         "thermo_reduce"};
+                                         "site_partials_overflow", "pair_gather", "thermo_fold"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
@@ -38,6 +37,9 @@ struct mbmd_ctx {
     size_t ws_bytes = 0;
     bool ws_owned = false;
     Buffers buf{};
+    int max_nn = kMaxSlots;      // largest list count of the last build
+    int fold_from = 0;           // first step whose thermo row is not folded yet
+    int fold_to = 0;             // one past the last step with pending partials
     int64_t laid_n = -1;         // layout currently held by buf
     int laid_M = 0;
     std::string err;
@@ -134,7 +136,7 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
     t.cell_start = (int*)take(sizeof(int) * (ncap + 1));
     t.cell_fill = (int*)take(sizeof(int) * (ncap + 1 + nscan));
     t.cell_atoms = (int*)take(sizeof(int) * nn);
-    t.part_b = (double*)take(sizeof(double) * kPartialCols * nblk);
+    t.part_b = (double*)take(sizeof(double) * kPartialCols * nblk * kThermoRing);
     t.ovf_count = (int*)take(sizeof(int));
     t.ovf_list = (int*)take(sizeof(int) * nn);
     t.status = (unsigned*)take(sizeof(unsigned));
@@ -143,6 +145,7 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
     t.vsnap = (double*)take(sizeof(double) * 3 * nn);
     t.step_disp2 = (unsigned long long*)take(sizeof(unsigned long long) * kMaxChunk);
     t.maxdisp2 = (unsigned long long*)take(sizeof(unsigned long long));
+    t.maxnn = (int*)take(sizeof(int));
     if (b) *b = t;
     return off;
 }
@@ -260,11 +263,22 @@ mbmd_status begin(mbmd_ctx* c, int64_t n, const Box& box, const double* pos, con
     return MBMD_OK;
 }
 
+// Builds the list and reads back its largest count (one stream sync per
+// build), which decides whether the partials overflow pass is needed.
 hipError_t build(mbmd_ctx* c, int cur, const Box& box)
 {
-    ProfScope ps(c, P_BUILD);
-    const double rl = cutoff_of(c) + c->skin;
-    return launch_build_neighbors(c->buf, cur, box, make_grid(box, rl, c->buf.n), rl, c->stream);
+    hipError_t e;
+    {
+        ProfScope ps(c, P_BUILD);
+        const double rl = cutoff_of(c) + c->skin;
+        e = launch_build_neighbors(c->buf, cur, box, make_grid(box, rl, c->buf.n), rl, c->stream);
+    }
+    int mx = kMaxSlots;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&mx, c->buf.maxnn, sizeof mx, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    c->max_nn = mx;
+    return e;
 }
 
 template <class T>
@@ -274,9 +288,10 @@ hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
     for (int pass = 0; pass < 2; ++pass) {
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)
-            e = launch_sw_partials<T>(c->buf, cur, box, c->sp, U, pass == 1, c->stream);
+            e = launch_sw_partials<T>(c->buf, cur, box, c->sp, U, pass == 1, c->max_nn, c->stream);
         else
-            e = launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, pass == 1, c->stream);
+            e = launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, pass == 1, c->max_nn,
+                                           c->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -290,11 +305,6 @@ hipError_t gather(mbmd_ctx* c, const Box& box, const StepArgs& a, const double* 
     return launch_pair_gather<T>(c->buf, box, a, U, vel, F, W, J, c->stream);
 }
 
-hipError_t thermo_row(mbmd_ctx* c, double* row)
-{
-    ProfScope ps(c, P_THERMO);
-    return launch_thermo_reduce(c->buf, c->buf.n, row, c->stream);
-}
 
 template <class T>
 mbmd_status compute_impl(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
@@ -319,6 +329,17 @@ double disp_of(unsigned long long bits)
     return std::sqrt(d2);
 }
 
+// Folds the pending per-step partials into thermo rows.
+hipError_t flush_thermo(mbmd_ctx* c, double* thermo)
+{
+    if (!thermo || c->fold_to <= c->fold_from) return hipSuccess;
+    ProfScope ps(c, P_THERMO);
+    hipError_t e = launch_thermo_fold(c->buf, c->fold_from, c->fold_to - c->fold_from, thermo,
+                                      c->stream);
+    c->fold_from = c->fold_to;
+    return e;
+}
+
 // One MD step: force evaluation at the current positions, second half-kick,
 // heat current and thermo row, then (unless last) first half-kick and drift.
 template <class T>
@@ -332,8 +353,15 @@ hipError_t md_step(mbmd_ctx* c, const Box& box, StepArgs& a, int step, int n_ste
     a.advance = step < n_steps;
     a.check_skin = a.advance && check;
     a.disp_slot = slot;
+    a.part_row = thermo ? c->buf.part_b + (size_t)(step % kThermoRing) * blocks_for(c->buf.n) *
+                                              kPartialCols
+                        : nullptr;
     if (e == hipSuccess) e = gather<T>(c, box, a, U, vel, F, W, J);
-    if (e == hipSuccess && thermo) e = thermo_row(c, thermo + (size_t)step * kThermoCols);
+    if (e == hipSuccess && thermo) {
+        if (step < c->fold_from || step > c->fold_to) c->fold_from = step;   // replayed steps
+        c->fold_to = step + 1;
+        if (c->fold_to - c->fold_from == kThermoRing) e = flush_thermo(c, thermo);
+    }
     return e;
 }
 
@@ -353,6 +381,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     a.kin_scale = 0.5 * mass / kappa;
     mbmd_run_stats st{};
     st.steps = n_steps;
+    c->fold_from = c->fold_to = 0;
     int cur = 0, last_build = 0;
     hipError_t e = launch_fill_int((int*)b.maxdisp2, 2, 0, c->stream);
     if (e == hipSuccess) e = build(c, cur, box);
@@ -373,6 +402,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
                            thermo);
             if (step < n_steps) cur ^= 1;
         }
+        if (e == hipSuccess) e = flush_thermo(c, thermo);
         if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
         unsigned long long bits = 0;
         if (e == hipSuccess)
@@ -413,6 +443,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
                            thermo);
             if (sk < n_steps) cur ^= 1;
         }
+        if (e == hipSuccess) e = flush_thermo(c, thermo);
         if (e == hipSuccess)
             e = hipMemcpyAsync(disp.data(), b.step_disp2, sizeof(unsigned long long) * len,
                                hipMemcpyDeviceToHost, c->stream);
@@ -455,6 +486,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         ++st.rollbacks;
         chunk = bad - cs > 0 ? bad - cs : 1;
     }
+    if (e == hipSuccess) e = flush_thermo(c, thermo);
     if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nve launch");
     s = finish(c);

@@ -8,7 +8,7 @@
 //                    coalesced), ascending index within each atom
 //   rev[M][N]        int32 slot of i inside the list of nl[m][i]
 //   mask[N]          uint64 bit m set iff slot m lies inside the potential cutoff
-//   dpart[M][N][3]   T: dU_i/dr_ij of the c-th in-cutoff neighbour (compacted)
+//   dpart[M][N][3]   T: dU_i/dr_ij for list slot m (written for in-cutoff slots only)
 //   outputs          FP64 SoA: U[N], F[3][N], W[9][N] (component 3a+b), J[3][N]
 #pragma once
 
@@ -29,7 +29,8 @@ constexpr int kBlock = 256;          // threads per block of every per-atom kern
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
 constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
-constexpr int kMaxChunk = 1024;      // steps enqueued between two checks of the skin
+constexpr int kMaxChunk = 256;       // steps enqueued between two checks of the skin
+constexpr int kThermoRing = 256;     // per-step rows of block partials kept before a fold
 
 struct Box {
     double L[3];
@@ -66,7 +67,7 @@ struct Buffers {
     int* cell_start;
     int* cell_fill;
     int* cell_atoms;
-    double* part_b;          // [nblocks][kPartialCols]
+    double* part_b;          // [kThermoRing][nblocks][kPartialCols]
     int* ovf_count;          // atoms whose in-cutoff count exceeds the register tile
     int* ovf_list;           // [N]
     unsigned* status;
@@ -75,6 +76,7 @@ struct Buffers {
     double* vsnap;           // [3][N] velocities at the start of a checked chunk
     unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
     unsigned long long* maxdisp2;    // largest squared displacement over a run
+    int* maxnn;                      // largest list count of the last build
 };
 
 // Mapping of a hardware block index to a logical block so that each XCD
@@ -94,17 +96,20 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
                                  Box box, double4* xw, unsigned* status, hipStream_t s);
 hipError_t launch_store_positions(const double4* xw, int64_t n, double* pos_soa, hipStream_t s);
+// Builds the sorted lists, their reverse slots and the largest count (maxnn).
 hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid grid,
                                   double rlist, hipStream_t s);
 
 // overflow_pass = false launches the register-tile kernel over all atoms;
 // true launches the kernel for the atoms the first pass left over.
+// max_nn bounds the in-cutoff count of every atom; the overflow pass is only
+// launched when it can exceed the register tile.
 template <class T>
 hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, bool overflow_pass, hipStream_t s);
+                                   double* U, bool overflow_pass, int max_nn, hipStream_t s);
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p,
-                              double* U, bool overflow_pass, hipStream_t s);
+                              double* U, bool overflow_pass, int max_nn, hipStream_t s);
 
 struct StepArgs {
     int cur;                 // position buffer read this step
@@ -112,6 +117,7 @@ struct StepArgs {
     bool advance;            // then v += dt/2 a, x_next = wrap(x + dt v)
     bool check_skin;         // measure how far x_next moved since the list build
     unsigned long long* disp_slot;  // receives (atomic max) the squared displacement, as bits
+    double* part_row;        // this step's row of block partials (null: no thermo)
     double half_dt_acc;      // dt/2 * kappa / m
     double dt;
     double skin_half2;       // (skin/2)^2
@@ -122,6 +128,9 @@ template <class T>
 hipError_t launch_pair_gather(const Buffers& b, Box box, const StepArgs& a, const double* U,
                               double* vel_soa, double* F, double* W, double* J, hipStream_t s);
 
-hipError_t launch_thermo_reduce(const Buffers& b, int64_t n, double* row, hipStream_t s);
+// Thermo rows of steps [first_step, first_step + count) from the partials ring.
+hipError_t launch_thermo_fold(const Buffers& b, int first_step, int count, double* thermo,
+                              hipStream_t s);
+
 
 }  // namespace mbmd

@@ -223,15 +223,34 @@ constexpr int kSearchBlock = 128;
 // One thread per atom; its sorted list is kept in LDS (column-major over the
 // block so that neighbouring threads hit distinct banks), then written out
 // slot-major.
+// A cheap test (multiply by 1/L, fused arithmetic allowed) settles every
+// candidate whose squared distance is not within a relative 1e-10 of r_list^2;
+// only those near the boundary take the exact unfused test above, whose
+// rounding error is many orders of magnitude below that margin.
+__device__ __forceinline__ bool in_list(const double4& a, const double4& b, const Box& box,
+                                        double rl2, double rl2_lo, double rl2_hi)
+{
+    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+    dx -= box.L[0] * rint(dx * box.inv[0]);
+    dy -= box.L[1] * rint(dy * box.inv[1]);
+    dz -= box.L[2] * rint(dz * box.inv[2]);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rl2_lo) return true;
+    if (r2 > rl2_hi) return false;
+    return list_r2(a, b, box) < rl2;
+}
+
 __global__ void __launch_bounds__(kSearchBlock)
-k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double rl2, int M,
-         const int* __restrict__ cell_of, const int* __restrict__ start,
-         const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
-         unsigned* __restrict__ status)
+k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double rl2,
+         double rl2_lo, double rl2_hi, int M, const int* __restrict__ cell_of,
+         const int* __restrict__ start, const int* __restrict__ cell_atoms, int* __restrict__ nn,
+         int* __restrict__ nl, int* __restrict__ maxnn, unsigned* __restrict__ status)
 {
     extern __shared__ int lbuf[];
+    __shared__ int lds_max[kSearchBlock / 64];
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kSearchBlock + threadIdx.x;
-    if (i >= n) return;
+    int cnt = 0;
+    if (i < n) {
     int* buf = lbuf + threadIdx.x;
     const double4 xi = xw[i];
     const int c = cell_of[i];
@@ -242,7 +261,6 @@ k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double 
         lo[a] = g.nc[a] >= 3 ? -1 : 0;
         hi[a] = g.nc[a] >= 2 ? 1 : 0;
     }
-    int cnt = 0;
     for (int oz = lo[2]; oz <= hi[2]; ++oz) {
         const int zz = (cz + oz + g.nc[2]) % g.nc[2];
         for (int oy = lo[1]; oy <= hi[1]; ++oy) {
@@ -254,7 +272,7 @@ k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double 
                 for (int p = start[cc]; p < e; ++p) {
                     const int j = cell_atoms[p];
                     if (j == (int)i) continue;
-                    if (list_r2(xi, xw[j], box) < rl2) {
+                    if (in_list(xi, xw[j], box, rl2, rl2_lo, rl2_hi)) {
                         // insertion into the sorted LDS list (capacity M)
                         int q = cnt < M ? cnt : M;
                         while (q > 0 && buf[(q - 1) * kSearchBlock] > j) {
@@ -274,6 +292,19 @@ k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double 
     nn[i] = cnt;
     const int w = cnt < M ? cnt : M;
     for (int m = 0; m < w; ++m) nl[(int64_t)m * n + i] = buf[m * kSearchBlock];
+    }
+    // largest count of the block, one atomic per block
+    int mx = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bm = lds_max[0];
+#pragma unroll
+        for (int k = 1; k < kSearchBlock / 64; ++k) bm = max(bm, lds_max[k]);
+        atomicMax(maxnn, bm);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -300,6 +331,7 @@ hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid g
     const int64_t n = b.n;
     if (n <= 0) return hipSuccess;
     hipError_t e = launch_fill_int(b.cell_count, grid.ncell, 0, s);
+    if (e == hipSuccess) e = launch_fill_int(b.maxnn, 1, 0, s);
     if (e != hipSuccess) return e;
     k_cell_count<<<blocks_for(n), kBlock, 0, s>>>(b.xw[cur], n, grid, b.cell_of, b.cell_count,
                                                   b.xbuild);
@@ -315,9 +347,10 @@ hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid g
                                                  b.cell_atoms);
     const int sb = (int)((n + kSearchBlock - 1) / kSearchBlock);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
-    k_search<<<sb, kSearchBlock, lds, s>>>(b.xw[cur], n, box, grid, rlist * rlist, b.M,
-                                           b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl,
-                                           b.status);
+    const double rl2 = rlist * rlist;
+    k_search<<<sb, kSearchBlock, lds, s>>>(b.xw[cur], n, box, grid, rl2, rl2 * (1.0 - 1e-10),
+                                           rl2 * (1.0 + 1e-10), b.M, b.cell_of, b.cell_start,
+                                           b.cell_atoms, b.nn, b.nl, b.maxnn, b.status);
     k_reverse<<<blocks_for(n), kBlock, 0, s>>>(b.nn, b.nl, n, b.M, b.rev, b.status);
     return hipGetLastError();
 }

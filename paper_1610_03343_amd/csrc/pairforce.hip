@@ -3,17 +3,26 @@
 // One thread owns atom i and, over the in-cutoff neighbours j of its list,
 // forms the paper's explicit pairwise force (Sections 2.3 and 2.4)
 //   F_ij = dU_i/dr_ij - dU_j/dr_ji
-// from the partials the site-local pass stored for i and for j, and
-// accumulates in FP64 registers
+// from the partials the site-local pass stored for i (at slot m of i's list)
+// and for j (at the slot of i in j's list), and accumulates in FP64 registers
 //   F_i = sum_j F_ij,   W_i = -1/2 sum_j r_ij (x) F_ij,
 //   M_i = sum_j r_ij (x) dU_j/dr_ji   so that   J_i = M_i v_i
 //       = sum_j r_ij (dU_j/dr_ji . v_i).
 // Every output of atom i is written once, by its own thread: no write
-// conflict and no atomics, the property the paper builds its GPU algorithm
-// on.  J_i is formed after the second half-kick, so it pairs r(t) with v(t).
-// Optionally the thread then performs the next step's first half-kick and
-// drift into the other position buffer (the neighbours' positions of the
-// current buffer are still being read by other threads).
+// conflict and no atomics on results, the property the paper builds its GPU
+// algorithm on.  J_i is formed after the second half-kick, so it pairs r(t)
+// with v(t).  Optionally the thread then performs the next step's first
+// half-kick and drift into the other position buffer (the neighbours'
+// positions in the current buffer are still being read by other threads).
+//
+// Slot m of atom i is inside the cutoff iff slot rev of atom j is: both
+// masks come from the same unfused evaluation of r^2, and
+// (x_i - x_j)^2 equals (x_j - x_i)^2 bit for bit.
+//
+// Per-step totals (U, E_kin, W, J) are reduced per block in a fixed tree into
+// a ring of per-step rows; a separate fold kernel sums each row in block
+// order (a grid-wide fence inside this kernel would have to write back the
+// L2 of every XCD).
 #include "mbmd_internal.h"
 
 namespace mbmd {
@@ -35,6 +44,27 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Fixed-order block sum of kPartialCols values per thread into lds_out.
+__device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
+                                               double (*lds)[kPartialCols],
+                                               double* lds_out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kPartialCols; ++c) {
+        const double s = wave_sum(vals[c]);
+        if (lane == 0) lds[wave][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPartialCols) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; ++k) s += lds[k][threadIdx.x];
+        lds_out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__ xw,
@@ -43,10 +73,10 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
               const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
               const T* __restrict__ dpart, const double* __restrict__ U,
               double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
-              double* __restrict__ J, double* __restrict__ part_b, int* __restrict__ ovf_count,
-              unsigned* __restrict__ status)
+              double* __restrict__ J, int* __restrict__ ovf_count)
 {
     __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
     __shared__ double lds_max[kBlock / 64];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
@@ -58,21 +88,12 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
         const int nnb = min(nn[i], M);
-        int ci = 0;
         for (int m = 0; m < nnb; ++m) {
             if (!((msk >> m) & 1ull)) continue;
             const int j = nl[(int64_t)m * n + i];
             const int rs = rev[(int64_t)m * n + i];
-            const unsigned long long mj = mask[j];
-            if (!((mj >> rs) & 1ull)) {
-                atomicOr(status, ST_ASYMMETRIC);
-                ++ci;
-                continue;
-            }
-            const int cj = __popcll(mj & ((1ull << rs) - 1ull));
-            const T* pij = dpart + ((int64_t)ci * n + i) * 3;
-            const T* pji = dpart + ((int64_t)cj * n + j) * 3;
-            ++ci;
+            const T* pij = dpart + ((int64_t)m * n + i) * 3;
+            const T* pji = dpart + ((int64_t)rs * n + j) * 3;
             const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
             const double fij0 = (double)pij[0] - dji0;
             const double fij1 = (double)pij[1] - dji1;
@@ -148,29 +169,7 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
             }
         }
     }
-    // deterministic per-block partial sums: U, E_kin, W (9), J (3)
-    if (part_b) {
-        double vals[kPartialCols];
-        vals[0] = ui;
-        vals[1] = ekin;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) vals[2 + c] = w[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) vals[11 + c] = jj[c];
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int c = 0; c < kPartialCols; ++c) {
-            const double s = wave_sum(vals[c]);
-            if (lane == 0) lds[wave][c] = s;
-        }
-        __syncthreads();
-        if (threadIdx.x < kPartialCols) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < kBlock / 64; ++k) s += lds[k][threadIdx.x];
-            part_b[(int64_t)lb * (kPartialCols) + threadIdx.x] = s;
-        }
-    }
+
     // largest squared displacement since the list build: one atomic per block
     if (a.check_skin) {
         double m = disp2;
@@ -186,6 +185,57 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
             atomicMax(a.disp_slot, (unsigned long long)__double_as_longlong(bm));
         }
     }
+
+    if (!a.part_row) return;
+    // per-block partial sums (U, E_kin, W (9), J (3)) into this step's row of
+    // the partials ring; the fold kernel sums the rows in block order
+    double vals[kPartialCols];
+    vals[0] = ui;
+    vals[1] = ekin;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) vals[2 + c] = w[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vals[11 + c] = jj[c];
+    block_sum_cols(vals, lds, lds_tot);
+    if (threadIdx.x < kPartialCols) a.part_row[(int64_t)lb * kPartialCols + threadIdx.x] = lds_tot[threadIdx.x];
+}
+
+// One block per step: folds that step's per-block partials, in block order,
+// into its thermo row: 0 E_pot, 1 E_kin, 2..10 W, 11..13 J, 14 E_pot + E_kin,
+// 15 kinetic temperature (k_B in eV/K, 3N - 3 degrees of freedom).
+__global__ void __launch_bounds__(kBlock)
+k_thermo_fold(const double* __restrict__ part_b, int nblocks, int ring, int first_step,
+              int64_t n, double* __restrict__ thermo)
+{
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    const int step = first_step + blockIdx.x;
+    const double* rowp = part_b + (int64_t)(step % ring) * nblocks * kPartialCols;
+    double vals[kPartialCols];
+#pragma unroll
+    for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        const double* p = rowp + (int64_t)b * kPartialCols;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
+    }
+    block_sum_cols(vals, lds, lds_tot);
+    if (threadIdx.x == 0) {
+        double* row = thermo + (int64_t)step * kThermoCols;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) row[c] = lds_tot[c];
+        row[14] = lds_tot[0] + lds_tot[1];
+        row[15] = n > 1 ? 2.0 * lds_tot[1] / ((3.0 * (double)n - 3.0) * 8.617333262e-5) : 0.0;
+    }
+}
+
+hipError_t launch_thermo_fold(const Buffers& b, int first_step, int count, double* thermo,
+                              hipStream_t s)
+{
+    if (b.n <= 0 || count <= 0) return hipSuccess;
+    k_thermo_fold<<<count, kBlock, 0, s>>>(b.part_b, blocks_for(b.n), kThermoRing, first_step,
+                                            b.n, thermo);
+    return hipGetLastError();
 }
 
 template <class T>
@@ -196,8 +246,7 @@ hipError_t launch_pair_gather(const Buffers& b, Box box, const StepArgs& a, cons
     if (n <= 0) return hipSuccess;
     k_pair_gather<T><<<blocks_for(n), kBlock, 0, s>>>(
         box, n, b.M, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nn, b.nl, b.rev, b.mask,
-        static_cast<const T*>(b.dpart), U, vel_soa, F, W, J, b.part_b, b.ovf_count,
-        b.status);
+        static_cast<const T*>(b.dpart), U, vel_soa, F, W, J, b.ovf_count);
     return hipGetLastError();
 }
 
@@ -206,41 +255,5 @@ template hipError_t launch_pair_gather<double>(const Buffers&, Box, const StepAr
                                                hipStream_t);
 template hipError_t launch_pair_gather<float>(const Buffers&, Box, const StepArgs&, const double*,
                                               double*, double*, double*, double*, hipStream_t);
-
-// One block folds the per-block partials in a fixed order into a thermo row:
-// 0 E_pot, 1 E_kin, 2..10 W, 11..13 J, 14 E_pot + E_kin, 15 kinetic
-// temperature (k_B in eV/K, 3N - 3 degrees of freedom).
-__global__ void __launch_bounds__(kBlock)
-k_thermo_reduce(const double* __restrict__ part_b, int nblocks, int64_t n,
-                double* __restrict__ row)
-{
-    __shared__ double lds[kBlock / 64][kPartialCols];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c < kPartialCols; ++c) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += part_b[(int64_t)b * (kPartialCols) + c];
-        s = wave_sum(s);
-        if (lane == 0) lds[wave][c] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t[kPartialCols];
-        for (int c = 0; c < kPartialCols; ++c) {
-            double s = 0.0;
-            for (int k = 0; k < kBlock / 64; ++k) s += lds[k][c];
-            t[c] = s;
-        }
-        for (int c = 0; c < 14; ++c) row[c] = t[c];
-        row[14] = t[0] + t[1];
-        row[15] = n > 1 ? 2.0 * t[1] / ((3.0 * (double)n - 3.0) * 8.617333262e-5) : 0.0;
-    }
-}
-
-hipError_t launch_thermo_reduce(const Buffers& b, int64_t n, double* row, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    k_thermo_reduce<<<1, kBlock, 0, s>>>(b.part_b, blocks_for(n), n, row);
-    return hipGetLastError();
-}
 
 }  // namespace mbmd

@@ -50,13 +50,16 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, c
                                         double* __restrict__ U, T* __restrict__ dpart)
 {
     T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], ex[MAXC], qg[MAXC], dph[MAXC];
+    int slot[MAXC];
     unsigned long long rem = msk;
     double u_i = 0.0;
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         ux[c] = uy[c] = uz[c] = rr[c] = ex[c] = qg[c] = dph[c] = T(0);
+        slot[c] = 0;
         if (c < cnt) {
             const int m = __builtin_ctzll(rem);
+            slot[c] = m;
             rem &= rem - 1;
             const int j = nl[(int64_t)m * n + i];
             const Disp d = cut_disp(xi, xw[j], box);
@@ -112,7 +115,7 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, c
                     dz += radial * uz[c] + angular * (uz[e] - cs * uz[c]);
                 }
             }
-            T* o = dpart + ((int64_t)c * n + i) * 3;
+            T* o = dpart + ((int64_t)slot[c] * n + i) * 3;
             o[0] = dx;
             o[1] = dy;
             o[2] = dz;
@@ -161,7 +164,7 @@ constexpr int kSWOvfGrid = 64;
 
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p, double* U,
-                              bool overflow_pass, hipStream_t s)
+                              bool overflow_pass, int max_nn, hipStream_t s)
 {
     const int64_t n = b.n;
     if (n <= 0) return hipSuccess;
@@ -173,15 +176,15 @@ hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams
         k, rc * rc, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kSWTile)
+    if (b.M > kSWTile && max_nn > kSWTile)
         k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
-template hipError_t launch_sw_partials<double>(const Buffers&, int, Box, const SWParams&, double*, bool,
+template hipError_t launch_sw_partials<double>(const Buffers&, int, Box, const SWParams&, double*, bool, int,
                                                hipStream_t);
-template hipError_t launch_sw_partials<float>(const Buffers&, int, Box, const SWParams&, double*, bool,
+template hipError_t launch_sw_partials<float>(const Buffers&, int, Box, const SWParams&, double*, bool, int,
                                               hipStream_t);
 
 }  // namespace mbmd

@@ -13,8 +13,8 @@
 //             - 1/2 sum_{e != c} P_e f_C'(r_c) g(cos_ce) u_c,
 //   P_c = f_C(r_c) f_A(r_c) db_c/dzeta_c,
 // i.e. the derivative of U_i through r_c's own bond and through the bond
-// orders of all other bonds of atom i.  The partials are stored per compacted
-// in-cutoff neighbour for the pairwise-force pass.
+// orders of all other bonds of atom i.  The partials are stored at the list
+// slot of the neighbour for the pairwise-force pass.
 //
 // g is evaluated as 1 + c^2 t^2 / (d^2 (d^2 + t^2)), t = h - cos (identical to
 // the printed 1 + c^2/d^2 - c^2/(d^2 + t^2) without its large cancellation);
@@ -98,12 +98,15 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
                                              double* __restrict__ U, T* __restrict__ dpart)
 {
     T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], fc[MAXC], dfc[MAXC], zp[MAXC], pd[MAXC];
+    int slot[MAXC];
     unsigned long long rem = msk;
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         ux[c] = uy[c] = uz[c] = rr[c] = fc[c] = dfc[c] = zp[c] = pd[c] = T(0);
+        slot[c] = 0;
         if (c < cnt) {
             const int m = __builtin_ctzll(rem);
+            slot[c] = m;
             rem &= rem - 1;
             const int j = nl[(int64_t)m * n + i];
             const Disp d = cut_disp(xi, xw[j], box);
@@ -170,7 +173,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
                     dz += a * (uz[e] - cs * uz[c]) + bb * uz[c];
                 }
             }
-            T* o = dpart + ((int64_t)c * n + i) * 3;
+            T* o = dpart + ((int64_t)slot[c] * n + i) * 3;
             o[0] = dx;
             o[1] = dy;
             o[2] = dz;
@@ -222,7 +225,7 @@ constexpr int kOvfGrid = 64;
 
 template <class T>
 hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, bool overflow_pass, hipStream_t s)
+                                   double* U, bool overflow_pass, int max_nn, hipStream_t s)
 {
     const int64_t n = b.n;
     if (n <= 0) return hipSuccess;
@@ -234,15 +237,15 @@ hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const Ter
         k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kTersoffTile)
+    if (b.M > kTersoffTile && max_nn > kTersoffTile)
         k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
 template hipError_t launch_tersoff_partials<double>(const Buffers&, int, Box, const TersoffParams&,
-                                                    double*, bool, hipStream_t);
+                                                    double*, bool, int, hipStream_t);
 template hipError_t launch_tersoff_partials<float>(const Buffers&, int, Box, const TersoffParams&,
-                                                   double*, bool, hipStream_t);
+                                                   double*, bool, int, hipStream_t);
 
 }  // namespace mbmd
