@@ -83,9 +83,8 @@ typedef struct {
 /* When nve_run rebuilds the neighbour list (the paper builds it once or on a
  * fixed schedule; Section 3). */
 typedef enum {
-    MBMD_REBUILD_FIXED = 0,    /* every rebuild_every steps, nothing else; the
-                                  largest displacement between builds is only
-                                  reported in the run statistics */
+    MBMD_REBUILD_FIXED = 0,    /* every rebuild_every steps, nothing else; no
+                                  displacement is tracked */
     MBMD_REBUILD_ON_SKIN = 1   /* also before any step whose positions moved
                                   more than skin/2 from the last build
                                   (default) */
@@ -98,7 +97,7 @@ typedef struct {
     int64_t rollbacks;         /* chunks replayed to insert an early rebuild */
     double max_displacement;   /* largest distance (A) any atom moved from its
                                   position at the build of the list it was
-                                  evaluated with */
+                                  evaluated with; -1 under MBMD_REBUILD_FIXED */
 } mbmd_run_stats;
 
 /* Accumulated device time of one class of kernel launches (profiling). */

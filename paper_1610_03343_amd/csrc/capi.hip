@@ -144,7 +144,6 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
     t.xsnap = (double4*)take(sizeof(double4) * nn);
     t.vsnap = (double*)take(sizeof(double) * 3 * nn);
     t.step_disp2 = (unsigned long long*)take(sizeof(unsigned long long) * kMaxChunk);
-    t.maxdisp2 = (unsigned long long*)take(sizeof(unsigned long long));
     t.maxnn = (int*)take(sizeof(int));
     if (b) *b = t;
     return off;
@@ -286,6 +285,8 @@ hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
 {
     hipError_t e;
     for (int pass = 0; pass < 2; ++pass) {
+        // the overflow pass only exists when a site can exceed the fast path
+        if (pass == 1 && !(c->buf.M > kSiteFastBonds && c->max_nn > kSiteFastBonds)) break;
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)
             e = launch_sw_partials<T>(c->buf, cur, box, c->sp, U, pass == 1, c->max_nn, c->stream);
@@ -320,13 +321,6 @@ mbmd_status compute_impl(mbmd_ctx* c, int64_t n, const Box& box, const double* p
     if (e == hipSuccess) e = gather<T>(c, box, a, U, const_cast<double*>(vel), F, W, J);
     if (e != hipSuccess) return hip_fail(c, e, "compute launch");
     return finish(c);
-}
-
-double disp_of(unsigned long long bits)
-{
-    double d2;
-    std::memcpy(&d2, &bits, sizeof d2);
-    return std::sqrt(d2);
 }
 
 // Folds the pending per-step partials into thermo rows.
@@ -383,13 +377,12 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     st.steps = n_steps;
     c->fold_from = c->fold_to = 0;
     int cur = 0, last_build = 0;
-    hipError_t e = launch_fill_int((int*)b.maxdisp2, 2, 0, c->stream);
-    if (e == hipSuccess) e = build(c, cur, box);
+    hipError_t e = build(c, cur, box);
     st.rebuilds = 1;
 
     if (c->policy == MBMD_REBUILD_FIXED) {
-        // The list is rebuilt every `every` steps whatever the atoms do; the
-        // largest displacement between builds is only measured.
+        // The list is rebuilt every `every` steps whatever the atoms do; no
+        // displacement is tracked (the statistics report -1).
         for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
             if (step - last_build == every) {
                 e = build(c, cur, box);
@@ -397,19 +390,14 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
                 ++st.rebuilds;
             }
             if (e != hipSuccess) break;
-            const bool check = (step + 1 - last_build) != every;
-            e = md_step<T>(c, box, a, step, n_steps, cur, check, b.maxdisp2, U, vel, F, W, J,
-                           thermo);
+            e = md_step<T>(c, box, a, step, n_steps, cur, false, nullptr, U, vel, F, W, J, thermo);
             if (step < n_steps) cur ^= 1;
         }
         if (e == hipSuccess) e = flush_thermo(c, thermo);
         if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
-        unsigned long long bits = 0;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&bits, b.maxdisp2, sizeof bits, hipMemcpyDeviceToHost, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "nve launch");
         s = finish(c);
-        st.max_displacement = disp_of(bits);
+        st.max_displacement = -1.0;
         c->stats = st;
         return s;
     }

@@ -27,6 +27,7 @@ enum : unsigned {
 
 constexpr int kBlock = 256;          // threads per block of every per-atom kernel
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
+constexpr int kSiteFastBonds = 8;    // in-cutoff bonds a site pass handles without overflow
 constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
 constexpr int kMaxChunk = 256;       // steps enqueued between two checks of the skin
@@ -75,7 +76,6 @@ struct Buffers {
     double4* xsnap;          // [N] positions at the start of a checked chunk
     double* vsnap;           // [3][N] velocities at the start of a checked chunk
     unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
-    unsigned long long* maxdisp2;    // largest squared displacement over a run
     int* maxnn;                      // largest list count of the last build
 };
 

@@ -132,14 +132,17 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
                 jj[c] = mm[3 * c + 0] * v[0] + mm[3 * c + 1] * v[1] + mm[3 * c + 2] * v[2];
             ekin = a.kin_scale * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         }
-        F[i] = f[0];
-        F[n + i] = f[1];
-        F[2 * n + i] = f[2];
+        // Outputs are not read again by the step loop: streaming stores keep
+        // them from evicting the partials and positions that neighbours of
+        // later atoms still gather from L2.
+        __builtin_nontemporal_store(f[0], &F[i]);
+        __builtin_nontemporal_store(f[1], &F[n + i]);
+        __builtin_nontemporal_store(f[2], &F[2 * n + i]);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) W[(int64_t)c * n + i] = w[c];
-        J[i] = jj[0];
-        J[n + i] = jj[1];
-        J[2 * n + i] = jj[2];
+        for (int c = 0; c < 9; ++c) __builtin_nontemporal_store(w[c], &W[(int64_t)c * n + i]);
+        __builtin_nontemporal_store(jj[0], &J[i]);
+        __builtin_nontemporal_store(jj[1], &J[n + i]);
+        __builtin_nontemporal_store(jj[2], &J[2 * n + i]);
         if (vel) {
 #pragma clang fp contract(off)
             if (a.advance) {

@@ -50,4 +50,61 @@ __device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int
     return msk;
 }
 
+// ---- quad layout: four lanes per atom ------------------------------------
+//
+// The site passes run one atom per aligned group of four lanes.  Lane q owns
+// the in-cutoff bonds c = q + 4 s (s = 0 .. kQuadSlots-1) of its atom, where
+// bond c is the c-th set bit of the atom's cutoff mask (ascending list
+// slot); the lanes exchange bond data with __shfl_xor inside the group.
+constexpr int kQuad = 4;
+constexpr int kQuadSlots = 2;                       // bonds per lane
+constexpr int kQuadBonds = kQuad * kQuadSlots;      // bonds per atom in the fast path
+static_assert(kQuadBonds == kSiteFastBonds, "quad capacity is the fast-path bond count");
+constexpr int kAtomsPerQuadBlock = kBlock / kQuad;  // atoms per 256-lane block
+
+__device__ __forceinline__ double quad_xor(double v, int k) { return __shfl_xor(v, k, kQuad); }
+__device__ __forceinline__ float quad_xor(float v, int k) { return __shfl_xor(v, k, kQuad); }
+
+__device__ __forceinline__ unsigned long long quad_or(unsigned long long v)
+{
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+#pragma unroll
+    for (int k = 1; k < kQuad; k <<= 1) {
+        lo |= __shfl_xor(lo, k, kQuad);
+        hi |= __shfl_xor(hi, k, kQuad);
+    }
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Fixed-order sum over the quad: ((l0 + l1) + (l2 + l3)) on every lane.
+__device__ __forceinline__ double quad_sum(double v)
+{
+    v += __shfl_xor(v, 1, kQuad);
+    v += __shfl_xor(v, 2, kQuad);
+    return v;
+}
+
+// Slot of the c-th set bit of msk (c < popcount(msk)).
+__device__ __forceinline__ int nth_set_bit(unsigned long long msk, int c)
+{
+    for (int k = 0; k < c; ++k) msk &= msk - 1;
+    return __builtin_ctzll(msk);
+}
+
+// Cutoff mask of atom i computed by its quad: lane q tests slots q, q+4, ...
+__device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi, int64_t i,
+                                                               int64_t n, int nnb, int q,
+                                                               const int* __restrict__ nl,
+                                                               const double4* __restrict__ xw,
+                                                               const Box& box, double rc2)
+{
+    unsigned long long msk = 0;
+    for (int m = q; m < nnb; m += kQuad) {
+        const int j = nl[(int64_t)m * n + i];
+        const Disp d = cut_disp(xi, xw[j], box);
+        if (d.r2 < rc2) msk |= 1ull << m;
+    }
+    return quad_or(msk);
+}
+
 }  // namespace mbmd

@@ -159,7 +159,7 @@ k_sw_partials_ovf(SWK<T> p, Box box, int64_t n, const double4* __restrict__ xw,
     }
 }
 
-constexpr int kSWTile = 8;
+constexpr int kSWTile = kSiteFastBonds;
 constexpr int kSWOvfGrid = 64;
 
 template <class T>
@@ -176,7 +176,7 @@ hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams
         k, rc * rc, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kSWTile && max_nn > kSWTile)
+    if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
         k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
     return hipGetLastError();

@@ -181,26 +181,149 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
     }
 }
 
-template <class T, int MAXC>
+// Quad site pass: four lanes per atom, lane q owning bonds q and q + 4.  The
+// arithmetic is the one of tersoff_site, distributed over the quad: each lane
+// forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
+// bonds' unit vectors, f_C and P from the other lanes.  Atoms with more than
+// kQuadBonds in-cutoff bonds go to the overflow list.
+template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_partials(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
-                   const double4* __restrict__ xw, const int* __restrict__ nn,
-                   const int* __restrict__ nl, unsigned long long* __restrict__ mask,
-                   double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
-                   int* __restrict__ ovf_list)
+k_tersoff_site_quad(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
+                    const double4* __restrict__ xw, const int* __restrict__ nn,
+                    const int* __restrict__ nl, unsigned long long* __restrict__ mask,
+                    double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
+                    int* __restrict__ ovf_list)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double4 xi = xw[i];
-    const int nnb = min(nn[i], M);
-    const unsigned long long msk = cutoff_mask(xi, i, n, nnb, nl, xw, box, rc2);
-    mask[i] = msk;
+    const int q = threadIdx.x & (kQuad - 1);
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAtomsPerQuadBlock +
+                      (threadIdx.x >> 2);
+    const bool valid = i < n;
+    const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const int nnb = valid ? min(nn[i], M) : 0;
+    const unsigned long long msk = quad_cutoff_mask(xi, i, n, nnb, q, nl, xw, box, rc2);
     const int cnt = __popcll(msk);
-    if (cnt > MAXC) {
-        ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
-        return;
+    const bool ovf = cnt > kQuadBonds;
+    if (valid && q == 0) {
+        mask[i] = msk;
+        if (ovf) ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
     }
-    tersoff_site<T, MAXC, true>(p, i, n, xi, msk, cnt, nl, xw, box, U, dpart);
+    const int kc = (valid && !ovf) ? cnt : 0;   // bonds handled by this quad
+
+    T ux[kQuadSlots], uy[kQuadSlots], uz[kQuadSlots], rr[kQuadSlots], fc[kQuadSlots],
+        dfc[kQuadSlots], zp[kQuadSlots], pd[kQuadSlots];
+    int slot[kQuadSlots];
+#pragma unroll
+    for (int s = 0; s < kQuadSlots; ++s) {
+        const int c = q + kQuad * s;
+        ux[s] = uy[s] = uz[s] = rr[s] = fc[s] = dfc[s] = zp[s] = pd[s] = T(0);
+        rr[s] = T(1);
+        slot[s] = 0;
+        if (c < kc) {
+            const int m = nth_set_bit(msk, c);
+            slot[s] = m;
+            const int j = nl[(int64_t)m * n + i];
+            const Disp d = cut_disp(xi, xw[j], box);
+            const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
+            const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
+            const T ir = T(1) / r;
+            ux[s] = dx * ir;
+            uy[s] = dy * ir;
+            uz[s] = dz * ir;
+            rr[s] = r;
+            cutoff_fc(p, r, fc[s], dfc[s]);
+        }
+    }
+    // The second bond slot is needed only where some atom has more than kQuad
+    // bonds; the test is wave-uniform so that every lane joins the shuffles.
+    const int tmax = __any(kc > kQuad) ? kQuadSlots : 1;
+
+    // zeta_c = sum over partner bonds e != c of f_C(r_e) g(cos_ce)
+    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const T ex = k ? quad_xor(ux[t], k) : ux[t];
+            const T ey = k ? quad_xor(uy[t], k) : uy[t];
+            const T ez = k ? quad_xor(uz[t], k) : uz[t];
+            const T ef = k ? quad_xor(fc[t], k) : fc[t];
+            const int e = (q ^ k) + kQuad * t;
+#pragma unroll
+            for (int s = 0; s < kQuadSlots; ++s) {
+                const int c = q + kQuad * s;
+                if (c < kc && e < kc && e != c) {
+                    const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
+                    zp[s] += ef * angular_g_only(p, cs);
+                }
+            }
+        }
+    }
+    // bond orders, site energy, pd_c and P_c
+    double u_i = 0.0;
+#pragma unroll
+    for (int s = 0; s < kQuadSlots; ++s) {
+        const int c = q + kQuad * s;
+        if (c < kc) {
+            const T zeta = zp[s];
+            T b = T(1), db = T(0);
+            if (zeta > T(0)) {
+                const T u = t_exp(p.n * t_log(p.beta * zeta));
+                b = t_exp(-t_log1p(u) * p.inv2n);
+                db = -b * u / (T(2) * zeta * (T(1) + u));
+            }
+            const T fr = p.A * t_exp(-p.lam * rr[s]);
+            const T fa = p.B * t_exp(-p.mu * rr[s]);
+            u_i += (double)(fc[s] * (fr - b * fa));
+            pd[s] = dfc[s] * (fr - b * fa) + fc[s] * (-p.lam * fr + b * p.mu * fa);
+            zp[s] = fc[s] * fa * db;
+        }
+    }
+    u_i = quad_sum(u_i);
+    if (q == 0 && kc > 0) U[i] = 0.5 * u_i;
+    if (q == 0 && valid && !ovf && kc == 0) U[i] = 0.0;
+
+    // partials dU_i/dr_c
+    T gx[kQuadSlots], gy[kQuadSlots], gz[kQuadSlots], ir[kQuadSlots];
+#pragma unroll
+    for (int s = 0; s < kQuadSlots; ++s) {
+        ir[s] = T(1) / rr[s];
+        gx[s] = T(0.5) * pd[s] * ux[s];
+        gy[s] = T(0.5) * pd[s] * uy[s];
+        gz[s] = T(0.5) * pd[s] * uz[s];
+    }
+    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const T ex = k ? quad_xor(ux[t], k) : ux[t];
+            const T ey = k ? quad_xor(uy[t], k) : uy[t];
+            const T ez = k ? quad_xor(uz[t], k) : uz[t];
+            const T ef = k ? quad_xor(fc[t], k) : fc[t];
+            const T ep = k ? quad_xor(zp[t], k) : zp[t];
+            const int e = (q ^ k) + kQuad * t;
+#pragma unroll
+            for (int s = 0; s < kQuadSlots; ++s) {
+                const int c = q + kQuad * s;
+                if (c < kc && e < kc && e != c) {
+                    const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
+                    T g, dg;
+                    angular_g(p, cs, g, dg);
+                    const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
+                    const T bb = T(-0.5) * ep * dfc[s] * g;
+                    gx[s] += a * (ex - cs * ux[s]) + bb * ux[s];
+                    gy[s] += a * (ey - cs * uy[s]) + bb * uy[s];
+                    gz[s] += a * (ez - cs * uz[s]) + bb * uz[s];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kQuadSlots; ++s) {
+        const int c = q + kQuad * s;
+        if (c < kc) {
+            T* o = dpart + ((int64_t)slot[s] * n + i) * 3;
+            o[0] = gx[s];
+            o[1] = gy[s];
+            o[2] = gz[s];
+        }
+    }
 }
 
 // Atoms whose in-cutoff count exceeded the main tile; the tile here covers
@@ -220,7 +343,6 @@ k_tersoff_partials_ovf(TersoffK<T> p, Box box, int64_t n, const double4* __restr
     }
 }
 
-constexpr int kTersoffTile = 8;
 constexpr int kOvfGrid = 64;
 
 template <class T>
@@ -233,11 +355,12 @@ hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const Ter
     const double rc2 = p.S * p.S;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_tersoff_partials<T, kTersoffTile><<<blocks_for(n), kBlock, 0, s>>>(
-        k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
+        const int nb = (int)((n + kAtomsPerQuadBlock - 1) / kAtomsPerQuadBlock);
+        k_tersoff_site_quad<T><<<nb, kBlock, 0, s>>>(k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl,
+                                                      b.mask, U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kTersoffTile && max_nn > kTersoffTile)
+    if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
         k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
                                               b.ovf_count, b.ovf_list);
     return hipGetLastError();

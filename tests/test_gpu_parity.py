@@ -176,7 +176,7 @@ def test_nve_trajectory_parity(pot, cells, steps, policy):
           f"oracle builds {ref['builds']}, max displacement {stats['max_displacement']:.3f} A")
     assert stats["rebuilds"] == ref["builds"]
     if policy == "skin":
-        assert stats["max_displacement"] <= 0.25
+        assert 0.0 < stats["max_displacement"] <= 0.25
     print(f"trajectory tolerances: x {tol['x']:.2e} A, v {tol['v']:.2e} A/fs")
     assert np.max(np.abs(min_image(gp - ref["pos"], s.box))) <= tol["x"]
     assert np.max(np.abs(gv - ref["vel"])) <= tol["v"]
@@ -292,7 +292,7 @@ def test_error_paths():
         ctx.set_rebuild_policy("fixed")
         ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
         st = ctx.run_stats()
-        assert st["rebuilds"] == 1 and st["max_displacement"] > 0.8
+        assert st["rebuilds"] == 1 and st["max_displacement"] == -1.0
         vel = torch.full((3, s.n), 0.05, dtype=torch.float64, device="cuda:0")
         ctx.set_rebuild_policy("skin")
         ctx.nve_run(pos.clone(), vel, s.box, wl.M_SI, 1.0, 10, rebuild_every=100)
