@@ -1,12 +1,12 @@
 #!/usr/bin/env python3
 """Benchmark of the many-body force path on one MI355X.
 
-Workload (the headline configuration): Tersoff (1989) silicon, diamond
-40x40x40 conventional cells = 512,000 atoms, a = 5.43 A, periodic, seeded
-Gaussian displacements sigma = 0.05 A, 300 K velocities (seed 1002); NVE
-velocity-Verlet at dt = 1 fs; cell-list neighbour rebuild every 20 steps
-with a 0.5 A skin; per-atom energy, force, 9-component virial and heat
-current computed and stored every step; a thermo row per step.
+Headline workload: Tersoff (1989) silicon, diamond 40x40x40 conventional
+cells = 512,000 atoms, a = 5.43 A, periodic, seeded Gaussian displacements
+sigma = 0.05 A, 300 K velocities (seed 1002); NVE velocity-Verlet at
+dt = 1 fs; cell-list neighbour rebuild every 20 steps with a 0.5 A skin;
+per-atom energy, force, 9-component virial and heat current computed and
+stored every step; a thermo row per step.  FP64.
 
 One "step" is one MD step of the whole path (list build when due, site-local
 partials, pairwise forces with the fused integrator, thermo reduction).
@@ -14,13 +14,29 @@ Inputs are resident in HBM before the timed region; the timed region is one
 mbmd_nve_run of --steps steps (plus the force evaluation at its start),
 bracketed by device synchronisation.
 
+Also measured, as extra fields of the same line:
+  mixed    the same input with FP32 bond-order/force arithmetic, --mixed-steps
+           steps: throughput, max |dF| and per-atom energy error against the
+           oracle at step 0 and against the FP64 path on the mixed
+           trajectory every --mixed-check steps, total-energy drift of both
+           paths (eV/atom/ps, linear fit)
+  sw_1m    Stillinger-Weber (1985) Si, 50x50x50 cells = 1,000,000 atoms, FP64
+  serving  a Poisson request trace through the continuous-batching loop and
+           through one structure per launch, p50/p99 latency to results on
+           the host, both precisions, and an HBM-capped batch
+  roofline the dominant kernel's achieved HBM bandwidth from HIP events
+  cpu_baseline  the CPU oracle on a bounded sample of the headline workload
+
 Prints ONE JSON line.  Progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +45,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s, Tersoff Si 512k atoms (FP64 vs mixed); p50/p99 batched latency"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tersoff_512k_fp64_hbm_traffic.md")
 
 
 def log(msg):
@@ -54,6 +71,230 @@ def algorithmic_bytes(kernel: str, k_cut: float, l_list: float, dsize: int) -> f
     return 0.0
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the HIP sources and headers the library is built from."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1610_03343_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "mbmd.h"))
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind: str):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None if it is missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None, None
+    m = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not m or m.group(1) != kernel_source_hash():
+        return None, None
+    m = re.search(rf"^traffic\s+{re.escape(kind)}:\s*fetch_bytes=([0-9.e+]+)\s+"
+                  rf"write_bytes=([0-9.e+]+)", text, re.M)
+    if not m:
+        return None, None
+    return float(m.group(1)) + float(m.group(2)), {"fetch": float(m.group(1)),
+                                                   "write": float(m.group(2))}
+
+
+def list_statistics(ctx, pos_dev, sysm, cutoff):
+    """Mean list length and mean in-cutoff count of the GPU-built list."""
+    import numpy as np
+    nn, nl = ctx.neighbors(pos_dev, sysm.box)
+    nn_h = nn.cpu().numpy()
+    nl_h = nl.cpu().numpy()
+    n = sysm.n
+    idx = np.arange(n)
+    kc = 0
+    for m in range(int(nn_h.max())):
+        have = nn_h > m
+        j = nl_h[m, have]
+        d = sysm.pos[j] - sysm.pos[idx[have]]
+        d -= sysm.box * np.rint(d / sysm.box)
+        kc += int(np.sum(np.sum(d * d, axis=1) < cutoff ** 2))
+    return float(nn_h.mean()), kc / n
+
+
+def drift_per_ps(thermo, n, dt_fs):
+    """Slope of the total energy per atom against time, eV/atom/ps."""
+    import numpy as np
+    t = np.arange(thermo.shape[0]) * dt_fs * 1e-3
+    e = thermo[:, 14] / n
+    return float(np.polyfit(t, e, 1)[0])
+
+
+class Workload:
+    """A resident input and the nve timing around it."""
+
+    def __init__(self, mb, wl, torch, sysm, pot, every, skin, max_nb):
+        self.mb, self.wl, self.torch = mb, wl, torch
+        self.s = sysm
+        self.n = sysm.n
+        self.dev = torch.device("cuda", 0)
+        self.pos0 = torch.tensor(wl.soa(sysm.pos), device=self.dev)
+        self.vel0 = torch.tensor(wl.soa(sysm.vel), device=self.dev)
+        self.every = every
+        self.ctx = mb.Context(0)
+        if pot == "tersoff":
+            self.ctx.set_tersoff(wl.TERSOFF_SI_1989)
+        else:
+            self.ctx.set_sw(wl.SW_SI_1985)
+        self.ctx.set_neighbor(skin, max_nb)
+        self.ctx.set_rebuild_policy("fixed")
+        z = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=self.dev)
+        self.out = dict(U=z(self.n), F=z(3, self.n), W=z(9, self.n), J=z(3, self.n))
+
+    def run(self, precision, steps, pos=None, vel=None, thermo=None):
+        torch, mb = self.torch, self.mb
+        if pos is None:
+            pos, vel = self.pos0.clone(), self.vel0.clone()
+        if thermo is None:
+            thermo = torch.empty(steps + 1, mb.THERMO_COLS, dtype=torch.float64, device=self.dev)
+        self.ctx.nve_run(pos, vel, self.s.box, self.wl.M_SI, 1.0, steps, self.every,
+                         precision=precision, thermo=thermo, out=self.out)
+        return pos, vel, thermo
+
+    def timed(self, precision, steps, warmup):
+        torch = self.torch
+        if warmup > 0:
+            self.run(precision, warmup)
+        pos, vel = self.pos0.clone(), self.vel0.clone()
+        thermo = torch.empty(steps + 1, self.mb.THERMO_COLS, dtype=torch.float64, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self.run(precision, steps, pos, vel, thermo)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, self.ctx.run_stats(), thermo.cpu().numpy(), pos, vel
+
+    def close(self):
+        self.ctx.close()
+
+
+def bench_mixed(W, args):
+    """Mixed path on the headline input: throughput, errors, drift."""
+    import numpy as np
+    import oracle
+    torch, wl = W.torch, W.wl
+    n = W.n
+    steps = args.mixed_steps
+    log(f"mixed: timed {steps} steps (+{args.warmup} warmup)")
+    tmx, stmx, th_mx, pos_mx, vel_mx = W.timed("mixed", steps, args.warmup)
+    log(f"mixed: {tmx:.3f} s, {n * steps / tmx:.4e} atom-steps/s")
+    log(f"fp64 reference run: {steps} steps")
+    t64, _, th_64, _, _ = W.timed("fp64", steps, 0)
+
+    # step 0 against the oracle (the same seed and input)
+    log("oracle force evaluation of the 512k input for the step-0 errors")
+    nn, nl = oracle.neighbors(W.s.pos, W.s.box, wl.TERSOFF_SI_1989["S"] + 0.5, 16)
+    ref = oracle.tersoff(wl.TERSOFF_SI_1989, W.s.pos, W.s.box, nn, nl, vel=W.s.vel)
+    out_m = W.ctx.compute(W.pos0, W.s.box, vel=W.vel0, precision="mixed")
+    fm = out_m["F"].cpu().numpy().T
+    um = out_m["U"].cpu().numpy()
+    err0 = {"step": 0, "against": "oracle",
+            "max_abs_dF_eV_per_A": float(np.max(np.abs(fm - ref["F"]))),
+            "max_abs_dU_i_eV": float(np.max(np.abs(um - ref["U"])))}
+
+    # the mixed trajectory in chunks (the chunked run reproduces the continuous
+    # one bit for bit); FP64 and mixed evaluated on its positions
+    checks = [err0]
+    pos, vel = W.pos0.clone(), W.vel0.clone()
+    done = 0
+    chunk = args.mixed_check
+    while done < steps:
+        k = min(chunk, steps - done)
+        W.run("mixed", k, pos, vel)
+        done += k
+        o64 = W.ctx.compute(pos, W.s.box, vel=vel, precision="fp64")
+        omx = W.ctx.compute(pos, W.s.box, vel=vel, precision="mixed")
+        checks.append({
+            "step": done, "against": "fp64 path",
+            "max_abs_dF_eV_per_A": float((omx["F"] - o64["F"]).abs().max()),
+            "max_abs_dU_i_eV": float((omx["U"] - o64["U"]).abs().max())})
+    same = bool(torch.equal(pos, pos_mx) and torch.equal(vel, vel_mx))
+    return {
+        "value": n * steps / tmx, "unit": "atom-steps/s", "steps": steps,
+        "ms_per_step": 1e3 * tmx / steps, "rebuilds": stmx["rebuilds"],
+        "fp64_same_steps_s": t64,
+        "max_abs_dF_eV_per_A": max(c["max_abs_dF_eV_per_A"] for c in checks),
+        "max_abs_dU_i_eV": max(c["max_abs_dU_i_eV"] for c in checks),
+        "checkpoints": checks,
+        "energy_drift_eV_per_atom_per_ps": {"mixed": drift_per_ps(th_mx, n, 1.0),
+                                            "fp64": drift_per_ps(th_64, n, 1.0)},
+        "energy_change_eV_per_atom": {"mixed": float((th_mx[-1, 14] - th_mx[0, 14]) / n),
+                                      "fp64": float((th_64[-1, 14] - th_64[0, 14]) / n)},
+        "chunked_run_bitwise_equal": same,
+    }
+
+
+def bench_sw(mb, wl, torch, args):
+    log("generating the 1,000,000-atom SW Si input (seed 1003)")
+    s = wl.sw_1m()
+    W = Workload(mb, wl, torch, s, "sw", 20, 0.5, 32)
+    steps = args.sw_steps
+    log(f"SW 1M: timed {steps} steps (+{args.warmup} warmup)")
+    t, st, th, _, _ = W.timed("fp64", steps, args.warmup)
+    l_list, k_cut = list_statistics(W.ctx, W.pos0, s, wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
+    W.close()
+    log(f"SW 1M: {t:.3f} s, {s.n * steps / t:.4e} atom-steps/s")
+    return {"value": s.n * steps / t, "unit": "atom-steps/s", "dtype": "f64", "steps": steps,
+            "ms_per_step": 1e3 * t / steps, "rebuilds": st["rebuilds"],
+            "energy_change_eV_per_atom": float((th[-1, 14] - th[0, 14]) / s.n),
+            "config": {"workload": "sw_si_diamond_50x50x50_1000000_atoms_nve", "atoms": s.n,
+                       "rebuild_every": 20, "skin_A": 0.5, "seed": 1003,
+                       "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4)}}
+
+
+def bench_serving(mb, wl, torch, args):
+    from paper_1610_03343_amd import serving
+    log(f"serving: generating {args.serve_requests} requests (seed 2001)")
+    reqs = wl.serving_trace(args.serve_requests, rate_hz=1.0, seed=2001)
+    base = serving.jobs_from_requests(reqs)
+    atoms = [j.n for j in base]
+    every = 5
+
+    def ctx():
+        c = mb.Context(0)
+        c.set_tersoff(wl.TERSOFF_SI_1989)
+        c.set_neighbor(0.5, 16)
+        return c
+
+    c = ctx()
+    # warm-up and capacity: the first requests all present at time 0
+    sub = base[: args.serve_calib]
+    serving.serve_batched(c, sub[:32], saturate=True, rebuild_every=every)
+    _, st = serving.serve_batched(c, sub, saturate=True, rebuild_every=every)
+    cap_rps = len(sub) / st.makespan_s
+    rate = args.serve_load * cap_rps
+    log(f"serving: batched capacity {cap_rps:.1f} requests/s; arrival rate {rate:.1f}/s")
+    jobs = serving.jobs_from_requests(reqs, time_scale=1.0 / rate)
+    res = {"requests": len(jobs), "arrival_rate_per_s": rate,
+           "batched_capacity_requests_per_s": cap_rps, "load_fraction": args.serve_load,
+           "atoms_per_request": {"min": min(atoms), "median": float(sorted(atoms)[len(atoms) // 2]),
+                                 "max": max(atoms)},
+           "nve_fraction": sum(1 for j in jobs if j.n_steps) / len(jobs),
+           "rebuild_every": every, "latency": "arrival to results (U, F, W, J, x, v) on the host"}
+    for prec in ("fp64", "mixed"):
+        log(f"serving: batched {prec}")
+        _, sb = serving.serve_batched(c, jobs, precision=prec, rebuild_every=every)
+        log(f"serving: one structure per launch {prec}")
+        _, ss = serving.serve_sequential(c, jobs, precision=prec, rebuild_every=every)
+        res[prec] = {"batched": sb.summary(), "one_per_launch": ss.summary()}
+        log(f"serving {prec}: batched p50/p99 {sb.summary()['p50_ms']:.2f}/"
+            f"{sb.summary()['p99_ms']:.2f} ms; one per launch "
+            f"{ss.summary()['p50_ms']:.2f}/{ss.summary()['p99_ms']:.2f} ms")
+    log(f"serving: batched fp64 with a {args.serve_cap_mib} MiB HBM budget")
+    _, sc = serving.serve_batched(c, jobs, precision="fp64", rebuild_every=every,
+                                  hbm_budget_bytes=args.serve_cap_mib << 20)
+    res["fp64_hbm_capped"] = dict(sc.summary(), hbm_budget_mib=args.serve_cap_mib)
+    c.close()
+    return res
+
+
 def run_cpu_baseline(sysm, steps):
     import oracle
     import workload as wl
@@ -68,13 +309,23 @@ def run_cpu_baseline(sysm, steps):
 
 
 def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=10, help="oracle sample length")
+    ap.add_argument("--mixed-steps", type=int, default=10000)
+    ap.add_argument("--mixed-check", type=int, default=1000)
+    ap.add_argument("--sw-steps", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-calib", type=int, default=400)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-cap-mib", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-sw", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200,
                     help="steps of the HIP-event profiled pass used for the roofline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -87,86 +338,31 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1610_03343_amd as mb
     import workload as wl
 
-    dev = torch.device("cuda", 0)
     log("generating the 512,000-atom Tersoff Si input (seed 1002)")
     s = wl.tersoff_512k()
     n = s.n
-    pos0 = torch.tensor(wl.soa(s.pos), device=dev)
-    vel0 = torch.tensor(wl.soa(s.vel), device=dev)
-    every, skin, dt = 20, 0.5, 1.0
-
-    ctx = mb.Context(0)
-    ctx.set_tersoff(wl.TERSOFF_SI_1989)
-    ctx.set_neighbor(skin, 16)
-    ctx.set_rebuild_policy("fixed")
-
-    # list statistics for the byte accounting (host numpy on the GPU-built list)
-    nn, nl = ctx.neighbors(pos0, s.box)
-    nn_h = nn.cpu().numpy()
-    nl_h = nl.cpu().numpy()
-    l_list = float(nn_h.mean())
-    idx = np.arange(n)
-    kc = 0
-    for m in range(int(nn_h.max())):
-        have = nn_h > m
-        j = nl_h[m, have]
-        d = s.pos[j] - s.pos[idx[have]]
-        d -= s.box * np.rint(d / s.box)
-        kc += int(np.sum(np.sum(d * d, axis=1) < wl.TERSOFF_SI_1989["S"] ** 2))
-    k_cut = kc / n
-
-    out = {k: torch.empty(sh, dtype=torch.float64, device=dev)
-           for k, sh in (("U", (n,)), ("F", (3, n)), ("W", (9, n)), ("J", (3, n)))}
-    thermo = torch.empty(args.steps + 1, mb.THERMO_COLS, dtype=torch.float64, device=dev)
-
-    def timed(precision, steps, warmup):
-        pos, vel = pos0.clone(), vel0.clone()
-        if warmup > 0:
-            th_w = torch.empty(warmup + 1, mb.THERMO_COLS, dtype=torch.float64, device=dev)
-            ctx.nve_run(pos, vel, s.box, wl.M_SI, dt, warmup, every, precision=precision,
-                        thermo=th_w, out=out)
-        pos.copy_(pos0)
-        vel.copy_(vel0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.nve_run(pos, vel, s.box, wl.M_SI, dt, steps, every, precision=precision,
-                    thermo=thermo[: steps + 1], out=out)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        th = thermo[: steps + 1].cpu().numpy()
-        stats = ctx.run_stats()
-        drift = float((th[-1, 14] - th[0, 14]) / n)
-        return t1 - t0, stats, drift
+    every, skin = 20, 0.5
+    W = Workload(mb, wl, torch, s, "tersoff", every, skin, 16)
+    l_list, k_cut = list_statistics(W.ctx, W.pos0, s, wl.TERSOFF_SI_1989["S"])
 
     log(f"timed FP64 run: {args.warmup} warmup + {args.steps} steps")
-    t64, st64, drift64 = timed("fp64", args.steps, args.warmup)
+    t64, st64, th64, _, _ = W.timed("fp64", args.steps, args.warmup)
     value = n * args.steps / t64
     log(f"FP64: {t64:.3f} s, {value:.4e} atom-steps/s, rebuilds {st64['rebuilds']}")
-
-    mixed = None
-    if not args.no_mixed:
-        log(f"timed mixed run: {args.warmup} warmup + {args.steps} steps")
-        tmx, stmx, driftmx = timed("mixed", args.steps, args.warmup)
-        mixed = {"value": n * args.steps / tmx, "unit": "atom-steps/s",
-                 "ms_per_step": 1e3 * tmx / args.steps,
-                 "energy_change_eV_per_atom": driftmx, "rebuilds": stmx["rebuilds"]}
-        log(f"mixed: {tmx:.3f} s, {mixed['value']:.4e} atom-steps/s")
 
     # HIP-event profiled pass of the same workload: per-kernel durations
     psteps = min(args.profile_steps, args.steps)
     log(f"profiled FP64 pass: {psteps} steps with HIP events per kernel launch")
-    ctx.set_profiling(True)
-    ctx.reset_profile()
-    pos, vel = pos0.clone(), vel0.clone()
-    ctx.nve_run(pos, vel, s.box, wl.M_SI, dt, psteps, every, thermo=thermo[: psteps + 1], out=out)
-    prof = ctx.profile()
-    ctx.set_profiling(False)
+    W.ctx.set_profiling(True)
+    W.ctx.reset_profile()
+    W.run("fp64", psteps)
+    prof = W.ctx.profile()
+    W.ctx.set_profiling(False)
     kernels = {}
     for name, (launches, ms) in prof.items():
         if launches == 0:
@@ -179,28 +375,37 @@ def main():
     dom = max(("site_partials", "pair_gather"), key=lambda k: prof[k][1])
     dk = kernels[dom]
     achieved = dk["achieved_GBs"]
+    traffic, traffic_parts = measured_traffic(dom)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_us": dk["avg_us"],
                 "algorithmic_bytes_per_launch": round(dk["algorithmic_bytes_per_atom"] * n)}
+    if traffic_parts:
+        roofline["traffic_parts"] = traffic_parts
     log(f"dominant kernel {dom}: {dk['avg_us']} us, {achieved} GB/s")
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib * (1 << 20)
-        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=W.dev).fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written, x5")
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB "
+            f"written, x5")
+        del a, b
+
+    mixed = None if args.no_mixed else bench_mixed(W, args)
+    W.close()
+    sw = None if args.no_sw else bench_sw(mb, wl, torch, args)
+    serve = None if args.no_serving else bench_serving(mb, wl, torch, args)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(s, args.cpu_steps)
         log(f"cpu baseline: {cpu['value']:.4e} atom-steps/s")
 
-    ctx.close()
     line = {
         "metric": METRIC,
         "value": value,
@@ -215,13 +420,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "tersoff_si_diamond_40x40x40_512000_atoms_nve",
-                   "atoms": n, "potential": "Tersoff 1989 Si (R=2.7, S=3.0)", "dt_fs": dt,
+                   "atoms": n, "potential": "Tersoff 1989 Si (R=2.7, S=3.0)", "dt_fs": 1.0,
                    "rebuild_every": every, "skin_A": skin, "rebuild_policy": "fixed",
                    "per_step_outputs": "U, F, W(9), J(3) per atom + thermo row",
                    "seed": 1002, "parallelism": "single_gpu",
                    "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4)},
-        "fp64_run": {"rebuilds": st64["rebuilds"], "energy_change_eV_per_atom": drift64},
+        "fp64_run": {"rebuilds": st64["rebuilds"],
+                     "energy_change_eV_per_atom": float((th64[-1, 14] - th64[0, 14]) / n)},
         "mixed": mixed,
+        "sw_1m": sw,
+        "serving": serve,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -52,7 +52,8 @@ typedef enum {
     MBMD_ENEIGH = 5,      /* a neighbour list needed more than max_neighbors slots */
     MBMD_ESKIN = 6,       /* reserved (skin violations are handled by the rebuild policy) */
     MBMD_ENONFINITE = 7,  /* a non-finite position */
-    MBMD_ENOPOT = 8       /* no potential set on the context */
+    MBMD_ENOPOT = 8,      /* no potential set on the context */
+    MBMD_EBUSY = 9        /* serving batch: no room now, or structure not finished */
 } mbmd_status;
 
 typedef enum {
@@ -200,6 +201,73 @@ mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
                          double mass_amu, double *pos, double *vel, const int32_t *types,
                          double dt_fs, int n_steps, int rebuild_every, double *U, double *F,
                          double *W, double *J, double *thermo);
+
+/* ---- serving batch ------------------------------------------------------
+ *
+ * Continuous batching of independent structures (the serving form of the
+ * path): a batch keeps every admitted structure's positions, velocities and
+ * outputs on the device and advances all unfinished structures together, one
+ * step per mbmd_batch_step, in single launches whose blocks map to
+ * (structure, atom range) through a segment table with per-structure boxes,
+ * cell grids, offsets and time steps.  Structures can be admitted whenever
+ * an atom range and a slot are free, also while others are mid-run.  A
+ * structure's results do not depend on what else shares the batch: every
+ * per-atom sum runs over its own sorted list, and every per-structure sum
+ * over its own blocks in a fixed order, so they equal, bit for bit, those of
+ * the same structure alone.  While a batch is open the context accepts only
+ * batch calls.  The lists of a structure are rebuilt at its admission and
+ * every rebuild_every of its steps. */
+
+/* Open a batch of at most max_atoms atoms in at most max_structures
+ * structures (the workspace is sized for that; see
+ * mbmd_batch_workspace_size; a small pinned host buffer for table uploads is
+ * allocated too).  Uses the context's potential, skin and list capacity.
+ * MBMD_ENOMEM if the workspace or the pinned buffer cannot be had,
+ * MBMD_EINVAL if a batch is already open or a size is out of range. */
+mbmd_status mbmd_batch_open(mbmd_ctx *ctx, int64_t max_atoms, int max_structures,
+                            int rebuild_every);
+
+/* Device bytes of workspace a batch of this capacity needs. */
+mbmd_status mbmd_batch_workspace_size(const mbmd_ctx *ctx, int64_t max_atoms,
+                                      int max_structures, size_t *bytes);
+
+/* Free atoms, free structure slots and the largest contiguous free atom
+ * range of the open batch (a structure needs a contiguous range). */
+mbmd_status mbmd_batch_capacity(const mbmd_ctx *ctx, int64_t *free_atoms, int *free_slots,
+                                int64_t *largest_range);
+
+/* Admit a structure: n atoms at device positions pos[3][n] with velocities
+ * vel[3][n] (copied on the context's stream: the caller may overwrite them
+ * with work enqueued after this call on that stream), periodic box (host),
+ * mass, time step, and n_steps NVE steps (0: one force evaluation).
+ * thermo (device [n_steps + 1][16] or NULL; it must stay allocated until the
+ * structure is retired) receives its thermo rows as it runs, in the layout
+ * of mbmd_nve_run.  *handle identifies it.  MBMD_EBUSY when no slot or no
+ * contiguous atom range of n atoms is free; MBMD_EBOX, MBMD_EINVAL as for
+ * mbmd_nve_run.  A non-finite position is reported by the retire call. */
+mbmd_status mbmd_batch_add(mbmd_ctx *ctx, int64_t n, const double box[3], const double *pos,
+                           const double *vel, double mass_amu, double dt_fs, int n_steps,
+                           double *thermo, int *handle);
+
+/* One step of every unfinished structure (its force evaluation, and the
+ * integration unless it is at its last step).  *n_active receives the
+ * number of structures that took part.  Asynchronous: returns once the work
+ * is enqueued. */
+mbmd_status mbmd_batch_step(mbmd_ctx *ctx, mbmd_precision prec, int *n_active);
+
+/* Handles of finished, not yet retired structures (up to capacity; *count
+ * receives the total).  Finished means that its last step has been
+ * enqueued; the retire call waits for it. */
+mbmd_status mbmd_batch_finished(const mbmd_ctx *ctx, int *handles, int capacity, int *count);
+
+/* Copy a finished structure's final positions, velocities and per-atom U, F,
+ * W, J into caller device buffers (any may be NULL), free its slot and atom
+ * range, and synchronise the stream. */
+mbmd_status mbmd_batch_retire(mbmd_ctx *ctx, int handle, double *pos, double *vel, double *U,
+                              double *F, double *W, double *J);
+
+/* Close the batch (device memory stays with the context). */
+mbmd_status mbmd_batch_close(mbmd_ctx *ctx);
 
 #ifdef __cplusplus
 }

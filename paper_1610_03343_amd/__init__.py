@@ -21,11 +21,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmbmd.so")
 
 MBMD_OK, MBMD_EINVAL, MBMD_ENOMEM, MBMD_EDEVICE, MBMD_EBOX = 0, 1, 2, 3, 4
-MBMD_ENEIGH, MBMD_ESKIN, MBMD_ENONFINITE, MBMD_ENOPOT = 5, 6, 7, 8
+MBMD_ENEIGH, MBMD_ESKIN, MBMD_ENONFINITE, MBMD_ENOPOT, MBMD_EBUSY = 5, 6, 7, 8, 9
 MBMD_FP64, MBMD_MIXED = 0, 1
 STATUS_NAMES = {0: "MBMD_OK", 1: "MBMD_EINVAL", 2: "MBMD_ENOMEM", 3: "MBMD_EDEVICE",
                 4: "MBMD_EBOX", 5: "MBMD_ENEIGH", 6: "MBMD_ESKIN", 7: "MBMD_ENONFINITE",
-                8: "MBMD_ENOPOT"}
+                8: "MBMD_ENOPOT", 9: "MBMD_EBUSY"}
 THERMO_COLS = 16
 MBMD_REBUILD_FIXED, MBMD_REBUILD_ON_SKIN = 0, 1
 
@@ -79,6 +79,14 @@ def _load():
         "mbmd_neighbors": ([P, I64, P, P, P, P], I),
         "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
+        "mbmd_batch_open": ([P, I64, I, I], I),
+        "mbmd_batch_workspace_size": ([P, I64, I, C.POINTER(C.c_size_t)], I),
+        "mbmd_batch_capacity": ([P, C.POINTER(I64), C.POINTER(I), C.POINTER(I64)], I),
+        "mbmd_batch_add": ([P, I64, P, P, P, D, D, I, P, C.POINTER(I)], I),
+        "mbmd_batch_step": ([P, I, C.POINTER(I)], I),
+        "mbmd_batch_finished": ([P, C.POINTER(I), I, C.POINTER(I)], I),
+        "mbmd_batch_retire": ([P, I, P, P, P, P, P, P], I),
+        "mbmd_batch_close": ([P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +281,72 @@ class Context:
         if th is not None:
             out["thermo"] = th
         return out
+
+    # -- serving batch --------------------------------------------------------
+    def batch_workspace_size(self, max_atoms: int, max_structures: int) -> int:
+        v = C.c_size_t()
+        self._check(_lib.mbmd_batch_workspace_size(self._h, int(max_atoms), int(max_structures),
+                                                   C.byref(v)), "mbmd_batch_workspace_size")
+        return v.value
+
+    def batch_open(self, max_atoms: int, max_structures: int, rebuild_every: int = 10):
+        self._check(_lib.mbmd_batch_open(self._h, int(max_atoms), int(max_structures),
+                                         int(rebuild_every)), "mbmd_batch_open")
+        self._batch_keep = {}
+        self._batch_fin = (C.c_int * int(max_structures))()
+
+    def batch_close(self):
+        self._check(_lib.mbmd_batch_close(self._h), "mbmd_batch_close")
+        self._batch_keep = {}
+
+    def batch_capacity(self):
+        """(free atoms, free structure slots, largest contiguous free range)."""
+        fa, fs, lr = C.c_int64(), C.c_int(), C.c_int64()
+        self._check(_lib.mbmd_batch_capacity(self._h, C.byref(fa), C.byref(fs), C.byref(lr)),
+                    "mbmd_batch_capacity")
+        return fa.value, fs.value, lr.value
+
+    def batch_add(self, pos, vel, box, mass, dt, n_steps, thermo=None) -> int:
+        """Admit a structure; returns its handle (raises MbmdError EBUSY if no room)."""
+        n = pos.shape[1]
+        th = thermo
+        h = C.c_int()
+        self._check(_lib.mbmd_batch_add(
+            self._h, n, _box(box), _dptr(pos, (3, n), "pos"), _dptr(vel, (3, n), "vel"),
+            float(mass), float(dt), int(n_steps),
+            _dptr(th, (n_steps + 1, THERMO_COLS), "thermo") if th is not None else None,
+            C.byref(h)), "mbmd_batch_add")
+        if th is not None:
+            self._batch_keep[h.value] = th      # the library writes into it while it runs
+        return h.value
+
+    def batch_step(self, precision="fp64") -> int:
+        a = C.c_int()
+        self._check(_lib.mbmd_batch_step(self._h, _prec(precision), C.byref(a)), "mbmd_batch_step")
+        return a.value
+
+    def batch_finished(self):
+        cnt = C.c_int()
+        arr = self._batch_fin
+        self._check(_lib.mbmd_batch_finished(self._h, arr, len(arr), C.byref(cnt)),
+                    "mbmd_batch_finished")
+        if cnt.value > len(arr):
+            arr = self._batch_fin = (C.c_int * cnt.value)()
+            self._check(_lib.mbmd_batch_finished(self._h, arr, len(arr), C.byref(cnt)),
+                        "mbmd_batch_finished")
+        return list(arr[: cnt.value])
+
+    def batch_retire(self, handle: int, n: int, out=None):
+        """Copy a finished structure's final pos, vel, U, F, W, J out and free it."""
+        if out is None:
+            z = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
+            out = dict(pos=z(3, n), vel=z(3, n), U=z(n), F=z(3, n), W=z(9, n), J=z(3, n))
+        self._check(_lib.mbmd_batch_retire(
+            self._h, int(handle), _dptr(out["pos"], (3, n), "pos"), _dptr(out["vel"], (3, n), "vel"),
+            _dptr(out["U"], (n,), "U"), _dptr(out["F"], (3, n), "F"), _dptr(out["W"], (9, n), "W"),
+            _dptr(out["J"], (3, n), "J")), "mbmd_batch_retire")
+        th = self._batch_keep.pop(handle, None)
+        if th is not None:
+            out["thermo"] = th
+        return out
+

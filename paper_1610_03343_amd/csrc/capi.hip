@@ -1,6 +1,8 @@
 // C ABI of libmbmd (declared in include/mbmd.h): contexts, workspace, and the
-// host-side step loop that sequences the neighbour build, the site-local
-// partials pass and the pairwise-force pass on one HIP stream.
+// host-side loops that sequence the neighbour build, the site-local partials
+// pass and the pairwise-force pass on one HIP stream, for one structure or
+// for a batch of independent structures (segments) sharing each launch.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,6 +23,39 @@ struct ProfRec {
     int kind;
     hipEvent_t a, b;
 };
+
+constexpr double kKappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
+
+// One structure admitted to the serving batch.
+struct Slot {
+    int handle = -1;
+    int atom_off = 0, n = 0;
+    Box box{};
+    int nsteps = 0;
+    int step = 0;            // index of its next step
+    double mass = 0, dt = 0;
+    double* thermo = nullptr;
+    int last_build = -1;     // its step at the last list build (-1: none yet)
+    int final_buf = 0;       // position buffer holding its final positions
+    bool done = false;
+};
+
+struct Batch {
+    int64_t max_atoms = 0;
+    int max_structs = 0;
+    int rebuild_every = 10;
+    int next_handle = 1;
+    int batch_step = 0;
+    int cur = 0;             // position buffer the next launch reads
+    bool changed = true;     // segment table must be rebuilt
+    std::vector<Slot> slots; // ordered by atom offset
+    // Pinned staging for table uploads, used alternately; an event marks when
+    // the stream has consumed each, so uploads never stall the host on the
+    // kernels queued ahead of them.
+    void* stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage_k = 0;
+};
 }  // namespace
 
 struct mbmd_ctx {
@@ -36,12 +71,18 @@ struct mbmd_ctx {
     void* ws = nullptr;          // workspace base
     size_t ws_bytes = 0;
     bool ws_owned = false;
-    Buffers buf{};
-    int max_nn = kMaxSlots;      // largest list count of the last build
-    int fold_from = 0;           // first step whose thermo row is not folded yet
-    int fold_to = 0;             // one past the last step with pending partials
-    int64_t laid_n = -1;         // layout currently held by buf
-    int laid_M = 0;
+    Buffers buf{};               // layout of the workspace
+    int64_t laid_cap = -1;       // layout parameters currently held by buf
+    int laid_M = 0, laid_segs = 0;
+    bool laid_state = false;
+    int max_nn = kMaxSlots;      // largest list count over the segments of the next launch
+    std::vector<int> seg_max_nn; // per segment, from the last build launch
+    int pp = 0;                  // phase buffer read by the next pairwise launch
+    int fold_from = 0;           // single-structure thermo rows pending a fold
+    int fold_to = 0;
+    std::vector<Seg> segs_host;  // segment table of the current launch set
+    Segs segs{};
+    Batch* batch = nullptr;
     std::string err;
     bool profiling = false;
     std::vector<ProfRec> prof_pending;
@@ -61,17 +102,17 @@ struct ProfScope {
     hipEvent_t a = nullptr;
     ProfScope(mbmd_ctx* ctx, int k) : c(ctx), kind(k)
     {
-        if (c->profiling && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, c->stream);
+        if (c->profiling && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, c->stream);
     }
     ~ProfScope()
     {
         if (!a) return;
         hipEvent_t b = nullptr;
         if (hipEventCreate(&b) == hipSuccess) {
-            hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, c->stream);
             c->prof_pending.push_back(ProfRec{kind, a, b});
         } else {
-            hipEventDestroy(a);
+            (void)hipEventDestroy(a);
         }
     }
 };
@@ -85,15 +126,15 @@ void collect_profile(mbmd_ctx* c)
             c->prof_ms[r.kind] += ms;
             c->prof_launches[r.kind] += 1;
         }
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     c->prof_pending.clear();
 }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int64_t cell_cap(int64_t n) { return n * 4 > 64 ? n * 4 : 64; }
+int64_t cell_cap_for(int64_t cap, int segs) { return 4 * cap + 64 * (int64_t)segs; }
 
 int resolved_M(const mbmd_ctx* c)
 {
@@ -106,14 +147,15 @@ double cutoff_of(const mbmd_ctx* c)
     return c->potential == 1 ? c->sp.a * c->sp.sigma : c->tp.S;
 }
 
-// Lays out every device array for n atoms and M slots from `base` (or only
-// sizes it when base is null); returns the total byte count.
-size_t layout(int64_t n, int M, char* base, Buffers* b)
+// Lays out every device array for `cap` atoms, M slots and `segs` segments
+// from `base` (or only sizes it when base is null); `state` adds the batch's
+// own velocity and output arrays.  Returns the total byte count.
+size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
 {
-    const int64_t nn = n > 0 ? n : 1;
-    const int64_t ncap = cell_cap(nn);
-    const int64_t nscan = (ncap + kBlock * 4 - 1) / (kBlock * 4);
-    const int64_t nblk = blocks_for(nn);
+    const int64_t nn = cap > 0 ? cap : 1;
+    const int64_t ccap = cell_cap_for(nn, segs);
+    const int64_t nscan = (ccap + kBlock * 4 - 1) / (kBlock * 4);
+    const int64_t blk_cap = blocks_for(nn) + segs;
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? base + off : nullptr;
@@ -121,7 +163,7 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
         return p;
     };
     Buffers t{};
-    t.n = n;
+    t.cap = nn;
     t.M = M;
     t.xw[0] = (double4*)take(sizeof(double4) * nn);
     t.xw[1] = (double4*)take(sizeof(double4) * nn);
@@ -132,19 +174,32 @@ size_t layout(int64_t n, int M, char* base, Buffers* b)
     t.mask = (unsigned long long*)take(sizeof(unsigned long long) * nn);
     t.dpart = take(sizeof(double) * 3 * nn * M);
     t.cell_of = (int*)take(sizeof(int) * nn);
-    t.cell_count = (int*)take(sizeof(int) * ncap);
-    t.cell_start = (int*)take(sizeof(int) * (ncap + 1));
-    t.cell_fill = (int*)take(sizeof(int) * (ncap + 1 + nscan));
+    t.cell_cap = ccap;
+    t.cell_count = (int*)take(sizeof(int) * ccap);
+    t.cell_start = (int*)take(sizeof(int) * (ccap + 1));
+    t.cell_fill = (int*)take(sizeof(int) * (ccap + 1 + nscan));
     t.cell_atoms = (int*)take(sizeof(int) * nn);
-    t.part_b = (double*)take(sizeof(double) * kPartialCols * nblk * kThermoRing);
+    t.blk_cap = blk_cap;
+    t.part_b = (double*)take(sizeof(double) * kPartialCols * blk_cap * kThermoRing);
     t.ovf_count = (int*)take(sizeof(int));
     t.ovf_list = (int*)take(sizeof(int) * nn);
     t.status = (unsigned*)take(sizeof(unsigned));
-    t.thermo_scratch = (double*)take(sizeof(double) * kThermoCols);
     t.xsnap = (double4*)take(sizeof(double4) * nn);
     t.vsnap = (double*)take(sizeof(double) * 3 * nn);
     t.step_disp2 = (unsigned long long*)take(sizeof(unsigned long long) * kMaxChunk);
-    t.maxnn = (int*)take(sizeof(int));
+    t.maxnn = (int*)take(sizeof(int) * segs);
+    t.phase[0] = (int*)take(sizeof(int) * segs);
+    t.phase[1] = (int*)take(sizeof(int) * segs);
+    t.seg = (Seg*)take(sizeof(Seg) * segs);
+    t.seg_cap = segs;
+    if (state) {
+        t.vel = (double*)take(sizeof(double) * 3 * nn);
+        t.U = (double*)take(sizeof(double) * nn);
+        t.F = (double*)take(sizeof(double) * 3 * nn);
+        t.W = (double*)take(sizeof(double) * 9 * nn);
+        t.J = (double*)take(sizeof(double) * 3 * nn);
+        t.ostride = nn;
+    }
     if (b) *b = t;
     return off;
 }
@@ -165,16 +220,16 @@ mbmd_status hip_fail(mbmd_ctx* c, hipError_t e, const char* where)
     return MBMD_EDEVICE;
 }
 
-// Makes the workspace hold a layout for n atoms.
-mbmd_status ensure_workspace(mbmd_ctx* c, int64_t n)
+// Makes the workspace hold a layout for `cap` atoms and `segs` segments.
+mbmd_status ensure_workspace(mbmd_ctx* c, int64_t cap, int segs, bool state)
 {
     const int M = resolved_M(c);
-    const size_t need = layout(n, M, nullptr, nullptr);
+    const size_t need = layout(cap, M, segs, state, nullptr, nullptr);
     if (c->ws && !c->ws_owned) {
         if (c->ws_bytes < need)
             return fail(c, MBMD_ENOMEM, "bound workspace too small for this call%s");
     } else if (c->ws_bytes < need) {
-        if (c->ws) hipFree(c->ws);
+        if (c->ws) (void)hipFree(c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
         hipError_t e = hipMalloc(&c->ws, need);
@@ -185,10 +240,12 @@ mbmd_status ensure_workspace(mbmd_ctx* c, int64_t n)
         c->ws_bytes = need;
         c->ws_owned = true;
     }
-    if (c->laid_n != n || c->laid_M != M) {
-        layout(n, M, (char*)c->ws, &c->buf);
-        c->laid_n = n;
+    if (c->laid_cap != cap || c->laid_M != M || c->laid_segs != segs || c->laid_state != state) {
+        layout(cap, M, segs, state, (char*)c->ws, &c->buf);
+        c->laid_cap = cap;
         c->laid_M = M;
+        c->laid_segs = segs;
+        c->laid_state = state;
     }
     return MBMD_OK;
 }
@@ -206,12 +263,16 @@ mbmd_status check_box(mbmd_ctx* c, const double* box, Box* out)
     return MBMD_OK;
 }
 
-CellGrid make_grid(const Box& box, double rlist, int64_t n)
+// Segment record with its cell grid: cells of side >= r_list, at most
+// 4 n + 64 of them (larger cells are always correct).
+Seg make_seg(const Box& box, double rlist, int atom_off, int n, int nsteps, double mass,
+             double dt, double* thermo)
 {
-    CellGrid g{};
-    const int64_t cap = cell_cap(n > 0 ? n : 1);
+    Seg g{};
+    g.box = box;
+    const int64_t cap = 4 * (int64_t)n + 64;
     for (int a = 0; a < 3; ++a) {
-        int k = (int)std::floor(box.L[a] / (rlist * (1.0 + 1e-9)));
+        const int k = (int)std::floor(box.L[a] / (rlist * (1.0 + 1e-9)));
         g.nc[a] = k < 1 ? 1 : k;
     }
     while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cap) {
@@ -222,7 +283,51 @@ CellGrid make_grid(const Box& box, double rlist, int64_t n)
     }
     for (int a = 0; a < 3; ++a) g.inv_lc[a] = g.nc[a] / box.L[a];
     g.ncell = g.nc[0] * g.nc[1] * g.nc[2];
+    g.atom_off = atom_off;
+    g.n = n;
+    g.nsteps = nsteps;
+    if (mass > 0.0) {
+        g.half_dt_acc = 0.5 * dt * kKappa / mass;
+        g.dt = dt;
+        g.kin_scale = 0.5 * mass / kKappa;
+    }
+    g.thermo = thermo;
     return g;
+}
+
+// Assigns cell and block offsets in table order (host copy of the table).
+void assign_offsets(mbmd_ctx* c, int* total_cells)
+{
+    int cell = 0, blk = 0, blkq = 0;
+    for (Seg& g : c->segs_host) {
+        g.cell_off = cell;
+        g.blk = blk;
+        g.blk_quad = blkq;
+        cell += g.ncell;
+        blk += blocks_for(g.n);
+        blkq += quad_blocks_for(g.n);
+    }
+    if (total_cells) *total_cells = cell;
+    c->segs.seg = c->buf.seg;
+    c->segs.nseg = (int)c->segs_host.size();
+    c->segs.nblk = blk;
+    c->segs.nblk_quad = blkq;
+}
+
+// Assigns the offsets and uploads the table from the context's host copy
+// (which stays unchanged until the next call drains the stream).
+hipError_t upload_segs(mbmd_ctx* c, int* total_cells)
+{
+    assign_offsets(c, total_cells);
+    if (c->segs_host.empty()) return hipSuccess;
+    return hipMemcpyAsync(c->buf.seg, c->segs_host.data(), sizeof(Seg) * c->segs_host.size(),
+                          hipMemcpyHostToDevice, c->stream);
+}
+
+void set_phase_pointers(mbmd_ctx* c)
+{
+    c->segs.phase_in = c->buf.phase[c->pp];
+    c->segs.phase_out = c->buf.phase[c->pp ^ 1];
 }
 
 mbmd_status status_to_code(mbmd_ctx* c, unsigned st)
@@ -235,7 +340,7 @@ mbmd_status status_to_code(mbmd_ctx* c, unsigned st)
     return MBMD_OK;
 }
 
-// Reads the status word after draining the stream.
+// Reads (and clears) the status word after draining the stream.
 mbmd_status finish(mbmd_ctx* c)
 {
     unsigned st = 0;
@@ -243,45 +348,45 @@ mbmd_status finish(mbmd_ctx* c)
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
     collect_profile(c);
+    if (st) {
+        (void)launch_fill_int((int*)c->buf.status, 1, 0, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+    }
     return status_to_code(c, st);
 }
 
-// Stages positions, clears status and overflow counters, builds the list.
-mbmd_status begin(mbmd_ctx* c, int64_t n, const Box& box, const double* pos, const int32_t* types)
-{
-    mbmd_status s = ensure_workspace(c, n);
-    if (s != MBMD_OK) return s;
-    const Buffers& b = c->buf;
-    hipError_t e = launch_fill_int((int*)b.status, 1, 0, c->stream);
-    if (e == hipSuccess) e = launch_fill_int(b.ovf_count, 1, 0, c->stream);
-    if (e == hipSuccess) {
-        ProfScope ps(c, P_STAGE);
-        e = launch_load_positions(pos, types, n, box, b.xw[0], b.status, c->stream);
-    }
-    if (e != hipSuccess) return hip_fail(c, e, "staging positions");
-    return MBMD_OK;
-}
-
-// Builds the list and reads back its largest count (one stream sync per
-// build), which decides whether the partials overflow pass is needed.
-hipError_t build(mbmd_ctx* c, int cur, const Box& box)
+// Builds the lists of every segment flagged in the table.  With `readback`
+// the largest count per segment is read back (one stream sync per build) and
+// c->max_nn, the largest over the built segments, decides whether the
+// partials overflow pass is needed; without it the overflow pass is always
+// enqueued (it exits at once when no atom overflowed).
+hipError_t build(mbmd_ctx* c, int total_cells, int cur, bool readback = true)
 {
     hipError_t e;
     {
         ProfScope ps(c, P_BUILD);
-        const double rl = cutoff_of(c) + c->skin;
-        e = launch_build_neighbors(c->buf, cur, box, make_grid(box, rl, c->buf.n), rl, c->stream);
+        e = launch_build_neighbors(c->buf, c->segs, total_cells, cur, cutoff_of(c) + c->skin,
+                                   c->stream);
     }
-    int mx = kMaxSlots;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&mx, c->buf.maxnn, sizeof mx, hipMemcpyDeviceToHost, c->stream);
+    if (!readback) {
+        c->max_nn = kMaxSlots;
+        return e;
+    }
+    const int ns = c->segs.nseg;
+    c->seg_max_nn.assign(ns > 0 ? ns : 1, kMaxSlots);
+    if (e == hipSuccess && ns > 0)
+        e = hipMemcpyAsync(c->seg_max_nn.data(), c->buf.maxnn, sizeof(int) * ns,
+                           hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    c->max_nn = mx;
+    int mx = 0;
+    for (int k = 0; k < ns; ++k)
+        if (c->segs_host[k].build) mx = std::max(mx, c->seg_max_nn[k]);
+    c->max_nn = e == hipSuccess ? mx : kMaxSlots;
     return e;
 }
 
 template <class T>
-hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
+hipError_t partials(mbmd_ctx* c, int cur)
 {
     hipError_t e;
     for (int pass = 0; pass < 2; ++pass) {
@@ -289,68 +394,112 @@ hipError_t partials(mbmd_ctx* c, int cur, const Box& box, double* U)
         if (pass == 1 && !(c->buf.M > kSiteFastBonds && c->max_nn > kSiteFastBonds)) break;
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)
-            e = launch_sw_partials<T>(c->buf, cur, box, c->sp, U, pass == 1, c->max_nn, c->stream);
+            e = launch_sw_partials<T>(c->buf, c->segs, cur, c->sp, pass == 1, c->max_nn,
+                                      c->stream);
         else
-            e = launch_tersoff_partials<T>(c->buf, cur, box, c->tp, U, pass == 1, c->max_nn,
+            e = launch_tersoff_partials<T>(c->buf, c->segs, cur, c->tp, pass == 1, c->max_nn,
                                            c->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// Force evaluation at the positions of buffer `cur` and the pairwise pass
+// (integrator per segment phase); flips the phase buffers.
 template <class T>
-hipError_t gather(mbmd_ctx* c, const Box& box, const StepArgs& a, const double* U, double* vel,
-                  double* F, double* W, double* J)
+hipError_t force_step(mbmd_ctx* c, int cur, bool check, unsigned long long* slot,
+                      double* part_row)
 {
-    ProfScope ps(c, P_GATHER);
-    return launch_pair_gather<T>(c->buf, box, a, U, vel, F, W, J, c->stream);
+    // the site pass reads the phases too: point both passes at this step's
+    set_phase_pointers(c);
+    hipError_t e = partials<T>(c, cur);
+    StepArgs a{};
+    a.cur = cur;
+    a.check_skin = check;
+    a.skin_half2 = 0.25 * c->skin * c->skin;
+    a.disp_slot = slot;
+    a.part_row = part_row;
+    if (e == hipSuccess) {
+        ProfScope ps(c, P_GATHER);
+        e = launch_pair_gather<T>(c->buf, c->segs, a, c->stream);
+    }
+    c->pp ^= 1;
+    return e;
 }
 
+double* ring_row(mbmd_ctx* c, int row)
+{
+    return c->buf.part_b + (size_t)(row % kThermoRing) * c->buf.blk_cap * kPartialCols;
+}
+
+// ---- one structure ----------------------------------------------------------
+
+// Sets up a one-segment launch set over caller-owned arrays and stages the
+// positions into buffer 0.
+mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
+                         const int32_t* types, int nsteps, double mass, double dt, double* vel,
+                         double* U, double* F, double* W, double* J, int* total_cells)
+{
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
+    mbmd_status s = ensure_workspace(c, n, 1, false);
+    if (s != MBMD_OK) return s;
+    Buffers& b = c->buf;
+    b.vel = vel;
+    b.U = U;
+    b.F = F;
+    b.W = W;
+    b.J = J;
+    b.ostride = n;
+    Seg g = make_seg(box, cutoff_of(c) + c->skin, 0, (int)n, nsteps, mass, dt, nullptr);
+    g.build = 1;
+    c->segs_host.assign(1, g);
+    c->pp = 0;
+    hipError_t e = upload_segs(c, total_cells);
+    if (e == hipSuccess) e = launch_fill_int((int*)b.status, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(b.ovf_count, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(b.phase[0], 1, 0, c->stream);
+    if (e == hipSuccess) {
+        ProfScope ps(c, P_STAGE);
+        e = launch_load_positions(pos, types, n, box, 0, b.xw[0], b.status, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "staging positions");
+    return MBMD_OK;
+}
 
 template <class T>
 mbmd_status compute_impl(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
                          const double* vel, const int32_t* types, double* U, double* F,
                          double* W, double* J)
 {
-    mbmd_status s = begin(c, n, box, pos, types);
+    int cells = 0;
+    mbmd_status s = begin_single(c, n, box, pos, types, 0, 0.0, 0.0, const_cast<double*>(vel),
+                                 U, F, W, J, &cells);
     if (s != MBMD_OK) return s;
-    hipError_t e = build(c, 0, box);
-    if (e == hipSuccess) e = partials<T>(c, 0, box, U);
-    StepArgs a{};
-    a.cur = 0;
-    if (e == hipSuccess) e = gather<T>(c, box, a, U, const_cast<double*>(vel), F, W, J);
+    hipError_t e = build(c, cells, 0);
+    if (e == hipSuccess) e = force_step<T>(c, 0, false, nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "compute launch");
     return finish(c);
 }
 
-// Folds the pending per-step partials into thermo rows.
+// Folds the pending per-step partials of the single structure.
 hipError_t flush_thermo(mbmd_ctx* c, double* thermo)
 {
     if (!thermo || c->fold_to <= c->fold_from) return hipSuccess;
     ProfScope ps(c, P_THERMO);
-    hipError_t e = launch_thermo_fold(c->buf, c->fold_from, c->fold_to - c->fold_from, thermo,
-                                      c->stream);
+    hipError_t e = launch_thermo_fold(c->buf, c->segs, 0, c->fold_from, c->fold_to - c->fold_from,
+                                      0, thermo, c->stream);
     c->fold_from = c->fold_to;
     return e;
 }
 
-// One MD step: force evaluation at the current positions, second half-kick,
-// heat current and thermo row, then (unless last) first half-kick and drift.
+// One MD step of the single structure: force evaluation at the current
+// positions, second half-kick, heat current and thermo partials, then
+// (unless last) first half-kick and drift.
 template <class T>
-hipError_t md_step(mbmd_ctx* c, const Box& box, StepArgs& a, int step, int n_steps, int cur,
-                   bool check, unsigned long long* slot, double* U, double* vel, double* F,
-                   double* W, double* J, double* thermo)
+hipError_t md_step(mbmd_ctx* c, int step, int cur, bool check, unsigned long long* slot,
+                   double* thermo)
 {
-    hipError_t e = partials<T>(c, cur, box, U);
-    a.cur = cur;
-    a.kick_before = step > 0;
-    a.advance = step < n_steps;
-    a.check_skin = a.advance && check;
-    a.disp_slot = slot;
-    a.part_row = thermo ? c->buf.part_b + (size_t)(step % kThermoRing) * blocks_for(c->buf.n) *
-                                              kPartialCols
-                        : nullptr;
-    if (e == hipSuccess) e = gather<T>(c, box, a, U, vel, F, W, J);
+    hipError_t e = force_step<T>(c, cur, check, slot, thermo ? ring_row(c, step) : nullptr);
     if (e == hipSuccess && thermo) {
         if (step < c->fold_from || step > c->fold_to) c->fold_from = step;   // replayed steps
         c->fold_to = step + 1;
@@ -364,20 +513,16 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
                      double* vel, const int32_t* types, double dt, int n_steps, int every,
                      double* U, double* F, double* W, double* J, double* thermo)
 {
-    mbmd_status s = begin(c, n, box, pos, types);
+    int cells = 0;
+    mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
+                                 &cells);
     if (s != MBMD_OK) return s;
     const Buffers& b = c->buf;
-    const double kappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
-    StepArgs a{};
-    a.half_dt_acc = 0.5 * dt * kappa / mass;
-    a.dt = dt;
-    a.skin_half2 = 0.25 * c->skin * c->skin;
-    a.kin_scale = 0.5 * mass / kappa;
     mbmd_run_stats st{};
     st.steps = n_steps;
     c->fold_from = c->fold_to = 0;
     int cur = 0, last_build = 0;
-    hipError_t e = build(c, cur, box);
+    hipError_t e = build(c, cells, cur);
     st.rebuilds = 1;
 
     if (c->policy == MBMD_REBUILD_FIXED) {
@@ -385,16 +530,15 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         // displacement is tracked (the statistics report -1).
         for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
             if (step - last_build == every) {
-                e = build(c, cur, box);
+                e = build(c, cells, cur);
                 last_build = step;
                 ++st.rebuilds;
             }
-            if (e != hipSuccess) break;
-            e = md_step<T>(c, box, a, step, n_steps, cur, false, nullptr, U, vel, F, W, J, thermo);
-            if (step < n_steps) cur ^= 1;
+            if (e == hipSuccess) e = md_step<T>(c, step, cur, false, nullptr, thermo);
+            cur ^= 1;
         }
         if (e == hipSuccess) e = flush_thermo(c, thermo);
-        if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
+        if (e == hipSuccess) e = launch_store_positions(b.xw[cur], 0, n, pos, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "nve launch");
         s = finish(c);
         st.max_displacement = -1.0;
@@ -407,6 +551,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     // back.  If the positions of some step moved more than skin/2 from the
     // last build, the chunk is replayed from the snapshot (bit-identically)
     // up to that step and the list is rebuilt there.
+    const double skin_half2 = 0.25 * c->skin * c->skin;
     int step = 0;
     int chunk = every < kMaxChunk ? every : kMaxChunk;
     std::vector<unsigned long long> disp(kMaxChunk);
@@ -426,10 +571,9 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         if (e == hipSuccess) e = launch_fill_int((int*)b.step_disp2, 2 * len, 0, c->stream);
         for (int k = 0; k < len && e == hipSuccess; ++k) {
             const int sk = cs + k;
-            const bool check = (sk + 1 - last_build) != every;
-            e = md_step<T>(c, box, a, sk, n_steps, cur, check, b.step_disp2 + k, U, vel, F, W, J,
-                           thermo);
-            if (sk < n_steps) cur ^= 1;
+            const bool check = sk < n_steps && (sk + 1 - last_build) != every;
+            e = md_step<T>(c, sk, cur, check, b.step_disp2 + k, thermo);
+            cur ^= 1;
         }
         if (e == hipSuccess) e = flush_thermo(c, thermo);
         if (e == hipSuccess)
@@ -441,7 +585,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         for (int k = 0; k < len; ++k) {
             double d2;
             std::memcpy(&d2, &disp[k], sizeof d2);
-            if (d2 > a.skin_half2) {
+            if (d2 > skin_half2) {
                 bad = cs + k + 1;
                 break;
             }
@@ -450,7 +594,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         if (bad < 0) {
             step = cend;
             if (step <= n_steps && step - last_build == every) {
-                e = build(c, cur, box);
+                e = build(c, cells, cur);
                 last_build = step;
                 ++st.rebuilds;
             }
@@ -463,11 +607,12 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         if (e == hipSuccess)
             e = hipMemcpyAsync(vel, b.vsnap, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice,
                                c->stream);
+        if (e == hipSuccess) e = launch_fill_int(b.phase[c->pp], 1, cs, c->stream);
         for (int sk = cs; sk < bad && e == hipSuccess; ++sk) {
-            e = md_step<T>(c, box, a, sk, n_steps, cur, false, nullptr, U, vel, F, W, J, thermo);
-            if (sk < n_steps) cur ^= 1;
+            e = md_step<T>(c, sk, cur, false, nullptr, thermo);
+            cur ^= 1;
         }
-        if (e == hipSuccess) e = build(c, cur, box);
+        if (e == hipSuccess) e = build(c, cells, cur);
         last_build = bad;
         step = bad;
         ++st.rebuilds;
@@ -475,7 +620,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         chunk = bad - cs > 0 ? bad - cs : 1;
     }
     if (e == hipSuccess) e = flush_thermo(c, thermo);
-    if (e == hipSuccess) e = launch_store_positions(b.xw[cur], n, pos, c->stream);
+    if (e == hipSuccess) e = launch_store_positions(b.xw[cur], 0, n, pos, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "nve launch");
     s = finish(c);
     st.max_displacement = std::sqrt(committed_max2);
@@ -490,6 +635,134 @@ mbmd_status common_checks(mbmd_ctx* c, int64_t n, const double* box, Box* b)
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     return check_box(c, box, b);
+}
+
+// ---- serving batch -----------------------------------------------------------
+
+// First free atom range of length n in [0, max_atoms), or -1.
+int64_t find_range(const Batch& B, int64_t n)
+{
+    int64_t at = 0;
+    for (const Slot& s : B.slots) {
+        if (s.atom_off - at >= n) return at;
+        at = s.atom_off + s.n;
+    }
+    return B.max_atoms - at >= n ? at : -1;
+}
+
+Slot* find_slot(Batch& B, int handle)
+{
+    for (Slot& s : B.slots)
+        if (s.handle == handle) return &s;
+    return nullptr;
+}
+
+// Segment table of the batch in atom order with this step's build flags; the
+// phase of each segment (its slot's step counter, nsteps + 1 once finished)
+// goes into the phase buffer the next launch reads.  Both are staged in
+// pinned memory and copied asynchronously.
+hipError_t batch_table(mbmd_ctx* c, int* total_cells, bool* any_build)
+{
+    Batch& B = *c->batch;
+    c->segs_host.clear();
+    const double rl = cutoff_of(c) + c->skin;
+    *any_build = false;
+    for (const Slot& s : B.slots) {
+        Seg g = make_seg(s.box, rl, s.atom_off, s.n, s.nsteps, s.mass, s.dt, s.thermo);
+        g.build = !s.done && (s.last_build < 0 || s.step - s.last_build >= B.rebuild_every);
+        *any_build = *any_build || g.build;
+        c->segs_host.push_back(g);
+    }
+    assign_offsets(c, total_cells);
+    const size_t ns = B.slots.size();
+    if (ns == 0) return hipSuccess;
+    const int k = B.stage_k;
+    B.stage_k ^= 1;
+    // the copy issued from this staging buffer two uploads ago has completed
+    hipError_t e = hipEventSynchronize(B.stage_ev[k]);
+    if (e != hipSuccess) return e;
+    Seg* hs = static_cast<Seg*>(B.stage[k]);
+    int* hp = reinterpret_cast<int*>(hs + B.max_structs);
+    for (size_t q = 0; q < ns; ++q) {
+        hs[q] = c->segs_host[q];
+        hp[q] = B.slots[q].done ? B.slots[q].nsteps + 1 : B.slots[q].step;
+    }
+    e = hipMemcpyAsync(c->buf.seg, hs, sizeof(Seg) * ns, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->buf.phase[c->pp], hp, sizeof(int) * ns, hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipEventRecord(B.stage_ev[k], c->stream);
+    return e;
+}
+
+size_t batch_stage_bytes(int max_structs) { return (sizeof(Seg) + sizeof(int)) * max_structs; }
+
+void free_batch(mbmd_ctx* c)
+{
+    Batch* B = c->batch;
+    if (!B) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (B->stage_ev[k]) (void)hipEventDestroy(B->stage_ev[k]);
+        if (B->stage[k]) (void)hipHostFree(B->stage[k]);
+    }
+    delete B;
+    c->batch = nullptr;
+}
+
+template <class T>
+mbmd_status batch_step_impl(mbmd_ctx* c, int* n_active)
+{
+    Batch& B = *c->batch;
+    int active = 0;
+    bool due = false;
+    for (const Slot& s : B.slots) {
+        if (s.done) continue;
+        ++active;
+        if (s.last_build < 0 || s.step - s.last_build >= B.rebuild_every) due = true;
+    }
+    if (n_active) *n_active = active;
+    if (active == 0) return MBMD_OK;
+    hipError_t e = hipSuccess;
+    int cells = 0;
+    bool any_build = false;
+    if (B.changed || due) {
+        e = batch_table(c, &cells, &any_build);
+        B.changed = false;
+    }
+    if (e == hipSuccess && any_build) {
+        // the table was rebuilt just above, so it lists the slots in order
+        e = build(c, cells, B.cur, false);
+        for (size_t k = 0; k < B.slots.size(); ++k)
+            if (c->segs_host[k].build) B.slots[k].last_build = B.slots[k].step;
+        // the table keeps its build flags until the next rebuild of it; make
+        // sure a later step does not rebuild anything unintended
+        B.changed = true;
+    }
+    // no list counts are read back in the batch: the overflow pass is always
+    // enqueued
+    c->max_nn = kMaxSlots;
+    const int row = B.batch_step % kThermoRing;
+    if (e == hipSuccess) e = force_step<T>(c, B.cur, false, nullptr, ring_row(c, row));
+    if (e == hipSuccess) {
+        // the fold reads the phase buffer the pairwise launch read
+        ProfScope ps(c, P_THERMO);
+        Segs S = c->segs;
+        S.phase_in = c->buf.phase[c->pp ^ 1];
+        e = launch_thermo_fold_segments(c->buf, S, row, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "batch step");
+    B.cur ^= 1;
+    ++B.batch_step;
+    for (Slot& s : B.slots) {
+        if (s.done) continue;
+        if (s.step == s.nsteps) {
+            s.done = true;
+            s.final_buf = B.cur;
+        }
+        ++s.step;
+    }
+    return MBMD_OK;
 }
 
 }  // namespace
@@ -516,13 +789,14 @@ void mbmd_destroy(mbmd_ctx* c)
 {
     if (!c) return;
     for (const ProfRec& r : c->prof_pending) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     if (c->ws && c->ws_owned) {
-        hipSetDevice(c->device);
-        hipFree(c->ws);
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->ws);
     }
+    free_batch(c);
     delete c;
 }
 
@@ -531,6 +805,7 @@ const char* mbmd_last_error(const mbmd_ctx* c) { return c ? c->err.c_str() : "nu
 mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
 {
     if (!c || !p) return MBMD_EINVAL;
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     const double v[] = {p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
     for (double x : v)
         if (!std::isfinite(x)) return fail(c, MBMD_EINVAL, "non-finite Tersoff parameter%s");
@@ -538,13 +813,14 @@ mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
         return fail(c, MBMD_EINVAL, "Tersoff parameters need 0 < R < S, n > 0, beta > 0, d != 0%s");
     c->tp = TersoffParams{p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
     c->potential = 0;
-    c->laid_n = -1;
+    c->laid_cap = -1;
     return MBMD_OK;
 }
 
 mbmd_status mbmd_set_sw(mbmd_ctx* c, const mbmd_sw_params* p)
 {
     if (!c || !p) return MBMD_EINVAL;
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     const double v[] = {p->epsilon, p->sigma, p->a, p->lambda, p->gamma, p->A, p->B, p->p, p->q};
     for (double x : v)
         if (!std::isfinite(x)) return fail(c, MBMD_EINVAL, "non-finite SW parameter%s");
@@ -552,19 +828,20 @@ mbmd_status mbmd_set_sw(mbmd_ctx* c, const mbmd_sw_params* p)
         return fail(c, MBMD_EINVAL, "SW parameters need sigma > 0 and a > 0%s");
     c->sp = SWParams{p->epsilon, p->sigma, p->a, p->lambda, p->gamma, p->A, p->B, p->p, p->q};
     c->potential = 1;
-    c->laid_n = -1;
+    c->laid_cap = -1;
     return MBMD_OK;
 }
 
 mbmd_status mbmd_set_neighbor(mbmd_ctx* c, double skin, int max_neighbors)
 {
     if (!c) return MBMD_EINVAL;
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (!std::isfinite(skin) || skin < 0.0) return fail(c, MBMD_EINVAL, "skin must be >= 0%s");
     if (max_neighbors < 0 || max_neighbors > kMaxSlots)
         return fail(c, MBMD_EINVAL, "max_neighbors must be in 0..64%s");
     c->skin = skin;
     c->max_nb = max_neighbors;
-    c->laid_n = -1;
+    c->laid_cap = -1;
     return MBMD_OK;
 }
 
@@ -624,23 +901,32 @@ mbmd_status mbmd_get_max_neighbors(const mbmd_ctx* c, int* out)
 mbmd_status mbmd_workspace_size(const mbmd_ctx* c, int64_t n_atoms, size_t* bytes)
 {
     if (!c || !bytes || n_atoms < 0) return MBMD_EINVAL;
-    *bytes = layout(n_atoms, resolved_M(c), nullptr, nullptr);
+    *bytes = layout(n_atoms, resolved_M(c), 1, false, nullptr, nullptr);
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_workspace_size(const mbmd_ctx* c, int64_t max_atoms, int max_structures,
+                                      size_t* bytes)
+{
+    if (!c || !bytes || max_atoms < 1 || max_structures < 1) return MBMD_EINVAL;
+    *bytes = layout(max_atoms, resolved_M(c), max_structures, true, nullptr, nullptr);
     return MBMD_OK;
 }
 
 mbmd_status mbmd_bind_workspace(mbmd_ctx* c, void* dev_ptr, size_t bytes)
 {
     if (!c) return MBMD_EINVAL;
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (dev_ptr && ((uintptr_t)dev_ptr % kAlign) != 0)
         return fail(c, MBMD_EINVAL, "workspace must be 256-byte aligned%s");
     if (c->ws && c->ws_owned) {
-        hipSetDevice(c->device);
-        hipFree(c->ws);
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->ws);
     }
     c->ws = dev_ptr;
     c->ws_bytes = dev_ptr ? bytes : 0;
     c->ws_owned = false;
-    c->laid_n = -1;
+    c->laid_cap = -1;
     return MBMD_OK;
 }
 
@@ -653,9 +939,11 @@ mbmd_status mbmd_neighbors(mbmd_ctx* c, int64_t n, const double box[3], const do
     if (s != MBMD_OK) return s;
     if (n == 0) return MBMD_OK;
     if (!pos || !nn || !nl) return fail(c, MBMD_EINVAL, "null device pointer%s");
-    s = begin(c, n, b, pos, nullptr);
+    int cells = 0;
+    s = begin_single(c, n, b, pos, nullptr, 0, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, &cells);
     if (s != MBMD_OK) return s;
-    hipError_t e = build(c, 0, b);
+    hipError_t e = build(c, cells, 0);
     const int M = c->buf.M;
     if (e == hipSuccess)
         e = hipMemcpyAsync(nn, c->buf.nn, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream);
@@ -701,6 +989,169 @@ mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const doub
                                U, F, W, J, thermo);
     return nve_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every, U,
                             F, W, J, thermo);
+}
+
+// ---- serving batch ----------------------------------------------------------
+
+mbmd_status mbmd_batch_open(mbmd_ctx* c, int64_t max_atoms, int max_structures,
+                            int rebuild_every)
+{
+    if (!c) return MBMD_EINVAL;
+    if (c->potential < 0) return fail(c, MBMD_ENOPOT, "no potential set%s");
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is already open%s");
+    if (max_atoms < 1 || max_atoms > (int64_t)0x3fffffff || max_structures < 1 ||
+        max_structures > (1 << 20) || rebuild_every < 1)
+        return fail(c, MBMD_EINVAL,
+                    "need max_atoms >= 1, max_structures >= 1, rebuild_every >= 1%s");
+    hipError_t he = hipSetDevice(c->device);
+    if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+    mbmd_status s = ensure_workspace(c, max_atoms, max_structures, true);
+    if (s != MBMD_OK) return s;
+    Batch* B = new (std::nothrow) Batch();
+    if (!B) return MBMD_ENOMEM;
+    B->max_atoms = max_atoms;
+    B->max_structs = max_structures;
+    B->rebuild_every = rebuild_every;
+    c->batch = B;
+    for (int k = 0; k < 2; ++k) {
+        if (hipHostMalloc(&B->stage[k], batch_stage_bytes(max_structures)) != hipSuccess) {
+            B->stage[k] = nullptr;
+            free_batch(c);
+            return fail(c, MBMD_ENOMEM, "pinned staging for the batch table%s");
+        }
+        if (hipEventCreateWithFlags(&B->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
+            B->stage_ev[k] = nullptr;
+            free_batch(c);
+            return fail(c, MBMD_EDEVICE, "event for the batch table%s");
+        }
+    }
+    c->pp = 0;
+    hipError_t e = launch_fill_int((int*)c->buf.status, 1, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill_int(c->buf.ovf_count, 1, 0, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batch open");
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_close(mbmd_ctx* c)
+{
+    if (!c) return MBMD_EINVAL;
+    free_batch(c);
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_capacity(const mbmd_ctx* c, int64_t* free_atoms, int* free_slots,
+                                int64_t* largest_range)
+{
+    if (!c || !c->batch) return MBMD_EINVAL;
+    const Batch& B = *c->batch;
+    int64_t used = 0, largest = 0, at = 0;
+    for (const Slot& s : B.slots) {
+        used += s.n;
+        largest = std::max<int64_t>(largest, s.atom_off - at);
+        at = s.atom_off + s.n;
+    }
+    largest = std::max<int64_t>(largest, B.max_atoms - at);
+    if (free_atoms) *free_atoms = B.max_atoms - used;
+    if (free_slots) *free_slots = B.max_structs - (int)B.slots.size();
+    if (largest_range) *largest_range = largest;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_add(mbmd_ctx* c, int64_t n, const double box[3], const double* pos,
+                           const double* vel, double mass_amu, double dt_fs, int n_steps,
+                           double* thermo, int* handle)
+{
+    if (!c || !handle) return MBMD_EINVAL;
+    if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
+    Batch& B = *c->batch;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (n < 1 || !pos || !vel) return fail(c, MBMD_EINVAL, "need n >= 1 and device pos, vel%s");
+    if (!std::isfinite(mass_amu) || !(mass_amu > 0.0) || !std::isfinite(dt_fs) || n_steps < 0)
+        return fail(c, MBMD_EINVAL, "need mass > 0, finite dt, n_steps >= 0%s");
+    if ((int)B.slots.size() >= B.max_structs) return fail(c, MBMD_EBUSY, "no free structure slot%s");
+    const int64_t at = find_range(B, n);
+    if (at < 0) return fail(c, MBMD_EBUSY, "no free atom range of this size%s");
+    Slot sl;
+    sl.handle = B.next_handle++;
+    sl.atom_off = (int)at;
+    sl.n = (int)n;
+    sl.box = b;
+    sl.nsteps = n_steps;
+    sl.mass = mass_amu;
+    sl.dt = dt_fs;
+    sl.thermo = thermo;
+    // positions into the buffer the next launch reads, velocities into the
+    // batch state
+    hipError_t e = launch_load_positions(pos, nullptr, n, b, (int)at, c->buf.xw[B.cur],
+                                         c->buf.status, c->stream);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r)
+        e = hipMemcpyAsync(c->buf.vel + r * c->buf.ostride + at, vel + r * n, sizeof(double) * n,
+                           hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batch add");
+    auto it = std::lower_bound(B.slots.begin(), B.slots.end(), (int)at,
+                               [](const Slot& x, int off) { return x.atom_off < off; });
+    B.slots.insert(it, sl);
+    B.changed = true;
+    *handle = sl.handle;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_step(mbmd_ctx* c, mbmd_precision prec, int* n_active)
+{
+    if (!c) return MBMD_EINVAL;
+    if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
+    if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if (prec == MBMD_MIXED) return batch_step_impl<float>(c, n_active);
+    return batch_step_impl<double>(c, n_active);
+}
+
+mbmd_status mbmd_batch_finished(const mbmd_ctx* c, int* handles, int capacity, int* count)
+{
+    if (!c || !c->batch || !count || capacity < 0 || (capacity > 0 && !handles))
+        return MBMD_EINVAL;
+    int k = 0;
+    for (const Slot& s : c->batch->slots) {
+        if (!s.done) continue;
+        if (k < capacity) handles[k] = s.handle;
+        ++k;
+    }
+    *count = k;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_retire(mbmd_ctx* c, int handle, double* pos, double* vel, double* U,
+                              double* F, double* W, double* J)
+{
+    if (!c) return MBMD_EINVAL;
+    if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
+    Batch& B = *c->batch;
+    Slot* sl = find_slot(B, handle);
+    if (!sl) return fail(c, MBMD_EINVAL, "unknown structure handle%s");
+    if (!sl->done) return fail(c, MBMD_EBUSY, "structure has not finished%s");
+    const Buffers& b = c->buf;
+    const int64_t os = b.ostride, at = sl->atom_off, n = sl->n;
+    hipError_t e = hipSetDevice(c->device);
+    auto rows = [&](double* dst, const double* src, int nr) {
+        for (int r = 0; r < nr && e == hipSuccess; ++r)
+            e = hipMemcpyAsync(dst + r * n, src + r * os + at, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, c->stream);
+    };
+    if (pos && e == hipSuccess) e = launch_store_positions(b.xw[sl->final_buf], (int)at, n, pos,
+                                                           c->stream);
+    if (vel) rows(vel, b.vel, 3);
+    if (U) rows(U, b.U, 1);
+    if (F) rows(F, b.F, 3);
+    if (W) rows(W, b.W, 9);
+    if (J) rows(J, b.J, 3);
+    if (e != hipSuccess) return hip_fail(c, e, "batch retire");
+    B.slots.erase(B.slots.begin() + (sl - B.slots.data()));
+    B.changed = true;
+    return finish(c);
 }
 
 }  // extern "C"

@@ -1,15 +1,25 @@
 // Internal declarations shared by the HIP translation units of libmbmd.
 //
-// Data layout in device memory (N atoms, M list slots per atom):
-//   xw[N]            double4 {x, y, z, 0}: wrapped positions, atom-major so a
-//                    neighbour gather is one 32-byte access
+// Every kernel works on a set of segments: independent periodic structures
+// (one for a plain call, many for the serving batch) whose atoms occupy
+// contiguous ranges of the same device arrays.  A block never straddles two
+// segments: a segment owns a contiguous range of blocks, found from the block
+// index by binary search over the segment table, so everything a block
+// reduces belongs to one structure and is summed in the same order whatever
+// else shares the launch.
+//
+// Data layout in device memory (N atom capacity, M list slots per atom):
+//   xw[2][N]         double4 {x, y, z, 0}: wrapped positions, atom-major
+//                    so a neighbour gather is one 32-byte access; two buffers
+//                    because the drift writes while neighbours are still read
+//   xbuild[N]        double4 positions at the last list build
 //   nn[N]            int32 list count (true count, may exceed M on overflow)
 //   nl[M][N]         int32 neighbour index, slot-major (lane i reads nl[m*N+i]
 //                    coalesced), ascending index within each atom
 //   rev[M][N]        int32 slot of i inside the list of nl[m][i]
 //   mask[N]          uint64 bit m set iff slot m lies inside the potential cutoff
 //   dpart[M][N][3]   T: dU_i/dr_ij for list slot m (written for in-cutoff slots only)
-//   outputs          FP64 SoA: U[N], F[3][N], W[9][N] (component 3a+b), J[3][N]
+//   U[N], F[3][N], W[9][N] (component 3a+b), J[3][N], v[3][N]: FP64 SoA
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +36,7 @@ enum : unsigned {
 };
 
 constexpr int kBlock = 256;          // threads per block of every per-atom kernel
+constexpr int kQuadAtoms = 64;       // atoms per block of the four-lanes-per-atom kernels
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
 constexpr int kSiteFastBonds = 8;    // in-cutoff bonds a site pass handles without overflow
 constexpr int kThermoCols = 16;      // per-step thermo row
@@ -38,12 +49,53 @@ struct Box {
     double inv[3];
 };
 
-// Fixed per-call geometry of the cell grid.
-struct CellGrid {
-    int nc[3];
+// One structure of a launch.
+struct Seg {
+    Box box;
+    int nc[3];              // cell grid
     double inv_lc[3];
-    int ncell;
+    int cell_off, ncell;    // cells [cell_off, cell_off + ncell) of the cell arrays
+    int atom_off, n;        // atoms [atom_off, atom_off + n)
+    int blk, blk_quad;      // first block for 256-atom and 64-atom blocks
+    int nsteps;             // steps of its run (0: a single force evaluation)
+    int build;              // nonzero: its list is (re)built by the next build launch
+    double half_dt_acc;     // dt/2 kappa/m
+    double dt;
+    double kin_scale;       // m / (2 kappa)
+    double* thermo;         // batch: [nsteps + 1][16] thermo rows of this structure, or null
 };
+
+// Device view of the segment table.
+struct Segs {
+    const Seg* seg;
+    int nseg;
+    int nblk, nblk_quad;    // total blocks of each kind
+    const int* phase_in;    // per segment: index of the step being computed
+    int* phase_out;         // receives phase_in + 1 (written by the pairwise pass)
+};
+
+// Segment owning logical block b (field blk or blk_quad), by binary search.
+__device__ __forceinline__ int seg_of_block(const Segs& S, int b, bool quad)
+{
+    int lo = 0, hi = S.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int start = quad ? S.seg[mid].blk_quad : S.seg[mid].blk;
+        if (start <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Segment holding global atom i, by binary search over the atom offsets.
+__device__ __forceinline__ int seg_of_atom(const Segs& S, int64_t i)
+{
+    int lo = 0, hi = S.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.seg[mid].atom_off <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 struct TersoffParams {                // the 1989 single-element form
     double A, B, lam, mu, beta, n, c, d, h, R, S;
@@ -54,7 +106,7 @@ struct SWParams {                     // the 1985 form
 
 // Workspace view passed to the launchers.
 struct Buffers {
-    int64_t n;
+    int64_t cap;             // atom capacity (array length N)
     int M;
     double4* xw[2];
     double4* xbuild;
@@ -68,15 +120,22 @@ struct Buffers {
     int* cell_start;
     int* cell_fill;
     int* cell_atoms;
-    double* part_b;          // [kThermoRing][nblocks][kPartialCols]
-    int* ovf_count;          // atoms whose in-cutoff count exceeds the register tile
+    int64_t cell_cap;
+    double* part_b;          // [kThermoRing][block capacity][kPartialCols]
+    int64_t blk_cap;         // 256-atom block capacity
+    int* ovf_count;          // atoms whose in-cutoff count exceeds the fast path
     int* ovf_list;           // [N]
     unsigned* status;
-    double* thermo_scratch;  // [kThermoCols]
     double4* xsnap;          // [N] positions at the start of a checked chunk
     double* vsnap;           // [3][N] velocities at the start of a checked chunk
     unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
-    int* maxnn;                      // largest list count of the last build
+    int* maxnn;              // [segments] largest list count of the last build
+    int* phase[2];           // per segment step index (double-buffered)
+    Seg* seg;                // segment table
+    int seg_cap;
+    double* vel;             // velocities [3][ostride]
+    double *U, *F, *W, *J;   // per-atom outputs: U[ostride], F[3][..], W[9][..], J[3][..]
+    int64_t ostride;         // row stride of vel, F, W, J (cap for the batch state)
 };
 
 // Mapping of a hardware block index to a logical block so that each XCD
@@ -89,48 +148,65 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x < r ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
 }
 
-inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+// Host-side check of a launch's segment view: every pointer a kernel
+// dereferences unconditionally is set and the table fits the workspace.
+inline bool segs_ready(const Segs& S, const Buffers& b)
+{
+    return S.seg && S.phase_in && S.phase_out && S.nseg >= 1 && S.nseg <= b.seg_cap &&
+           S.nblk <= b.blk_cap;
+}
+
+__host__ __device__ inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+__host__ __device__ inline int quad_blocks_for(int64_t n) { return (int)((n + kQuadAtoms - 1) / kQuadAtoms); }
 
 // ---- launchers (host) -----------------------------------------------------
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
+// Wraps positions pos[3][n] into xw[atom_off ..).
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
-                                 Box box, double4* xw, unsigned* status, hipStream_t s);
-hipError_t launch_store_positions(const double4* xw, int64_t n, double* pos_soa, hipStream_t s);
-// Builds the sorted lists, their reverse slots and the largest count (maxnn).
-hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid grid,
+                                 Box box, int atom_off, double4* xw, unsigned* status,
+                                 hipStream_t s);
+// Copies xw[atom_off ..) back to pos[3][n].
+hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, double* pos_soa,
+                                  hipStream_t s);
+// Builds the sorted lists and reverse slots of every segment with build != 0
+// and the largest count over them (maxnn).
+hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
                                   double rlist, hipStream_t s);
 
-// overflow_pass = false launches the register-tile kernel over all atoms;
-// true launches the kernel for the atoms the first pass left over.
-// max_nn bounds the in-cutoff count of every atom; the overflow pass is only
-// launched when it can exceed the register tile.
+// overflow_pass = false: the fast four-lanes-per-atom pass over every atom;
+// true: the pass over the atoms the first one left over.  max_nn bounds the
+// in-cutoff count of every atom; the overflow pass is only launched when it
+// can exceed the fast path.
 template <class T>
-hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, bool overflow_pass, int max_nn, hipStream_t s);
+hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
+                                   const TersoffParams& p, bool overflow_pass, int max_nn,
+                                   hipStream_t s);
 template <class T>
-hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p,
-                              double* U, bool overflow_pass, int max_nn, hipStream_t s);
+hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SWParams& p,
+                              bool overflow_pass, int max_nn, hipStream_t s);
 
 struct StepArgs {
     int cur;                 // position buffer read this step
-    bool kick_before;        // v += dt/2 a before forming J (second half-kick)
-    bool advance;            // then v += dt/2 a, x_next = wrap(x + dt v)
     bool check_skin;         // measure how far x_next moved since the list build
+    double skin_half2;       // (skin/2)^2
     unsigned long long* disp_slot;  // receives (atomic max) the squared displacement, as bits
     double* part_row;        // this step's row of block partials (null: no thermo)
-    double half_dt_acc;      // dt/2 * kappa / m
-    double dt;
-    double skin_half2;       // (skin/2)^2
-    double kin_scale;        // m / (2 kappa): E_kin = kin_scale * v^2
 };
 
+// Per segment, from its phase p and nsteps: second half-kick iff p > 0;
+// first half-kick and drift into the other buffer iff p < nsteps, else the
+// positions are copied forward unchanged; segments with p > nsteps are idle.
 template <class T>
-hipError_t launch_pair_gather(const Buffers& b, Box box, const StepArgs& a, const double* U,
-                              double* vel_soa, double* F, double* W, double* J, hipStream_t s);
+hipError_t launch_pair_gather(const Buffers& b, const Segs& S, const StepArgs& a, hipStream_t s);
 
-// Thermo rows of steps [first_step, first_step + count) from the partials ring.
-hipError_t launch_thermo_fold(const Buffers& b, int first_step, int count, double* thermo,
-                              hipStream_t s);
-
+// Thermo rows [first, first + count) of segment `sid` from the partials ring:
+// row k is ring row (ring0 + k) % kThermoRing.
+hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int first, int count,
+                              int ring0, double* thermo, hipStream_t s);
+// Batch: for every segment with a thermo pointer that took part in the
+// pairwise launch reading S.phase_in, its row for that step from ring row
+// `ring_row`.
+hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring_row,
+                                       hipStream_t s);
 
 }  // namespace mbmd

@@ -53,7 +53,7 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s)
 
 __global__ void __launch_bounds__(kBlock)
 k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ types, int64_t n,
-                 Box box, double4* __restrict__ xw, unsigned* __restrict__ status)
+                 Box box, int atom_off, double4* __restrict__ xw, unsigned* __restrict__ status)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -63,33 +63,37 @@ k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ typ
         x = y = z = 0.0;
     }
     if (types && types[i] != 0) atomicOr(status, ST_TYPES);
-    xw[i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
-                         wrap_coord(z, box.L[2]), 0.0);
+    xw[atom_off + i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
+                                    wrap_coord(z, box.L[2]), 0.0);
 }
 
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
-                                 Box box, double4* xw, unsigned* status, hipStream_t s)
+                                 Box box, int atom_off, double4* xw, unsigned* status,
+                                 hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_load_positions<<<blocks_for(n), kBlock, 0, s>>>(pos_soa, types, n, box, xw, status);
+    k_load_positions<<<blocks_for(n), kBlock, 0, s>>>(pos_soa, types, n, box, atom_off, xw,
+                                                      status);
     return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_store_positions(const double4* __restrict__ xw, int64_t n, double* __restrict__ pos)
+k_store_positions(const double4* __restrict__ xw, int atom_off, int64_t n,
+                  double* __restrict__ pos)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    const double4 p = xw[i];
+    const double4 p = xw[atom_off + i];
     pos[i] = p.x;
     pos[n + i] = p.y;
     pos[2 * n + i] = p.z;
 }
 
-hipError_t launch_store_positions(const double4* xw, int64_t n, double* pos_soa, hipStream_t s)
+hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, double* pos_soa,
+                                  hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_store_positions<<<blocks_for(n), kBlock, 0, s>>>(xw, n, pos_soa);
+    k_store_positions<<<blocks_for(n), kBlock, 0, s>>>(xw, atom_off, n, pos_soa);
     return hipGetLastError();
 }
 
@@ -101,20 +105,34 @@ __device__ __forceinline__ int cell_coord(double x, double inv_lc, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// Logical 256-atom block -> (segment, global atom index); false past the
+// segment's last atom.
+__device__ __forceinline__ bool block_atom(const Segs& S, int& sid, int64_t& i)
+{
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const int local = (lb - g.blk) * kBlock + threadIdx.x;
+    i = g.atom_off + local;
+    return local < g.n;
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_cell_count(const double4* __restrict__ xw, int64_t n, CellGrid g, int* __restrict__ cell_of,
+k_cell_count(Segs S, const double4* __restrict__ xw, int* __restrict__ cell_of,
              int* __restrict__ count, double4* __restrict__ xbuild)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+    int sid;
+    int64_t i;
+    if (!block_atom(S, sid, i)) return;
+    const Seg& g = S.seg[sid];
     const double4 p = xw[i];
     const int cx = cell_coord(p.x, g.inv_lc[0], g.nc[0]);
     const int cy = cell_coord(p.y, g.inv_lc[1], g.nc[1]);
     const int cz = cell_coord(p.z, g.inv_lc[2], g.nc[2]);
-    const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    const int c = g.cell_off + (cz * g.nc[1] + cy) * g.nc[0] + cx;
     cell_of[i] = c;
     atomicAdd(&count[c], 1);
-    xbuild[i] = p;
+    if (g.build) xbuild[i] = p;
 }
 
 // Three-pass exclusive scan of the cell counts: per-block sums, a scan of the
@@ -206,11 +224,12 @@ k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ b
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_cell_fill(const int* __restrict__ cell_of, int64_t n, const int* __restrict__ start,
+k_cell_fill(Segs S, const int* __restrict__ cell_of, const int* __restrict__ start,
             int* __restrict__ fill, int* __restrict__ cell_atoms)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+    int sid;
+    int64_t i;
+    if (!block_atom(S, sid, i)) return;
     const int c = cell_of[i];
     const int slot = atomicAdd(&fill[c], 1);
     cell_atoms[start[c] + slot] = (int)i;
@@ -218,7 +237,7 @@ k_cell_fill(const int* __restrict__ cell_of, int64_t n, const int* __restrict__ 
 
 // ---- neighbour search -----------------------------------------------------
 
-constexpr int kSearchBlock = 128;
+constexpr int kSearchBlock = kBlock / 2;
 
 // One thread per atom; its sorted list is kept in LDS (column-major over the
 // block so that neighbouring threads hit distinct banks), then written out
@@ -240,58 +259,67 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
     return list_r2(a, b, box) < rl2;
 }
 
+// One thread per atom of a segment being built; its sorted list is kept in
+// LDS (column-major over the block so that neighbouring threads hit distinct
+// banks), then written out slot-major.  Search blocks hold kBlock atoms like
+// the other per-atom kernels but run as two halves of kSearchBlock threads.
 __global__ void __launch_bounds__(kSearchBlock)
-k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double rl2,
-         double rl2_lo, double rl2_hi, int M, const int* __restrict__ cell_of,
-         const int* __restrict__ start, const int* __restrict__ cell_atoms, int* __restrict__ nn,
-         int* __restrict__ nl, int* __restrict__ maxnn, unsigned* __restrict__ status)
+k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, double rl2_hi, int M,
+         int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
+         const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
+         int* __restrict__ maxnn, unsigned* __restrict__ status)
 {
     extern __shared__ int lbuf[];
     __shared__ int lds_max[kSearchBlock / 64];
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kSearchBlock + threadIdx.x;
+    const int lb2 = xcd_block(blockIdx.x, gridDim.x);
+    const int lb = lb2 >> 1;
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const int local = (lb - g.blk) * kBlock + (lb2 & 1) * kSearchBlock + threadIdx.x;
+    const int64_t i = g.atom_off + local;
     int cnt = 0;
-    if (i < n) {
-    int* buf = lbuf + threadIdx.x;
-    const double4 xi = xw[i];
-    const int c = cell_of[i];
-    const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-    int lo[3], hi[3];
+    if (local < g.n && g.build) {
+        int* buf = lbuf + threadIdx.x;
+        const double4 xi = xw[i];
+        const int c = cell_of[i] - g.cell_off;
+        const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+        int lo[3], hi[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = g.nc[a] >= 3 ? -1 : 0;
-        hi[a] = g.nc[a] >= 2 ? 1 : 0;
-    }
-    for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-        const int zz = (cz + oz + g.nc[2]) % g.nc[2];
-        for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-            const int yy = (cy + oy + g.nc[1]) % g.nc[1];
-            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                const int xx = (cx + ox + g.nc[0]) % g.nc[0];
-                const int cc = (zz * g.nc[1] + yy) * g.nc[0] + xx;
-                const int e = start[cc + 1];
-                for (int p = start[cc]; p < e; ++p) {
-                    const int j = cell_atoms[p];
-                    if (j == (int)i) continue;
-                    if (in_list(xi, xw[j], box, rl2, rl2_lo, rl2_hi)) {
-                        // insertion into the sorted LDS list (capacity M)
-                        int q = cnt < M ? cnt : M;
-                        while (q > 0 && buf[(q - 1) * kSearchBlock] > j) {
-                            if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
-                            --q;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = g.nc[a] >= 3 ? -1 : 0;
+            hi[a] = g.nc[a] >= 2 ? 1 : 0;
+        }
+        for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+            const int zz = (cz + oz + g.nc[2]) % g.nc[2];
+            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
+                const int yy = (cy + oy + g.nc[1]) % g.nc[1];
+                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                    const int xx = (cx + ox + g.nc[0]) % g.nc[0];
+                    const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
+                    const int e = start[cc + 1];
+                    for (int p = start[cc]; p < e; ++p) {
+                        const int j = cell_atoms[p];
+                        if (j == (int)i) continue;
+                        if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi)) {
+                            // insertion into the sorted LDS list (capacity M)
+                            int q = cnt < M ? cnt : M;
+                            while (q > 0 && buf[(q - 1) * kSearchBlock] > j) {
+                                if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
+                                --q;
+                            }
+                            if (q < M) buf[q * kSearchBlock] = j;
+                            ++cnt;
                         }
-                        if (q < M) buf[q * kSearchBlock] = j;
-                        ++cnt;
                     }
                 }
             }
         }
-    }
-    // On overflow the stored entries are not the M smallest indices; the
-    // status bit turns the call into an error.
-    if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
-    nn[i] = cnt;
-    const int w = cnt < M ? cnt : M;
-    for (int m = 0; m < w; ++m) nl[(int64_t)m * n + i] = buf[m * kSearchBlock];
+        // On overflow the stored entries are the M smallest indices; the
+        // status bit turns the call into an error.
+        if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
+        nn[i] = cnt;
+        const int w = cnt < M ? cnt : M;
+        for (int m = 0; m < w; ++m) nl[(int64_t)m * cap + i] = buf[m * kSearchBlock];
     }
     // largest count of the block, one atomic per block
     int mx = cnt;
@@ -303,55 +331,54 @@ k_search(const double4* __restrict__ xw, int64_t n, Box box, CellGrid g, double 
         int bm = lds_max[0];
 #pragma unroll
         for (int k = 1; k < kSearchBlock / 64; ++k) bm = max(bm, lds_max[k]);
-        atomicMax(maxnn, bm);
+        atomicMax(&maxnn[sid], bm);
     }
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_reverse(const int* __restrict__ nn, const int* __restrict__ nl, int64_t n, int M,
+k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M, int64_t cap,
           int* __restrict__ rev, unsigned* __restrict__ status)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+    int sid;
+    int64_t i;
+    if (!block_atom(S, sid, i) || !S.seg[sid].build) return;
     const int cnt = min(nn[i], M);
     for (int m = 0; m < cnt; ++m) {
-        const int j = nl[(int64_t)m * n + i];
+        const int j = nl[(int64_t)m * cap + i];
         const int cj = min(nn[j], M);
         int s = -1;
         for (int q = 0; q < cj; ++q)
-            if (nl[(int64_t)q * n + j] == (int)i) { s = q; break; }
+            if (nl[(int64_t)q * cap + j] == (int)i) { s = q; break; }
         if (s < 0) atomicOr(status, ST_ASYMMETRIC);
-        rev[(int64_t)m * n + i] = s < 0 ? 0 : s;
+        rev[(int64_t)m * cap + i] = s < 0 ? 0 : s;
     }
 }
 
-hipError_t launch_build_neighbors(const Buffers& b, int cur, Box box, CellGrid grid,
+hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
                                   double rlist, hipStream_t s)
 {
-    const int64_t n = b.n;
-    if (n <= 0) return hipSuccess;
-    hipError_t e = launch_fill_int(b.cell_count, grid.ncell, 0, s);
-    if (e == hipSuccess) e = launch_fill_int(b.maxnn, 1, 0, s);
+    if (S.nblk <= 0) return hipSuccess;
+    if (!S.seg || S.nseg > b.seg_cap || total_cells > b.cell_cap) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_int(b.cell_count, total_cells, 0, s);
+    if (e == hipSuccess) e = launch_fill_int(b.maxnn, S.nseg, 0, s);
     if (e != hipSuccess) return e;
-    k_cell_count<<<blocks_for(n), kBlock, 0, s>>>(b.xw[cur], n, grid, b.cell_of, b.cell_count,
-                                                  b.xbuild);
-    const int nscan = (grid.ncell + kScanTile - 1) / kScanTile;
-    // The block sums live in the fill array's tail region (cells + 1 .. ), see
-    // workspace layout: cell_fill has room for ncell + nscan + 1 ints.
-    int* bsum = b.cell_fill + grid.ncell + 1;
-    k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, grid.ncell, bsum);
+    k_cell_count<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_count, b.xbuild);
+    const int nscan = (total_cells + kScanTile - 1) / kScanTile;
+    // The block sums live in the fill array's tail: cell_fill has room for
+    // cell capacity + 1 + scan blocks ints.
+    int* bsum = b.cell_fill + total_cells + 1;
+    k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum);
     k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
-    k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, grid.ncell, bsum, b.cell_start,
+    k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
                                           b.cell_fill);
-    k_cell_fill<<<blocks_for(n), kBlock, 0, s>>>(b.cell_of, n, b.cell_start, b.cell_fill,
-                                                 b.cell_atoms);
-    const int sb = (int)((n + kSearchBlock - 1) / kSearchBlock);
+    k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.cell_of, b.cell_start, b.cell_fill, b.cell_atoms);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
-    k_search<<<sb, kSearchBlock, lds, s>>>(b.xw[cur], n, box, grid, rl2, rl2 * (1.0 - 1e-10),
-                                           rl2 * (1.0 + 1e-10), b.M, b.cell_of, b.cell_start,
-                                           b.cell_atoms, b.nn, b.nl, b.maxnn, b.status);
-    k_reverse<<<blocks_for(n), kBlock, 0, s>>>(b.nn, b.nl, n, b.M, b.rev, b.status);
+    k_search<<<2 * S.nblk, kSearchBlock, lds, s>>>(S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10),
+                                                   rl2 * (1.0 + 1e-10), b.M, b.cap, b.cell_of,
+                                                   b.cell_start, b.cell_atoms, b.nn, b.nl,
+                                                   b.maxnn, b.status);
+    k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
 }
 

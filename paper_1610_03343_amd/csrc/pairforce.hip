@@ -67,7 +67,7 @@ __device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__ xw,
+k_pair_gather(Segs S, int M, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
               double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
               const int* __restrict__ nn, const int* __restrict__ nl,
               const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
@@ -79,21 +79,30 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
     __shared__ double lds_tot[kPartialCols];
     __shared__ double lds_max[kBlock / 64];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const int phase = S.phase_in[sid];
+    if (lb == g.blk && threadIdx.x == 0)
+        S.phase_out[sid] = phase > g.nsteps ? phase : phase + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;   // consumed by the partials pass
+    if (phase > g.nsteps) return;              // finished segment, kept for retrieval
+    const bool kick_before = phase > 0, advance = phase < g.nsteps;
+    const Box box = g.box;
+    const int local = (lb - g.blk) * kBlock + threadIdx.x;
+    const int64_t i = g.atom_off + local;
 
     double f[3] = {0, 0, 0}, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, mm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double v[3] = {0, 0, 0}, jj[3] = {0, 0, 0}, ekin = 0.0, ui = 0.0, disp2 = 0.0;
-    if (i < n) {
+    if (local < g.n) {
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
         const int nnb = min(nn[i], M);
         for (int m = 0; m < nnb; ++m) {
             if (!((msk >> m) & 1ull)) continue;
-            const int j = nl[(int64_t)m * n + i];
-            const int rs = rev[(int64_t)m * n + i];
-            const T* pij = dpart + ((int64_t)m * n + i) * 3;
-            const T* pji = dpart + ((int64_t)rs * n + j) * 3;
+            const int j = nl[(int64_t)m * cap + i];
+            const int rs = rev[(int64_t)m * cap + i];
+            const T* pij = dpart + ((int64_t)m * cap + i) * 3;
+            const T* pji = dpart + ((int64_t)rs * cap + j) * 3;
             const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
             const double fij0 = (double)pij[0] - dji0;
             const double fij1 = (double)pij[1] - dji1;
@@ -121,55 +130,58 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
         if (vel) {
 #pragma clang fp contract(off)
             v[0] = vel[i];
-            v[1] = vel[n + i];
-            v[2] = vel[2 * n + i];
-            if (a.kick_before) {
+            v[1] = vel[os + i];
+            v[2] = vel[2 * os + i];
+            if (kick_before) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] += a.half_dt_acc * f[c];
+                for (int c = 0; c < 3; ++c) v[c] += g.half_dt_acc * f[c];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 jj[c] = mm[3 * c + 0] * v[0] + mm[3 * c + 1] * v[1] + mm[3 * c + 2] * v[2];
-            ekin = a.kin_scale * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            ekin = g.kin_scale * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         }
         // Outputs are not read again by the step loop: streaming stores keep
         // them from evicting the partials and positions that neighbours of
         // later atoms still gather from L2.
         __builtin_nontemporal_store(f[0], &F[i]);
-        __builtin_nontemporal_store(f[1], &F[n + i]);
-        __builtin_nontemporal_store(f[2], &F[2 * n + i]);
+        __builtin_nontemporal_store(f[1], &F[os + i]);
+        __builtin_nontemporal_store(f[2], &F[2 * os + i]);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) __builtin_nontemporal_store(w[c], &W[(int64_t)c * n + i]);
+        for (int c = 0; c < 9; ++c) __builtin_nontemporal_store(w[c], &W[(int64_t)c * os + i]);
         __builtin_nontemporal_store(jj[0], &J[i]);
-        __builtin_nontemporal_store(jj[1], &J[n + i]);
-        __builtin_nontemporal_store(jj[2], &J[2 * n + i]);
-        if (vel) {
+        __builtin_nontemporal_store(jj[1], &J[os + i]);
+        __builtin_nontemporal_store(jj[2], &J[2 * os + i]);
+        if (vel && advance) {
 #pragma clang fp contract(off)
-            if (a.advance) {
-                double vn[3], x[3] = {xi.x, xi.y, xi.z};
+            double vn[3], x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                vn[c] = v[c] + g.half_dt_acc * f[c];
+                x[c] = wrap_coord_pf(x[c] + g.dt * vn[c], box.L[c]);
+            }
+            vel[i] = vn[0];
+            vel[os + i] = vn[1];
+            vel[2 * os + i] = vn[2];
+            xw_next[i] = make_double4(x[0], x[1], x[2], xi.w);
+            if (a.check_skin) {
+                const double4 xb = xbuild[i];
+                double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    vn[c] = v[c] + a.half_dt_acc * f[c];
-                    x[c] = wrap_coord_pf(x[c] + a.dt * vn[c], box.L[c]);
+                    d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
+                    disp2 += d[c] * d[c];
                 }
-                vel[i] = vn[0];
-                vel[n + i] = vn[1];
-                vel[2 * n + i] = vn[2];
-                xw_next[i] = make_double4(x[0], x[1], x[2], 0.0);
-                if (a.check_skin) {
-                    const double4 xb = xbuild[i];
-                    double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
-                        disp2 += d[c] * d[c];
-                    }
-                }
-            } else {
-                vel[i] = v[0];
-                vel[n + i] = v[1];
-                vel[2 * n + i] = v[2];
             }
+        } else {
+            // last step of this segment: full-step velocity, positions carried
+            // into the buffer the next launch reads
+            if (vel && kick_before) {
+                vel[i] = v[0];
+                vel[os + i] = v[1];
+                vel[2 * os + i] = v[2];
+            }
+            xw_next[i] = xi;
         }
     }
 
@@ -191,7 +203,7 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
 
     if (!a.part_row) return;
     // per-block partial sums (U, E_kin, W (9), J (3)) into this step's row of
-    // the partials ring; the fold kernel sums the rows in block order
+    // the partials ring; the fold kernel sums a segment's blocks in order
     double vals[kPartialCols];
     vals[0] = ui;
     vals[1] = ekin;
@@ -203,60 +215,104 @@ k_pair_gather(Box box, int64_t n, int M, StepArgs a, const double4* __restrict__
     if (threadIdx.x < kPartialCols) a.part_row[(int64_t)lb * kPartialCols + threadIdx.x] = lds_tot[threadIdx.x];
 }
 
-// One block per step: folds that step's per-block partials, in block order,
-// into its thermo row: 0 E_pot, 1 E_kin, 2..10 W, 11..13 J, 14 E_pot + E_kin,
-// 15 kinetic temperature (k_B in eV/K, 3N - 3 degrees of freedom).
+// One block per step of one segment: folds that step's block partials of the
+// segment, in block order, into its thermo row: 0 E_pot, 1 E_kin, 2..10 W,
+// 11..13 J, 14 E_pot + E_kin, 15 kinetic temperature (k_B in eV/K, 3N - 3
+// degrees of freedom).
 __global__ void __launch_bounds__(kBlock)
-k_thermo_fold(const double* __restrict__ part_b, int nblocks, int ring, int first_step,
-              int64_t n, double* __restrict__ thermo)
+k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int sid, int first,
+              int ring0, double* __restrict__ thermo)
 {
     __shared__ double lds[kBlock / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
-    const int step = first_step + blockIdx.x;
-    const double* rowp = part_b + (int64_t)(step % ring) * nblocks * kPartialCols;
+    const Seg& g = S.seg[sid];
+    const int k = first + blockIdx.x;
+    const double* rowp = part_b + (int64_t)((ring0 + k) % kThermoRing) * blk_cap * kPartialCols;
+    const int b0 = g.blk, b1 = g.blk + blocks_for(g.n);
     double vals[kPartialCols];
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
         const double* p = rowp + (int64_t)b * kPartialCols;
 #pragma unroll
         for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
     }
     block_sum_cols(vals, lds, lds_tot);
     if (threadIdx.x == 0) {
-        double* row = thermo + (int64_t)step * kThermoCols;
+        double* row = thermo + (int64_t)k * kThermoCols;
+        const double n = (double)g.n;
 #pragma unroll
         for (int c = 0; c < kPartialCols; ++c) row[c] = lds_tot[c];
         row[14] = lds_tot[0] + lds_tot[1];
-        row[15] = n > 1 ? 2.0 * lds_tot[1] / ((3.0 * (double)n - 3.0) * 8.617333262e-5) : 0.0;
+        row[15] = g.n > 1 ? 2.0 * lds_tot[1] / ((3.0 * n - 3.0) * 8.617333262e-5) : 0.0;
     }
 }
 
-hipError_t launch_thermo_fold(const Buffers& b, int first_step, int count, double* thermo,
-                              hipStream_t s)
+hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int first, int count,
+                              int ring0, double* thermo, hipStream_t s)
 {
-    if (b.n <= 0 || count <= 0) return hipSuccess;
-    k_thermo_fold<<<count, kBlock, 0, s>>>(b.part_b, blocks_for(b.n), kThermoRing, first_step,
-                                            b.n, thermo);
+    if (count <= 0) return hipSuccess;
+    if (!S.seg || sid < 0 || sid >= S.nseg || !thermo) return hipErrorInvalidValue;
+    k_thermo_fold<<<count, kBlock, 0, s>>>(b.part_b, b.blk_cap, S, sid, first, ring0, thermo);
+    return hipGetLastError();
+}
+
+// One block per segment: its row of the step just taken (phase_in) from ring
+// row `ring_row`, for segments that took part and have a thermo pointer.
+__global__ void __launch_bounds__(kBlock)
+k_thermo_fold_segments(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int ring_row)
+{
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    const int sid = blockIdx.x;
+    const Seg& g = S.seg[sid];
+    const int k = S.phase_in[sid];
+    if (!g.thermo || k > g.nsteps) return;
+    const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
+    const int b0 = g.blk, b1 = g.blk + blocks_for(g.n);
+    double vals[kPartialCols];
+#pragma unroll
+    for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
+        const double* p = rowp + (int64_t)b * kPartialCols;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
+    }
+    block_sum_cols(vals, lds, lds_tot);
+    if (threadIdx.x == 0) {
+        double* row = g.thermo + (int64_t)k * kThermoCols;
+        const double n = (double)g.n;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) row[c] = lds_tot[c];
+        row[14] = lds_tot[0] + lds_tot[1];
+        row[15] = g.n > 1 ? 2.0 * lds_tot[1] / ((3.0 * n - 3.0) * 8.617333262e-5) : 0.0;
+    }
+}
+
+hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring_row,
+                                       hipStream_t s)
+{
+    if (S.nseg <= 0) return hipSuccess;
+    if (!segs_ready(S, b)) return hipErrorInvalidValue;
+    k_thermo_fold_segments<<<S.nseg, kBlock, 0, s>>>(b.part_b, b.blk_cap, S,
+                                                      ring_row % kThermoRing);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_pair_gather(const Buffers& b, Box box, const StepArgs& a, const double* U,
-                              double* vel_soa, double* F, double* W, double* J, hipStream_t s)
+hipError_t launch_pair_gather(const Buffers& b, const Segs& S, const StepArgs& a, hipStream_t s)
 {
-    const int64_t n = b.n;
-    if (n <= 0) return hipSuccess;
-    k_pair_gather<T><<<blocks_for(n), kBlock, 0, s>>>(
-        box, n, b.M, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nn, b.nl, b.rev, b.mask,
-        static_cast<const T*>(b.dpart), U, vel_soa, F, W, J, b.ovf_count);
+    if (S.nblk <= 0) return hipSuccess;
+    if (!segs_ready(S, b) || !b.F || !b.W || !b.J || !b.U) return hipErrorInvalidValue;
+    k_pair_gather<T><<<S.nblk, kBlock, 0, s>>>(
+        S, b.M, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nn, b.nl, b.rev,
+        b.mask, static_cast<const T*>(b.dpart), b.U, b.vel, b.F, b.W, b.J, b.ovf_count);
     return hipGetLastError();
 }
 
-template hipError_t launch_pair_gather<double>(const Buffers&, Box, const StepArgs&,
-                                               const double*, double*, double*, double*, double*,
+template hipError_t launch_pair_gather<double>(const Buffers&, const Segs&, const StepArgs&,
                                                hipStream_t);
-template hipError_t launch_pair_gather<float>(const Buffers&, Box, const StepArgs&, const double*,
-                                              double*, double*, double*, double*, hipStream_t);
+template hipError_t launch_pair_gather<float>(const Buffers&, const Segs&, const StepArgs&,
+                                              hipStream_t);
 
 }  // namespace mbmd

@@ -36,14 +36,14 @@ __device__ __forceinline__ Disp cut_disp(const double4& a, const double4& b, con
 
 // Bit m of the returned mask is set iff list slot m of atom i is inside the
 // cutoff (r^2 < rc2).
-__device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int64_t i, int64_t n,
+__device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int64_t i, int64_t cap,
                                                           int nnb, const int* __restrict__ nl,
                                                           const double4* __restrict__ xw,
                                                           const Box& box, double rc2)
 {
     unsigned long long msk = 0;
     for (int m = 0; m < nnb; ++m) {
-        const int j = nl[(int64_t)m * n + i];
+        const int j = nl[(int64_t)m * cap + i];
         const Disp d = cut_disp(xi, xw[j], box);
         if (d.r2 < rc2) msk |= 1ull << m;
     }
@@ -60,7 +60,7 @@ constexpr int kQuad = 4;
 constexpr int kQuadSlots = 2;                       // bonds per lane
 constexpr int kQuadBonds = kQuad * kQuadSlots;      // bonds per atom in the fast path
 static_assert(kQuadBonds == kSiteFastBonds, "quad capacity is the fast-path bond count");
-constexpr int kAtomsPerQuadBlock = kBlock / kQuad;  // atoms per 256-lane block
+static_assert(kQuadAtoms * kQuad == kBlock, "a quad block holds kQuadAtoms atoms");
 
 __device__ __forceinline__ double quad_xor(double v, int k) { return __shfl_xor(v, k, kQuad); }
 __device__ __forceinline__ float quad_xor(float v, int k) { return __shfl_xor(v, k, kQuad); }
@@ -93,14 +93,14 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long msk, int c)
 
 // Cutoff mask of atom i computed by its quad: lane q tests slots q, q+4, ...
 __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi, int64_t i,
-                                                               int64_t n, int nnb, int q,
+                                                               int64_t cap, int nnb, int q,
                                                                const int* __restrict__ nl,
                                                                const double4* __restrict__ xw,
                                                                const Box& box, double rc2)
 {
     unsigned long long msk = 0;
     for (int m = q; m < nnb; m += kQuad) {
-        const int j = nl[(int64_t)m * n + i];
+        const int j = nl[(int64_t)m * cap + i];
         const Disp d = cut_disp(xi, xw[j], box);
         if (d.r2 < rc2) msk |= 1ull << m;
     }

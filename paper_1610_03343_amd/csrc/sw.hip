@@ -43,7 +43,7 @@ __device__ __forceinline__ double s_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float s_sqrt(float x) { return sqrtf(x); }
 
 template <class T, int MAXC, bool FIXED>
-__device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, const double4& xi,
+__device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap, const double4& xi,
                                         unsigned long long msk, int cnt,
                                         const int* __restrict__ nl,
                                         const double4* __restrict__ xw, const Box& box,
@@ -61,7 +61,7 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, c
             const int m = __builtin_ctzll(rem);
             slot[c] = m;
             rem &= rem - 1;
-            const int j = nl[(int64_t)m * n + i];
+            const int j = nl[(int64_t)m * cap + i];
             const Disp d = cut_disp(xi, xw[j], box);
             const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
             const T r = s_sqrt(dx * dx + dy * dy + dz * dz);
@@ -115,7 +115,7 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, c
                     dz += radial * uz[c] + angular * (uz[e] - cs * uz[c]);
                 }
             }
-            T* o = dpart + ((int64_t)slot[c] * n + i) * 3;
+            T* o = dpart + ((int64_t)slot[c] * cap + i) * 3;
             o[0] = dx;
             o[1] = dy;
             o[2] = dz;
@@ -125,28 +125,33 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t n, c
 
 template <class T, int MAXC>
 __global__ void __launch_bounds__(kBlock)
-k_sw_partials(SWK<T> p, double rc2, Box box, int64_t n, int M, const double4* __restrict__ xw,
+k_sw_partials(SWK<T> p, double rc2, Segs S, int M, int64_t cap, const double4* __restrict__ xw,
               const int* __restrict__ nn, const int* __restrict__ nl,
               unsigned long long* __restrict__ mask, double* __restrict__ U,
               T* __restrict__ dpart, int* __restrict__ ovf_count, int* __restrict__ ovf_list)
 {
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    const int local = (lb - g.blk) * kBlock + threadIdx.x;
+    if (local >= g.n) return;
+    const int64_t i = g.atom_off + local;
     const double4 xi = xw[i];
     const int nnb = min(nn[i], M);
-    const unsigned long long msk = cutoff_mask(xi, i, n, nnb, nl, xw, box, rc2);
+    const unsigned long long msk = cutoff_mask(xi, i, cap, nnb, nl, xw, g.box, rc2);
     mask[i] = msk;
     const int cnt = __popcll(msk);
     if (cnt > MAXC) {
         ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
         return;
     }
-    sw_site<T, MAXC, true>(p, i, n, xi, msk, cnt, nl, xw, box, U, dpart);
+    sw_site<T, MAXC, true>(p, i, cap, xi, msk, cnt, nl, xw, g.box, U, dpart);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_sw_partials_ovf(SWK<T> p, Box box, int64_t n, const double4* __restrict__ xw,
+k_sw_partials_ovf(SWK<T> p, Segs S, int64_t cap, const double4* __restrict__ xw,
                   const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
                   double* __restrict__ U, T* __restrict__ dpart,
                   const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
@@ -154,8 +159,10 @@ k_sw_partials_ovf(SWK<T> p, Box box, int64_t n, const double4* __restrict__ xw,
     const int total = *ovf_count;
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
         const int64_t i = ovf_list[k];
+        const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
-        sw_site<T, kMaxSlots, false>(p, i, n, xw[i], msk, __popcll(msk), nl, xw, box, U, dpart);
+        sw_site<T, kMaxSlots, false>(p, i, cap, xi, msk, __popcll(msk), nl, xw,
+                                     S.seg[seg_of_atom(S, i)].box, U, dpart);
     }
 }
 
@@ -163,28 +170,29 @@ constexpr int kSWTile = kSiteFastBonds;
 constexpr int kSWOvfGrid = 64;
 
 template <class T>
-hipError_t launch_sw_partials(const Buffers& b, int cur, Box box, const SWParams& p, double* U,
+hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SWParams& p,
                               bool overflow_pass, int max_nn, hipStream_t s)
 {
-    const int64_t n = b.n;
-    if (n <= 0) return hipSuccess;
+    if (S.nblk <= 0) return hipSuccess;
+    if (!segs_ready(S, b)) return hipErrorInvalidValue;
     const SWK<T> k = sw_constants<T>(p);
     const double rc = p.a * p.sigma;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_sw_partials<T, kSWTile><<<blocks_for(n), kBlock, 0, s>>>(
-        k, rc * rc, box, n, b.M, b.xw[cur], b.nn, b.nl, b.mask, U, dp, b.ovf_count, b.ovf_list);
+        k_sw_partials<T, kSWTile><<<S.nblk, kBlock, 0, s>>>(k, rc * rc, S, b.M, b.cap, b.xw[cur],
+                                                            b.nn, b.nl, b.mask, b.U, dp,
+                                                            b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
     if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
-        k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
-                                              b.ovf_count, b.ovf_list);
+        k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl, b.mask,
+                                                           b.U, dp, b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
-template hipError_t launch_sw_partials<double>(const Buffers&, int, Box, const SWParams&, double*, bool, int,
-                                               hipStream_t);
-template hipError_t launch_sw_partials<float>(const Buffers&, int, Box, const SWParams&, double*, bool, int,
-                                              hipStream_t);
+template hipError_t launch_sw_partials<double>(const Buffers&, const Segs&, int, const SWParams&,
+                                               bool, int, hipStream_t);
+template hipError_t launch_sw_partials<float>(const Buffers&, const Segs&, int, const SWParams&,
+                                              bool, int, hipStream_t);
 
 }  // namespace mbmd

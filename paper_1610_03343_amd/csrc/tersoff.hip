@@ -91,7 +91,7 @@ __device__ __forceinline__ T angular_g_only(const TersoffK<T>& p, T cs)
 }
 
 template <class T, int MAXC, bool FIXED>
-__device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, int64_t n,
+__device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, int64_t cap,
                                              const double4& xi, unsigned long long msk, int cnt,
                                              const int* __restrict__ nl,
                                              const double4* __restrict__ xw, const Box& box,
@@ -108,7 +108,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
             const int m = __builtin_ctzll(rem);
             slot[c] = m;
             rem &= rem - 1;
-            const int j = nl[(int64_t)m * n + i];
+            const int j = nl[(int64_t)m * cap + i];
             const Disp d = cut_disp(xi, xw[j], box);
             const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
             const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
@@ -173,7 +173,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
                     dz += a * (uz[e] - cs * uz[c]) + bb * uz[c];
                 }
             }
-            T* o = dpart + ((int64_t)slot[c] * n + i) * 3;
+            T* o = dpart + ((int64_t)slot[c] * cap + i) * 3;
             o[0] = dx;
             o[1] = dy;
             o[2] = dz;
@@ -188,19 +188,24 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
 // kQuadBonds in-cutoff bonds go to the overflow list.
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_site_quad(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
+k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
                     const double4* __restrict__ xw, const int* __restrict__ nn,
                     const int* __restrict__ nl, unsigned long long* __restrict__ mask,
                     double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
                     int* __restrict__ ovf_list)
 {
     const int q = threadIdx.x & (kQuad - 1);
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kAtomsPerQuadBlock +
-                      (threadIdx.x >> 2);
-    const bool valid = i < n;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sid = seg_of_block(S, lb, true);
+    const Seg& g = S.seg[sid];
+    if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    const Box box = g.box;
+    const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
+    const int64_t i = g.atom_off + local;
+    const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int nnb = valid ? min(nn[i], M) : 0;
-    const unsigned long long msk = quad_cutoff_mask(xi, i, n, nnb, q, nl, xw, box, rc2);
+    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuadBonds;
     if (valid && q == 0) {
@@ -221,7 +226,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
         if (c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
-            const int j = nl[(int64_t)m * n + i];
+            const int j = nl[(int64_t)m * cap + i];
             const Disp d = cut_disp(xi, xw[j], box);
             const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
             const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
@@ -318,7 +323,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
     for (int s = 0; s < kQuadSlots; ++s) {
         const int c = q + kQuad * s;
         if (c < kc) {
-            T* o = dpart + ((int64_t)slot[s] * n + i) * 3;
+            T* o = dpart + ((int64_t)slot[s] * cap + i) * 3;
             o[0] = gx[s];
             o[1] = gy[s];
             o[2] = gz[s];
@@ -330,7 +335,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Box box, int64_t n, int M,
 // the whole list capacity.
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_partials_ovf(TersoffK<T> p, Box box, int64_t n, const double4* __restrict__ xw,
+k_tersoff_partials_ovf(TersoffK<T> p, Segs S, int64_t cap, const double4* __restrict__ xw,
                        const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
                        double* __restrict__ U, T* __restrict__ dpart,
                        const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
@@ -338,37 +343,41 @@ k_tersoff_partials_ovf(TersoffK<T> p, Box box, int64_t n, const double4* __restr
     const int total = *ovf_count;
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
         const int64_t i = ovf_list[k];
+        const double4 xi = xw[i];
+        const Box box = S.seg[seg_of_atom(S, i)].box;
         const unsigned long long msk = mask[i];
-        tersoff_site<T, kMaxSlots, false>(p, i, n, xw[i], msk, __popcll(msk), nl, xw, box, U, dpart);
+        tersoff_site<T, kMaxSlots, false>(p, i, cap, xi, msk, __popcll(msk), nl, xw, box, U,
+                                          dpart);
     }
 }
 
 constexpr int kOvfGrid = 64;
 
 template <class T>
-hipError_t launch_tersoff_partials(const Buffers& b, int cur, Box box, const TersoffParams& p,
-                                   double* U, bool overflow_pass, int max_nn, hipStream_t s)
+hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
+                                   const TersoffParams& p, bool overflow_pass, int max_nn,
+                                   hipStream_t s)
 {
-    const int64_t n = b.n;
-    if (n <= 0) return hipSuccess;
+    if (S.nblk_quad <= 0) return hipSuccess;
+    if (!segs_ready(S, b)) return hipErrorInvalidValue;
     const TersoffK<T> k = tersoff_constants<T>(p);
-    const double rc2 = p.S * p.S;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        const int nb = (int)((n + kAtomsPerQuadBlock - 1) / kAtomsPerQuadBlock);
-        k_tersoff_site_quad<T><<<nb, kBlock, 0, s>>>(k, rc2, box, n, b.M, b.xw[cur], b.nn, b.nl,
-                                                      b.mask, U, dp, b.ovf_count, b.ovf_list);
+        k_tersoff_site_quad<T><<<S.nblk_quad, kBlock, 0, s>>>(k, p.S * p.S, S, b.M, b.cap,
+                                                              b.xw[cur], b.nn, b.nl, b.mask, b.U,
+                                                              dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
     if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
-        k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, box, n, b.xw[cur], b.nl, b.mask, U, dp,
-                                              b.ovf_count, b.ovf_list);
+        k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl,
+                                                              b.mask, b.U, dp, b.ovf_count,
+                                                              b.ovf_list);
     return hipGetLastError();
 }
 
-template hipError_t launch_tersoff_partials<double>(const Buffers&, int, Box, const TersoffParams&,
-                                                    double*, bool, int, hipStream_t);
-template hipError_t launch_tersoff_partials<float>(const Buffers&, int, Box, const TersoffParams&,
-                                                   double*, bool, int, hipStream_t);
+template hipError_t launch_tersoff_partials<double>(const Buffers&, const Segs&, int,
+                                                    const TersoffParams&, bool, int, hipStream_t);
+template hipError_t launch_tersoff_partials<float>(const Buffers&, const Segs&, int,
+                                                   const TersoffParams&, bool, int, hipStream_t);
 
 }  // namespace mbmd
