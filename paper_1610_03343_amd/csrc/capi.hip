@@ -391,7 +391,8 @@ hipError_t partials(mbmd_ctx* c, int cur)
     hipError_t e;
     for (int pass = 0; pass < 2; ++pass) {
         // the overflow pass only exists when a site can exceed the fast path
-        if (pass == 1 && !(c->buf.M > kSiteFastBonds && c->max_nn > kSiteFastBonds)) break;
+        const int fast = kQuad * (c->potential == 1 ? kSWSlots : kTersoffSlots);
+        if (pass == 1 && !(c->buf.M > fast && c->max_nn > fast)) break;
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)
             e = launch_sw_partials<T>(c->buf, c->segs, cur, c->sp, pass == 1, c->max_nn,

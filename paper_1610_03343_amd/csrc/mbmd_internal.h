@@ -38,7 +38,9 @@ enum : unsigned {
 constexpr int kBlock = 256;          // threads per block of every per-atom kernel
 constexpr int kQuadAtoms = 64;       // atoms per block of the four-lanes-per-atom kernels
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
-constexpr int kSiteFastBonds = 8;    // in-cutoff bonds a site pass handles without overflow
+constexpr int kQuad = 4;             // lanes per atom in the site passes
+constexpr int kTersoffSlots = 2;     // bonds per lane: Tersoff site pass (8 bonds per atom)
+constexpr int kSWSlots = 3;          // bonds per lane: SW site pass (12 bonds per atom)
 constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
 constexpr int kMaxChunk = 256;       // steps enqueued between two checks of the skin

@@ -34,6 +34,33 @@ __device__ __forceinline__ Disp cut_disp(const double4& a, const double4& b, con
     return d;
 }
 
+// Reciprocal and reciprocal square root: the hardware estimate refined by
+// Newton's method, y <- y (2 - x y) and y <- y (3 - x y^2) / 2, twice in
+// double (each step squares the relative error) and once in float.  Inputs
+// are positive normal numbers here (bond lengths, sums of squares).
+__device__ __forceinline__ double nr_rcp(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return fma(fma(-x, y, 1.0), y, y);
+}
+__device__ __forceinline__ float nr_rcp(float x)
+{
+    const float y = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, y, 1.0f), y, y);
+}
+__device__ __forceinline__ double nr_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+__device__ __forceinline__ float nr_rsqrt(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+
 // Bit m of the returned mask is set iff list slot m of atom i is inside the
 // cutoff (r^2 < rc2).
 __device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int64_t i, int64_t cap,
@@ -53,14 +80,24 @@ __device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int
 // ---- quad layout: four lanes per atom ------------------------------------
 //
 // The site passes run one atom per aligned group of four lanes.  Lane q owns
-// the in-cutoff bonds c = q + 4 s (s = 0 .. kQuadSlots-1) of its atom, where
-// bond c is the c-th set bit of the atom's cutoff mask (ascending list
-// slot); the lanes exchange bond data with __shfl_xor inside the group.
-constexpr int kQuad = 4;
-constexpr int kQuadSlots = 2;                       // bonds per lane
-constexpr int kQuadBonds = kQuad * kQuadSlots;      // bonds per atom in the fast path
-static_assert(kQuadBonds == kSiteFastBonds, "quad capacity is the fast-path bond count");
+// the in-cutoff bonds c = q + 4 s (s = 0 .. SLOTS-1) of its atom, where bond
+// c is the c-th set bit of the atom's cutoff mask (ascending list slot); the
+// lanes exchange bond data with __shfl_xor inside the group.  Atoms with more
+// than 4 SLOTS in-cutoff bonds go to the overflow pass.
 static_assert(kQuadAtoms * kQuad == kBlock, "a quad block holds kQuadAtoms atoms");
+
+// Number of partner bond slots a wave must visit: the largest in-cutoff
+// count of its atoms, in slots (wave-uniform, so every lane joins the
+// shuffles).
+template <int SLOTS>
+__device__ __forceinline__ int wave_partner_slots(int kc)
+{
+    int tmax = 1;
+#pragma unroll
+    for (int t = 1; t < SLOTS; ++t)
+        if (__any(kc > kQuad * t)) tmax = t + 1;
+    return tmax;
+}
 
 __device__ __forceinline__ double quad_xor(double v, int k) { return __shfl_xor(v, k, kQuad); }
 __device__ __forceinline__ float quad_xor(float v, int k) { return __shfl_xor(v, k, kQuad); }

@@ -18,7 +18,13 @@ namespace mbmd {
 template <class T>
 struct SWK {
     T eps_A, B, p, q, sigma, asig, eps_lam, gsig;
+    int ip, iq;   // p and q as small non-negative integers, or -1
 };
+
+inline int small_int_exponent(double e)
+{
+    return (e >= 0.0 && e <= 16.0 && e == (double)(int)e) ? (int)e : -1;
+}
 
 template <class T>
 SWK<T> sw_constants(const SWParams& p)
@@ -32,6 +38,8 @@ SWK<T> sw_constants(const SWParams& p)
     k.asig = (T)(p.a * p.sigma);
     k.eps_lam = (T)(p.epsilon * p.lam);
     k.gsig = (T)(p.gamma * p.sigma);
+    k.ip = small_int_exponent(p.p);
+    k.iq = small_int_exponent(p.q);
     return k;
 }
 
@@ -39,8 +47,48 @@ __device__ __forceinline__ double s_exp(double x) { return exp(x); }
 __device__ __forceinline__ float s_exp(float x) { return expf(x); }
 __device__ __forceinline__ double s_pow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float s_pow(float x, float y) { return powf(x, y); }
-__device__ __forceinline__ double s_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float s_sqrt(float x) { return sqrtf(x); }
+
+// x^e for the exponents p and q: repeated multiplication when e is a small
+// non-negative integer (p = 4, q = 0 in the 1985 set), pow otherwise.
+template <class T>
+__device__ __forceinline__ T sw_power(T x, T e, int ie)
+{
+    if (ie < 0) return s_pow(x, e);
+    T r = T(1);
+    for (int k = 0; k < ie; ++k) r *= x;
+    return r;
+}
+
+// Per-bond quantities at length r (r < a sigma): E = exp(gamma sigma / (r - a sigma)),
+// qg = -d ln E / dr = gamma sigma / (r - a sigma)^2, the two-body term phi2(r)
+// and its derivative.
+template <class T>
+__device__ __forceinline__ void sw_bond(const SWK<T>& p, T r, T ir, T& E, T& qg, T& phi, T& dphi)
+{
+    const T idr = nr_rcp(r - p.asig);
+    E = s_exp(p.gsig * idr);
+    qg = p.gsig * idr * idr;
+    const T sr = p.sigma * ir;
+    const T srp = sw_power(sr, p.p, p.ip), srq = sw_power(sr, p.q, p.iq);
+    const T e2 = s_exp(p.sigma * idr);
+    const T poly = p.B * srp - srq;
+    const T dpoly = (-p.p * p.B * srp + p.q * srq) * ir;
+    phi = p.eps_A * poly * e2;
+    dphi = p.eps_A * dpoly * e2 - phi * p.sigma * idr * idr;
+}
+
+// Unit vector, length and inverse length of bond d (r^2 > 0).
+template <class T>
+__device__ __forceinline__ void sw_geometry(const Disp& d, T& ux, T& uy, T& uz, T& r, T& ir)
+{
+    const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    ir = nr_rsqrt(r2);
+    r = r2 * ir;
+    ux = dx * ir;
+    uy = dy * ir;
+    uz = dz * ir;
+}
 
 template <class T, int MAXC, bool FIXED>
 __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap, const double4& xi,
@@ -62,25 +110,9 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap,
             slot[c] = m;
             rem &= rem - 1;
             const int j = nl[(int64_t)m * cap + i];
-            const Disp d = cut_disp(xi, xw[j], box);
-            const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
-            const T r = s_sqrt(dx * dx + dy * dy + dz * dz);
-            const T ir = T(1) / r;
-            ux[c] = dx * ir;
-            uy[c] = dy * ir;
-            uz[c] = dz * ir;
-            rr[c] = r;
-            const T idr = T(1) / (r - p.asig);
-            ex[c] = s_exp(p.gsig * idr);
-            qg[c] = p.gsig * idr * idr;
-            // two-body term and its radial derivative
-            const T sr = p.sigma * ir;
-            const T srp = s_pow(sr, p.p), srq = s_pow(sr, p.q);
-            const T e2 = s_exp(p.sigma * idr);
-            const T poly = p.B * srp - srq;
-            const T dpoly = (-p.p * p.B * srp + p.q * srq) * ir;
-            const T phi = p.eps_A * poly * e2;
-            dph[c] = p.eps_A * dpoly * e2 - phi * p.sigma * idr * idr;
+            T ir, phi;
+            sw_geometry(cut_disp(xi, xw[j], box), ux[c], uy[c], uz[c], rr[c], ir);
+            sw_bond(p, rr[c], ir, ex[c], qg[c], phi, dph[c]);
             u_i += 0.5 * (double)phi;
         }
     }
@@ -100,7 +132,7 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap,
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         if (c < cnt) {
-            const T ir = T(1) / rr[c];
+            const T ir = nr_rcp(rr[c]);
             T dx = T(0.5) * dph[c] * ux[c], dy = T(0.5) * dph[c] * uy[c], dz = T(0.5) * dph[c] * uz[c];
 #pragma unroll
             for (int e = 0; e < (FIXED ? MAXC : cnt); ++e) {
@@ -123,30 +155,103 @@ __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap,
     }
 }
 
-template <class T, int MAXC>
+// Quad site pass: four lanes per atom, lane q owning bonds q, q + 4 and
+// q + 8 (the layout of the Tersoff quad pass with one more slot: SW crystals
+// near room temperature have 4 to 11 bonds inside the cutoff).  Each lane forms its bonds' E_c, qg_c
+// and two-body terms, then, over the partner bonds e fetched from the other
+// lanes, half of h_ce for U_i (each unordered pair is met from both ends)
+// and the three-body part of dU_i/dr_c.  Atoms with more than kQuadBonds
+// in-cutoff bonds go to the overflow list.
+template <class T, int SLOTS>
 __global__ void __launch_bounds__(kBlock)
-k_sw_partials(SWK<T> p, double rc2, Segs S, int M, int64_t cap, const double4* __restrict__ xw,
-              const int* __restrict__ nn, const int* __restrict__ nl,
-              unsigned long long* __restrict__ mask, double* __restrict__ U,
-              T* __restrict__ dpart, int* __restrict__ ovf_count, int* __restrict__ ovf_list)
+k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
+               const double4* __restrict__ xw, const int* __restrict__ nn,
+               const int* __restrict__ nl, unsigned long long* __restrict__ mask,
+               double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
+               int* __restrict__ ovf_list)
 {
+    const int q = threadIdx.x & (kQuad - 1);
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int sid = seg_of_block(S, lb, false);
+    const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
     if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
-    const int local = (lb - g.blk) * kBlock + threadIdx.x;
-    if (local >= g.n) return;
+    const Box box = g.box;
+    const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
     const int64_t i = g.atom_off + local;
-    const double4 xi = xw[i];
-    const int nnb = min(nn[i], M);
-    const unsigned long long msk = cutoff_mask(xi, i, cap, nnb, nl, xw, g.box, rc2);
-    mask[i] = msk;
+    const bool valid = local < g.n;
+    const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const int nnb = valid ? min(nn[i], M) : 0;
+    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2);
     const int cnt = __popcll(msk);
-    if (cnt > MAXC) {
-        ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
-        return;
+    const bool ovf = cnt > kQuad * SLOTS;
+    if (valid && q == 0) {
+        mask[i] = msk;
+        if (ovf) ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
     }
-    sw_site<T, MAXC, true>(p, i, cap, xi, msk, cnt, nl, xw, g.box, U, dpart);
+    const int kc = (valid && !ovf) ? cnt : 0;   // bonds handled by this quad
+
+    T ux[SLOTS], uy[SLOTS], uz[SLOTS], ir[SLOTS], ex[SLOTS],
+        qg[SLOTS], gx[SLOTS], gy[SLOTS], gz[SLOTS];
+    int slot[SLOTS];
+    double u_i = 0.0;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int c = q + kQuad * s;
+        ux[s] = uy[s] = uz[s] = ex[s] = qg[s] = gx[s] = gy[s] = gz[s] = T(0);
+        ir[s] = T(1);
+        slot[s] = 0;
+        if (c < kc) {
+            const int m = nth_set_bit(msk, c);
+            slot[s] = m;
+            const int j = nl[(int64_t)m * cap + i];
+            T r, phi, dphi;
+            sw_geometry(cut_disp(xi, xw[j], box), ux[s], uy[s], uz[s], r, ir[s]);
+            sw_bond(p, r, ir[s], ex[s], qg[s], phi, dphi);
+            u_i += 0.5 * (double)phi;
+            gx[s] = T(0.5) * dphi * ux[s];
+            gy[s] = T(0.5) * dphi * uy[s];
+            gz[s] = T(0.5) * dphi * uz[s];
+        }
+    }
+    const int tmax = wave_partner_slots<SLOTS>(kc);
+    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const T fx = k ? quad_xor(ux[t], k) : ux[t];
+            const T fy = k ? quad_xor(uy[t], k) : uy[t];
+            const T fz = k ? quad_xor(uz[t], k) : uz[t];
+            const T fe = k ? quad_xor(ex[t], k) : ex[t];
+            const int e = (q ^ k) + kQuad * t;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int c = q + kQuad * s;
+                if (c < kc && e < kc && e != c) {
+                    const T cs = ux[s] * fx + uy[s] * fy + uz[s] * fz;
+                    const T ang = cs + T(1) / T(3);
+                    const T ee = p.eps_lam * ex[s] * fe;
+                    const T h = ee * ang * ang;
+                    u_i += 0.5 * (double)h;
+                    const T radial = -h * qg[s];
+                    const T angular = T(2) * ee * ang * ir[s];
+                    gx[s] += radial * ux[s] + angular * (fx - cs * ux[s]);
+                    gy[s] += radial * uy[s] + angular * (fy - cs * uy[s]);
+                    gz[s] += radial * uz[s] + angular * (fz - cs * uz[s]);
+                }
+            }
+        }
+    }
+    u_i = quad_sum(u_i);
+    if (q == 0 && valid && !ovf) U[i] = u_i;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int c = q + kQuad * s;
+        if (c < kc) {
+            T* o = dpart + ((int64_t)slot[s] * cap + i) * 3;
+            o[0] = gx[s];
+            o[1] = gy[s];
+            o[2] = gz[s];
+        }
+    }
 }
 
 template <class T>
@@ -166,25 +271,24 @@ k_sw_partials_ovf(SWK<T> p, Segs S, int64_t cap, const double4* __restrict__ xw,
     }
 }
 
-constexpr int kSWTile = kSiteFastBonds;
 constexpr int kSWOvfGrid = 64;
 
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SWParams& p,
                               bool overflow_pass, int max_nn, hipStream_t s)
 {
-    if (S.nblk <= 0) return hipSuccess;
+    if (S.nblk_quad <= 0) return hipSuccess;
     if (!segs_ready(S, b)) return hipErrorInvalidValue;
     const SWK<T> k = sw_constants<T>(p);
     const double rc = p.a * p.sigma;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_sw_partials<T, kSWTile><<<S.nblk, kBlock, 0, s>>>(k, rc * rc, S, b.M, b.cap, b.xw[cur],
-                                                            b.nn, b.nl, b.mask, b.U, dp,
-                                                            b.ovf_count, b.ovf_list);
+        k_sw_site_quad<T, kSWSlots><<<S.nblk_quad, kBlock, 0, s>>>(k, rc * rc, S, b.M, b.cap, b.xw[cur],
+                                                         b.nn, b.nl, b.mask, b.U, dp,
+                                                         b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
+    if (b.M > kQuad * kSWSlots && max_nn > kQuad * kSWSlots)
         k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl, b.mask,
                                                            b.U, dp, b.ovf_count, b.ovf_list);
     return hipGetLastError();

@@ -26,6 +26,10 @@ namespace mbmd {
 template <class T>
 struct TersoffK {
     T A, B, lam, mu, beta, n, inv2n, c2, c2_d2, d2, h, R, pi_sr;
+    // b = (1 + u)^a, a = -1/(2n): binomial series coefficients a_k = C(a, k),
+    // used below u_series = 2^-9 where the first omitted term, |a_6| u^6, is
+    // below 2e-17 relative
+    T u_series, a1, a2, a3, a4, a5;
 };
 
 template <class T>
@@ -45,6 +49,15 @@ TersoffK<T> tersoff_constants(const TersoffParams& p)
     k.h = (T)p.h;
     k.R = (T)p.R;
     k.pi_sr = (T)(3.14159265358979323846 / (p.S - p.R));
+    const double a = -1.0 / (2.0 * p.n);
+    double ak[6] = {1.0, 0, 0, 0, 0, 0};
+    for (int j = 1; j < 6; ++j) ak[j] = ak[j - 1] * (a - (j - 1)) / j;
+    k.a1 = (T)ak[1];
+    k.a2 = (T)ak[2];
+    k.a3 = (T)ak[3];
+    k.a4 = (T)ak[4];
+    k.a5 = (T)ak[5];
+    k.u_series = (T)0x1p-9;
     return k;
 }
 
@@ -56,8 +69,6 @@ __device__ __forceinline__ double t_log1p(double x) { return log1p(x); }
 __device__ __forceinline__ float t_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ void t_sincos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
 
 // f_C and f_C' for r below S (the caller only passes in-cutoff bonds).
 template <class T>
@@ -78,16 +89,40 @@ template <class T>
 __device__ __forceinline__ void angular_g(const TersoffK<T>& p, T cs, T& g, T& dg)
 {
     const T t = p.h - cs;
-    const T iq = T(1) / (p.d2 + t * t);
+    const T iq = nr_rcp(p.d2 + t * t);
     g = T(1) + p.c2_d2 * t * t * iq;
     dg = T(-2) * p.c2 * t * iq * iq;
 }
 
+// b(zeta) and db/dzeta; b(0) = 1, db/dzeta(0) = 0.  With u = (beta zeta)^n,
+// b = (1 + u)^(-1/(2n)) is summed as its binomial series when u is small
+// (the usual case: u ~ 1e-4 in the crystal) and through exp/log1p otherwise.
 template <class T>
-__device__ __forceinline__ T angular_g_only(const TersoffK<T>& p, T cs)
+__device__ __forceinline__ void bond_order(const TersoffK<T>& p, T zeta, T& b, T& db)
 {
-    const T t = p.h - cs;
-    return T(1) + p.c2_d2 * t * t / (p.d2 + t * t);
+    b = T(1);
+    db = T(0);
+    if (zeta > T(0)) {
+        const T u = t_exp(p.n * t_log(p.beta * zeta));
+        if (u < p.u_series)
+            b = T(1) + u * (p.a1 + u * (p.a2 + u * (p.a3 + u * (p.a4 + u * p.a5))));
+        else
+            b = t_exp(-t_log1p(u) * p.inv2n);
+        db = -b * u * nr_rcp(T(2) * zeta * (T(1) + u));
+    }
+}
+
+// Unit vector, length and inverse length of bond d (r^2 > 0).
+template <class T>
+__device__ __forceinline__ void bond_geometry(const Disp& d, T& ux, T& uy, T& uz, T& r, T& ir)
+{
+    const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    ir = nr_rsqrt(r2);
+    r = r2 * ir;
+    ux = dx * ir;
+    uy = dy * ir;
+    uz = dz * ir;
 }
 
 template <class T, int MAXC, bool FIXED>
@@ -109,15 +144,9 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
             slot[c] = m;
             rem &= rem - 1;
             const int j = nl[(int64_t)m * cap + i];
-            const Disp d = cut_disp(xi, xw[j], box);
-            const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
-            const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
-            const T ir = T(1) / r;
-            ux[c] = dx * ir;
-            uy[c] = dy * ir;
-            uz[c] = dz * ir;
-            rr[c] = r;
-            cutoff_fc(p, r, fc[c], dfc[c]);
+            T ir;
+            bond_geometry(cut_disp(xi, xw[j], box), ux[c], uy[c], uz[c], rr[c], ir);
+            cutoff_fc(p, rr[c], fc[c], dfc[c]);
         }
     }
     // zeta_c over unordered pairs: g(cos_ce) is shared by zeta_c and zeta_e.
@@ -127,7 +156,8 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
         for (int e = c + 1; e < (FIXED ? MAXC : cnt); ++e) {
             if (e < cnt) {
                 const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
-                const T g = angular_g_only(p, cs);
+                T g, dg;
+                angular_g(p, cs, g, dg);
                 zp[c] += fc[e] * g;
                 zp[e] += fc[c] * g;
             }
@@ -139,13 +169,8 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         if (c < cnt) {
-            const T zeta = zp[c];
-            T b = T(1), db = T(0);
-            if (zeta > T(0)) {
-                const T u = t_exp(p.n * t_log(p.beta * zeta));
-                b = t_exp(-t_log1p(u) * p.inv2n);
-                db = -b * u / (T(2) * zeta * (T(1) + u));
-            }
+            T b, db;
+            bond_order(p, zp[c], b, db);
             const T fr = p.A * t_exp(-p.lam * rr[c]);
             const T fa = p.B * t_exp(-p.mu * rr[c]);
             u_i += (double)(fc[c] * (fr - b * fa));
@@ -158,7 +183,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         if (c < cnt) {
-            const T ir = T(1) / rr[c];
+            const T ir = nr_rcp(rr[c]);
             T dx = T(0.5) * pd[c] * ux[c], dy = T(0.5) * pd[c] * uy[c], dz = T(0.5) * pd[c] * uz[c];
 #pragma unroll
             for (int e = 0; e < (FIXED ? MAXC : cnt); ++e) {
@@ -185,8 +210,8 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
 // arithmetic is the one of tersoff_site, distributed over the quad: each lane
 // forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
 // bonds' unit vectors, f_C and P from the other lanes.  Atoms with more than
-// kQuadBonds in-cutoff bonds go to the overflow list.
-template <class T>
+// kQuad * SLOTS in-cutoff bonds go to the overflow list.
+template <class T, int SLOTS>
 __global__ void __launch_bounds__(kBlock)
 k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
                     const double4* __restrict__ xw, const int* __restrict__ nn,
@@ -207,42 +232,38 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     const int nnb = valid ? min(nn[i], M) : 0;
     const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2);
     const int cnt = __popcll(msk);
-    const bool ovf = cnt > kQuadBonds;
+    const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
         mask[i] = msk;
         if (ovf) ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
     }
     const int kc = (valid && !ovf) ? cnt : 0;   // bonds handled by this quad
 
-    T ux[kQuadSlots], uy[kQuadSlots], uz[kQuadSlots], rr[kQuadSlots], fc[kQuadSlots],
-        dfc[kQuadSlots], zp[kQuadSlots], pd[kQuadSlots];
-    int slot[kQuadSlots];
+    T ux[SLOTS], uy[SLOTS], uz[SLOTS], rr[SLOTS], ir[SLOTS],
+        fc[SLOTS], dfc[SLOTS], zp[SLOTS], pd[SLOTS];
+    int slot[SLOTS];
 #pragma unroll
-    for (int s = 0; s < kQuadSlots; ++s) {
+    for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
-        ux[s] = uy[s] = uz[s] = rr[s] = fc[s] = dfc[s] = zp[s] = pd[s] = T(0);
-        rr[s] = T(1);
+        ux[s] = uy[s] = uz[s] = fc[s] = dfc[s] = zp[s] = pd[s] = T(0);
+        rr[s] = ir[s] = T(1);
         slot[s] = 0;
         if (c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
             const int j = nl[(int64_t)m * cap + i];
-            const Disp d = cut_disp(xi, xw[j], box);
-            const T dx = (T)d.x, dy = (T)d.y, dz = (T)d.z;
-            const T r = t_sqrt(dx * dx + dy * dy + dz * dz);
-            const T ir = T(1) / r;
-            ux[s] = dx * ir;
-            uy[s] = dy * ir;
-            uz[s] = dz * ir;
-            rr[s] = r;
-            cutoff_fc(p, r, fc[s], dfc[s]);
+            bond_geometry(cut_disp(xi, xw[j], box), ux[s], uy[s], uz[s], rr[s], ir[s]);
+            cutoff_fc(p, rr[s], fc[s], dfc[s]);
         }
     }
-    // The second bond slot is needed only where some atom has more than kQuad
-    // bonds; the test is wave-uniform so that every lane joins the shuffles.
-    const int tmax = __any(kc > kQuad) ? kQuadSlots : 1;
+    const int tmax = wave_partner_slots<SLOTS>(kc);
 
-    // zeta_c = sum over partner bonds e != c of f_C(r_e) g(cos_ce)
+    // zeta_c = sum over partner bonds e != c of f_C(r_e) g(cos_ce).  g and g'
+    // of the angles between first-slot bonds (every angle of an atom with at
+    // most kQuad bonds) are kept for the derivative phase.
+    T g0[kQuad], dg0[kQuad];
+#pragma unroll
+    for (int k = 0; k < kQuad; ++k) g0[k] = dg0[k] = T(0);
     for (int t = 0; t < tmax; ++t) {
 #pragma unroll
         for (int k = 0; k < kQuad; ++k) {
@@ -252,11 +273,17 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
             const T ef = k ? quad_xor(fc[t], k) : fc[t];
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
-            for (int s = 0; s < kQuadSlots; ++s) {
+            for (int s = 0; s < SLOTS; ++s) {
                 const int c = q + kQuad * s;
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
-                    zp[s] += ef * angular_g_only(p, cs);
+                    T g, dg;
+                    angular_g(p, cs, g, dg);
+                    zp[s] += ef * g;
+                    if (s == 0 && t == 0) {
+                        g0[k] = g;
+                        dg0[k] = dg;
+                    }
                 }
             }
         }
@@ -264,16 +291,11 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     // bond orders, site energy, pd_c and P_c
     double u_i = 0.0;
 #pragma unroll
-    for (int s = 0; s < kQuadSlots; ++s) {
+    for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         if (c < kc) {
-            const T zeta = zp[s];
-            T b = T(1), db = T(0);
-            if (zeta > T(0)) {
-                const T u = t_exp(p.n * t_log(p.beta * zeta));
-                b = t_exp(-t_log1p(u) * p.inv2n);
-                db = -b * u / (T(2) * zeta * (T(1) + u));
-            }
+            T b, db;
+            bond_order(p, zp[s], b, db);
             const T fr = p.A * t_exp(-p.lam * rr[s]);
             const T fa = p.B * t_exp(-p.mu * rr[s]);
             u_i += (double)(fc[s] * (fr - b * fa));
@@ -286,10 +308,9 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     if (q == 0 && valid && !ovf && kc == 0) U[i] = 0.0;
 
     // partials dU_i/dr_c
-    T gx[kQuadSlots], gy[kQuadSlots], gz[kQuadSlots], ir[kQuadSlots];
+    T gx[SLOTS], gy[SLOTS], gz[SLOTS];
 #pragma unroll
-    for (int s = 0; s < kQuadSlots; ++s) {
-        ir[s] = T(1) / rr[s];
+    for (int s = 0; s < SLOTS; ++s) {
         gx[s] = T(0.5) * pd[s] * ux[s];
         gy[s] = T(0.5) * pd[s] * uy[s];
         gz[s] = T(0.5) * pd[s] * uz[s];
@@ -304,12 +325,17 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
             const T ep = k ? quad_xor(zp[t], k) : zp[t];
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
-            for (int s = 0; s < kQuadSlots; ++s) {
+            for (int s = 0; s < SLOTS; ++s) {
                 const int c = q + kQuad * s;
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
                     T g, dg;
-                    angular_g(p, cs, g, dg);
+                    if (s == 0 && t == 0) {
+                        g = g0[k];
+                        dg = dg0[k];
+                    } else {
+                        angular_g(p, cs, g, dg);
+                    }
                     const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
                     const T bb = T(-0.5) * ep * dfc[s] * g;
                     gx[s] += a * (ex - cs * ux[s]) + bb * ux[s];
@@ -320,7 +346,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
         }
     }
 #pragma unroll
-    for (int s = 0; s < kQuadSlots; ++s) {
+    for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         if (c < kc) {
             T* o = dpart + ((int64_t)slot[s] * cap + i) * 3;
@@ -363,12 +389,12 @@ hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
     const TersoffK<T> k = tersoff_constants<T>(p);
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_tersoff_site_quad<T><<<S.nblk_quad, kBlock, 0, s>>>(k, p.S * p.S, S, b.M, b.cap,
+        k_tersoff_site_quad<T, kTersoffSlots><<<S.nblk_quad, kBlock, 0, s>>>(k, p.S * p.S, S, b.M, b.cap,
                                                               b.xw[cur], b.nn, b.nl, b.mask, b.U,
                                                               dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kSiteFastBonds && max_nn > kSiteFastBonds)
+    if (b.M > kQuad * kTersoffSlots && max_nn > kQuad * kTersoffSlots)
         k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl,
                                                               b.mask, b.U, dp, b.ovf_count,
                                                               b.ovf_list);
