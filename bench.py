@@ -239,11 +239,20 @@ def bench_sw(mb, wl, torch, args):
     log(f"SW 1M: timed {steps} steps (+{args.warmup} warmup)")
     t, st, th, _, _ = W.timed("fp64", steps, args.warmup)
     l_list, k_cut = list_statistics(W.ctx, W.pos0, s, wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
+    psteps = min(args.profile_steps, steps)
+    W.ctx.set_profiling(True)
+    W.ctx.reset_profile()
+    W.run("fp64", psteps)
+    prof = W.ctx.profile()
+    W.ctx.set_profiling(False)
+    kernels = {k: {"launches": c, "avg_us": round(1e3 * ms / c, 3)}
+               for k, (c, ms) in prof.items() if c}
     W.close()
     log(f"SW 1M: {t:.3f} s, {s.n * steps / t:.4e} atom-steps/s")
     return {"value": s.n * steps / t, "unit": "atom-steps/s", "dtype": "f64", "steps": steps,
             "ms_per_step": 1e3 * t / steps, "rebuilds": st["rebuilds"],
             "energy_change_eV_per_atom": float((th[-1, 14] - th[0, 14]) / s.n),
+            "kernels": kernels,
             "config": {"workload": "sw_si_diamond_50x50x50_1000000_atoms_nve", "atoms": s.n,
                        "rebuild_every": 20, "skin_A": 0.5, "seed": 1003,
                        "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4)}}
@@ -321,7 +330,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
-    ap.add_argument("--serve-cap-mib", type=int, default=512)
+    ap.add_argument("--serve-cap-mib", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sw", action="store_true")

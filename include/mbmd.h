@@ -260,11 +260,23 @@ mbmd_status mbmd_batch_step(mbmd_ctx *ctx, mbmd_precision prec, int *n_active);
  * enqueued; the retire call waits for it. */
 mbmd_status mbmd_batch_finished(const mbmd_ctx *ctx, int *handles, int capacity, int *count);
 
-/* Copy a finished structure's final positions, velocities and per-atom U, F,
- * W, J into caller device buffers (any may be NULL), free its slot and atom
- * range, and synchronise the stream. */
+/* Enqueue the copy of a finished structure's final positions (wrapped),
+ * velocities and per-atom U, F, W, J into caller device buffers of its n
+ * atoms (layouts of mbmd_nve_run; any may be NULL) and free its slot and
+ * atom range at once (a later admission is ordered after the copy on the
+ * stream).  Asynchronous: the buffers hold the results once the stream has
+ * reached this point (mbmd_batch_sync).  MBMD_EBUSY if it has not finished,
+ * MBMD_EINVAL for an unknown handle.  Its thermo array is complete at the
+ * same point. */
 mbmd_status mbmd_batch_retire(mbmd_ctx *ctx, int handle, double *pos, double *vel, double *U,
                               double *F, double *W, double *J);
+
+/* Wait for everything enqueued on the context's stream and report the
+ * batch's status: MBMD_ENONFINITE if an admitted structure had a non-finite
+ * position, MBMD_ENEIGH if a list build overflowed the list capacity (the
+ * results of that build's structures are then wrong).  The status covers
+ * the whole batch since the previous sync and is cleared by the call. */
+mbmd_status mbmd_batch_sync(mbmd_ctx *ctx);
 
 /* Close the batch (device memory stays with the context). */
 mbmd_status mbmd_batch_close(mbmd_ctx *ctx);

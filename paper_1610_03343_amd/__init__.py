@@ -86,6 +86,7 @@ def _load():
         "mbmd_batch_step": ([P, I, C.POINTER(I)], I),
         "mbmd_batch_finished": ([P, C.POINTER(I), I, C.POINTER(I)], I),
         "mbmd_batch_retire": ([P, I, P, P, P, P, P, P], I),
+        "mbmd_batch_sync": ([P], I),
         "mbmd_batch_close": ([P], I),
     }
     for name, (args, res) in sig.items():
@@ -336,8 +337,14 @@ class Context:
                         "mbmd_batch_finished")
         return list(arr[: cnt.value])
 
+    def batch_sync(self):
+        """Wait for the stream; raises MbmdError on a batch-wide error status."""
+        self._check(_lib.mbmd_batch_sync(self._h), "mbmd_batch_sync")
+
     def batch_retire(self, handle: int, n: int, out=None):
-        """Copy a finished structure's final pos, vel, U, F, W, J out and free it."""
+        """Enqueue the copy of a finished structure's final pos, vel, U, F, W,
+        J into `out` (allocated if None) and free its slot; the values are
+        there once the stream reaches this point (batch_sync)."""
         if out is None:
             z = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
             out = dict(pos=z(3, n), vel=z(3, n), U=z(n), F=z(3, n), W=z(9, n), J=z(3, n))

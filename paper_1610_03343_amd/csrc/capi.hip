@@ -1086,11 +1086,8 @@ mbmd_status mbmd_batch_add(mbmd_ctx* c, int64_t n, const double box[3], const do
     sl.thermo = thermo;
     // positions into the buffer the next launch reads, velocities into the
     // batch state
-    hipError_t e = launch_load_positions(pos, nullptr, n, b, (int)at, c->buf.xw[B.cur],
-                                         c->buf.status, c->stream);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r)
-        e = hipMemcpyAsync(c->buf.vel + r * c->buf.ostride + at, vel + r * n, sizeof(double) * n,
-                           hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = launch_batch_admit(pos, vel, n, b, (int)at, c->buf.xw[B.cur], c->buf.vel,
+                                      c->buf.ostride, c->buf.status, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "batch add");
     auto it = std::lower_bound(B.slots.begin(), B.slots.end(), (int)at,
                                [](const Slot& x, int off) { return x.atom_off < off; });
@@ -1135,23 +1132,24 @@ mbmd_status mbmd_batch_retire(mbmd_ctx* c, int handle, double* pos, double* vel,
     if (!sl) return fail(c, MBMD_EINVAL, "unknown structure handle%s");
     if (!sl->done) return fail(c, MBMD_EBUSY, "structure has not finished%s");
     const Buffers& b = c->buf;
-    const int64_t os = b.ostride, at = sl->atom_off, n = sl->n;
     hipError_t e = hipSetDevice(c->device);
-    auto rows = [&](double* dst, const double* src, int nr) {
-        for (int r = 0; r < nr && e == hipSuccess; ++r)
-            e = hipMemcpyAsync(dst + r * n, src + r * os + at, sizeof(double) * n,
-                               hipMemcpyDeviceToDevice, c->stream);
-    };
-    if (pos && e == hipSuccess) e = launch_store_positions(b.xw[sl->final_buf], (int)at, n, pos,
-                                                           c->stream);
-    if (vel) rows(vel, b.vel, 3);
-    if (U) rows(U, b.U, 1);
-    if (F) rows(F, b.F, 3);
-    if (W) rows(W, b.W, 9);
-    if (J) rows(J, b.J, 3);
+    if (e == hipSuccess)
+        e = launch_batch_copy_out(b.xw[sl->final_buf], b.vel, b.U, b.F, b.W, b.J, b.ostride,
+                                  sl->atom_off, sl->n, pos, vel, U, F, W, J, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "batch retire");
+    // the range can be handed out at once: a later admission's copy-in is
+    // ordered after this copy-out on the stream
     B.slots.erase(B.slots.begin() + (sl - B.slots.data()));
     B.changed = true;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_batch_sync(mbmd_ctx* c)
+{
+    if (!c) return MBMD_EINVAL;
+    if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     return finish(c);
 }
 

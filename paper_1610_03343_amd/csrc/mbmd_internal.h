@@ -158,6 +158,18 @@ inline bool segs_ready(const Segs& S, const Buffers& b)
            S.nblk <= b.blk_cap;
 }
 
+// x folded into [0, L): x - L floor(x / L), unfused, with the rounding
+// corner cases (a result of exactly L, or below 0) folded back.
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+#pragma clang fp contract(off)
+    double r = x - L * floor(x / L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    if (r < 0.0 || r >= L) r = 0.0;
+    return r;
+}
+
 __host__ __device__ inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 __host__ __device__ inline int quad_blocks_for(int64_t n) { return (int)((n + kQuadAtoms - 1) / kQuadAtoms); }
 
@@ -167,6 +179,19 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
                                  Box box, int atom_off, double4* xw, unsigned* status,
                                  hipStream_t s);
+// Serving batch: wraps positions pos[3][n] into xw[atom_off ..) and copies
+// velocities vel[3][n] into vel_dst (row stride `stride`) at atom_off.
+hipError_t launch_batch_admit(const double* pos, const double* vel, int64_t n, Box box,
+                              int atom_off, double4* xw, double* vel_dst, int64_t stride,
+                              unsigned* status, hipStream_t s);
+// Serving batch: copies one structure's final positions (from xw), velocities
+// and U, F, W, J (row stride `stride`, from atom_off) into caller arrays of n
+// atoms; any output may be null.
+hipError_t launch_batch_copy_out(const double4* xw, const double* vel, const double* U,
+                                 const double* F, const double* W, const double* J,
+                                 int64_t stride, int atom_off, int64_t n, double* pos_o,
+                                 double* vel_o, double* U_o, double* F_o, double* W_o,
+                                 double* J_o, hipStream_t s);
 // Copies xw[atom_off ..) back to pos[3][n].
 hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, double* pos_soa,
                                   hipStream_t s);

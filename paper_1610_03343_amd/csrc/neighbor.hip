@@ -15,16 +15,6 @@
 
 namespace mbmd {
 
-__device__ __forceinline__ double wrap_coord(double x, double L)
-{
-#pragma clang fp contract(off)
-    double r = x - L * floor(x / L);
-    if (r < 0.0) r += L;
-    if (r >= L) r -= L;
-    if (r < 0.0 || r >= L) r = 0.0;
-    return r;
-}
-
 __device__ __forceinline__ double list_r2(const double4& a, const double4& b, const Box& box)
 {
 #pragma clang fp contract(off)

@@ -27,16 +27,6 @@
 
 namespace mbmd {
 
-__device__ __forceinline__ double wrap_coord_pf(double x, double L)
-{
-#pragma clang fp contract(off)
-    double r = x - L * floor(x / L);
-    if (r < 0.0) r += L;
-    if (r >= L) r -= L;
-    if (r < 0.0 || r >= L) r = 0.0;
-    return r;
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -158,7 +148,7 @@ k_pair_gather(Segs S, int M, int64_t cap, int64_t os, StepArgs a, const double4*
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 vn[c] = v[c] + g.half_dt_acc * f[c];
-                x[c] = wrap_coord_pf(x[c] + g.dt * vn[c], box.L[c]);
+                x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
             }
             vel[i] = vn[0];
             vel[os + i] = vn[1];

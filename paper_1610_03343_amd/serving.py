@@ -81,6 +81,13 @@ def _dev(a, device):
     return torch.tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T), device=device)
 
 
+def _dev_async(a, device):
+    """(n, 3) host array -> (3, n) device tensor through pinned memory, without
+    waiting for the copy (it is ordered before later work on the stream)."""
+    host = torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T))
+    return host.pin_memory().to(device, non_blocking=True)
+
+
 def _result_views(buf):
     return {"U": buf[0], "F": buf[1:4], "W": buf[4:13], "J": buf[13:16], "pos": buf[16:19],
             "vel": buf[19:22]}
@@ -142,8 +149,8 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
                 job = waiting[0]
                 th = torch.empty(job.n_steps + 1, THERMO_COLS, dtype=torch.float64, device=dev)
                 try:
-                    h = ctx.batch_add(_dev(job.pos, dev), _dev(job.vel, dev), job.box, job.mass,
-                                      job.dt, job.n_steps, thermo=th)
+                    h = ctx.batch_add(_dev_async(job.pos, dev), _dev_async(job.vel, dev), job.box,
+                                      job.mass, job.dt, job.n_steps, thermo=th)
                 except MbmdError as e:
                     if e.code != MBMD_EBUSY:
                         raise
@@ -162,21 +169,33 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
             ctx.batch_step(precision)
             stats.loop_steps += 1
             fin = ctx.batch_finished()
+            if not fin:
+                continue
+            # retire every finished structure (asynchronous copies into
+            # pinned host buffers), then wait once for all of them
+            done = []
             for h in fin:
                 job = in_flight.pop(h)
                 buf = torch.empty(RESULT_ROWS, job.n, dtype=torch.float64, device=dev)
-                out = _result_views(buf)
-                th = ctx.batch_retire(h, job.n, out).get("thermo")
-                host = buf.cpu()
-                stats.latencies_s[job.rid] = clock() - t0 - (0.0 if saturate else job.arrival_s)
+                th = ctx.batch_retire(h, job.n, _result_views(buf)).get("thermo")
+                host = torch.empty(RESULT_ROWS, job.n, dtype=torch.float64, pin_memory=True)
+                host.copy_(buf, non_blocking=True)
+                th_host = None
+                if keep_results and th is not None:
+                    th_host = torch.empty(th.shape, dtype=torch.float64, pin_memory=True)
+                    th_host.copy_(th, non_blocking=True)
+                done.append((job, host, th_host))
+            ctx.batch_sync()
+            now = clock() - t0
+            for job, host, th_host in done:
+                stats.latencies_s[job.rid] = now - (0.0 if saturate else job.arrival_s)
                 stats.atom_steps += job.n * max(1, job.n_steps)
                 if keep_results:
                     r = _unstack(host)
-                    if th is not None:
-                        r["thermo"] = th.cpu()
+                    if th_host is not None:
+                        r["thermo"] = th_host
                     results[job.rid] = r
-            if fin:
-                free_atoms, free_slots, largest = ctx.batch_capacity()
+            free_atoms, free_slots, largest = ctx.batch_capacity()
         stats.makespan_s = clock() - t0
     finally:
         ctx.batch_close()

@@ -81,7 +81,7 @@ def test_batch_equals_alone_bitwise(pot, precision):
                 idx = handles.pop(h)
                 n = systems[idx].n
                 out = ctx.batch_retire(h, n)
-                torch.cuda.synchronize()
+                ctx.batch_sync()
                 got[idx] = {k: v.cpu().numpy() for k, v in out.items()}
             assert step < 200
         ctx.batch_close()
@@ -107,7 +107,7 @@ def test_batch_single_points_match_oracle(pot):
         for h in fin:
             s = systems[hs[h]]
             out = ctx.batch_retire(h, s.n)
-            torch.cuda.synchronize()
+            ctx.batch_sync()
             ref = oracle_compute(pot, s)
             for k in ("U", "F", "W", "J"):
                 g = out[k].cpu().numpy()
