@@ -24,7 +24,9 @@ Also measured, as extra fields of the same line:
   serving  a Poisson request trace through the continuous-batching loop and
            through one structure per launch, p50/p99 latency to results on
            the host, both precisions, and an HBM-capped batch
-  roofline the dominant kernel's achieved HBM bandwidth from HIP events
+  roofline the dominant kernel against its bound, timed with HIP events: the
+           Tersoff site pass against the FP64 vector peak (algorithmic
+           FLOPs), the pairwise pass against HBM bandwidth (algorithmic bytes)
   cpu_baseline  the CPU oracle on a bounded sample of the headline workload
 
 Prints ONE JSON line.  Progress goes to stderr.
@@ -45,6 +47,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s, Tersoff Si 512k atoms (FP64 vs mixed); p50/p99 batched latency"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tersoff_512k_fp64_hbm_traffic.md")
 
 
@@ -69,6 +72,29 @@ def algorithmic_bytes(kernel: str, k_cut: float, l_list: float, dsize: int) -> f
     if kernel == "neighbor_build":
         return 24 + 4 + 8 * l_list
     return 0.0
+
+
+# FP64 operations (FMA = 2) of the special functions as this build compiles
+# them for gfx950 (read from the kernels' assembly), used as their weights
+EXP_FLOPS, LOG_FLOPS, RCP_FLOPS, RSQRT_FLOPS = 30, 80, 9, 13
+
+
+def tersoff_site_flops(mean_L, mean_K, mean_KK):
+    """Algorithmic FP64 operations per atom of the Tersoff site pass.
+
+    mean_L: list entries, mean_K: in-cutoff bonds K, mean_KK: mean of K(K-1)
+    (ordered angles).  Per list entry: minimum-image displacement and r^2 (20).
+    Per bond: length and unit vector (rsqrt + 4), f_R and f_A (exp + 2 each),
+    bond order b and db/dzeta (log + exp + 14 for the series and the
+    reciprocal + 1), energy and pair-derivative terms (17).  Per unordered
+    angle: cosine (5) and g, g' (10 + rcp).  Per ordered angle: the zeta
+    term (2) and the partial-derivative accumulation (27).  Bonds in the
+    cutoff taper (none in the 300 K crystal) would add a sincos each.
+    """
+    per_bond = (RSQRT_FLOPS + 4) + 2 * (EXP_FLOPS + 2) + (LOG_FLOPS + EXP_FLOPS + 14 + RCP_FLOPS + 2) + 17
+    per_pair = 5 + 10 + RCP_FLOPS
+    per_ordered = 2 + 27
+    return 20 * mean_L + per_bond * mean_K + per_pair * mean_KK / 2 + per_ordered * mean_KK
 
 
 def kernel_source_hash() -> str:
@@ -102,21 +128,22 @@ def measured_traffic(kind: str):
 
 
 def list_statistics(ctx, pos_dev, sysm, cutoff):
-    """Mean list length and mean in-cutoff count of the GPU-built list."""
+    """Mean list length, mean in-cutoff count K and mean K(K-1) of the
+    GPU-built list at the input positions."""
     import numpy as np
     nn, nl = ctx.neighbors(pos_dev, sysm.box)
     nn_h = nn.cpu().numpy()
     nl_h = nl.cpu().numpy()
     n = sysm.n
     idx = np.arange(n)
-    kc = 0
+    k = np.zeros(n, dtype=np.int64)
     for m in range(int(nn_h.max())):
         have = nn_h > m
         j = nl_h[m, have]
         d = sysm.pos[j] - sysm.pos[idx[have]]
         d -= sysm.box * np.rint(d / sysm.box)
-        kc += int(np.sum(np.sum(d * d, axis=1) < cutoff ** 2))
-    return float(nn_h.mean()), kc / n
+        k[have] += np.sum(d * d, axis=1) < cutoff ** 2
+    return float(nn_h.mean()), float(k.mean()), float((k * (k - 1)).mean())
 
 
 def drift_per_ps(thermo, n, dt_fs):
@@ -238,7 +265,8 @@ def bench_sw(mb, wl, torch, args):
     steps = args.sw_steps
     log(f"SW 1M: timed {steps} steps (+{args.warmup} warmup)")
     t, st, th, _, _ = W.timed("fp64", steps, args.warmup)
-    l_list, k_cut = list_statistics(W.ctx, W.pos0, s, wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
+    l_list, k_cut, _ = list_statistics(W.ctx, W.pos0, s,
+                                       wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
     psteps = min(args.profile_steps, steps)
     W.ctx.set_profiling(True)
     W.ctx.reset_profile()
@@ -357,7 +385,7 @@ def main():
     n = s.n
     every, skin = 20, 0.5
     W = Workload(mb, wl, torch, s, "tersoff", every, skin, 16)
-    l_list, k_cut = list_statistics(W.ctx, W.pos0, s, wl.TERSOFF_SI_1989["S"])
+    l_list, k_cut, k_kk = list_statistics(W.ctx, W.pos0, s, wl.TERSOFF_SI_1989["S"])
 
     log(f"timed FP64 run: {args.warmup} warmup + {args.steps} steps")
     t64, st64, th64, _, _ = W.timed("fp64", args.steps, args.warmup)
@@ -381,17 +409,30 @@ def main():
         kernels[name] = {"launches": launches, "avg_us": round(avg_us, 3),
                          "algorithmic_bytes_per_atom": round(b, 1),
                          "achieved_GBs": round(b * n / (avg_us * 1e-6) / 1e9, 1) if b else None}
+    flops_atom = tersoff_site_flops(l_list, k_cut, k_kk)
+    sk = kernels["site_partials"]
+    sk["algorithmic_flops_per_atom"] = round(flops_atom, 1)
+    sk["achieved_TFLOPs"] = round(flops_atom * n / (sk["avg_us"] * 1e-6) / 1e12, 3)
     dom = max(("site_partials", "pair_gather"), key=lambda k: prof[k][1])
     dk = kernels[dom]
-    achieved = dk["achieved_GBs"]
     traffic, traffic_parts = measured_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_us": dk["avg_us"],
-                "algorithmic_bytes_per_launch": round(dk["algorithmic_bytes_per_atom"] * n)}
+    if dom == "site_partials":
+        # bound by FP64 vector arithmetic (transcendentals), not by HBM
+        achieved = dk["achieved_TFLOPs"]
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": traffic, "kernel": dom, "avg_us": dk["avg_us"],
+                    "algorithmic_flops_per_launch": round(flops_atom * n),
+                    "hbm_achieved_GBs": dk["achieved_GBs"]}
+    else:
+        achieved = dk["achieved_GBs"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": dom, "avg_us": dk["avg_us"],
+                    "algorithmic_bytes_per_launch": round(dk["algorithmic_bytes_per_atom"] * n)}
     if traffic_parts:
         roofline["traffic_parts"] = traffic_parts
-    log(f"dominant kernel {dom}: {dk['avg_us']} us, {achieved} GB/s")
+    log(f"dominant kernel {dom}: {dk['avg_us']} us, {achieved} {roofline['unit']}")
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib * (1 << 20)
@@ -433,7 +474,8 @@ def main():
                    "rebuild_every": every, "skin_A": skin, "rebuild_policy": "fixed",
                    "per_step_outputs": "U, F, W(9), J(3) per atom + thermo row",
                    "seed": 1002, "parallelism": "single_gpu",
-                   "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4)},
+                   "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4),
+                   "mean_ordered_angles": round(k_kk, 4)},
         "fp64_run": {"rebuilds": st64["rebuilds"],
                      "energy_change_eV_per_atom": float((th64[-1, 14] - th64[0, 14]) / n)},
         "mixed": mixed,

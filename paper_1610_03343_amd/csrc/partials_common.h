@@ -99,25 +99,51 @@ __device__ __forceinline__ int wave_partner_slots(int kc)
     return tmax;
 }
 
-__device__ __forceinline__ double quad_xor(double v, int k) { return __shfl_xor(v, k, kQuad); }
-__device__ __forceinline__ float quad_xor(float v, int k) { return __shfl_xor(v, k, kQuad); }
+// Value of lane (q xor k) of the same quad, k = 1, 2, 3 a compile-time
+// constant after unrolling: a DPP quad permutation (a register move inside
+// the vector unit, no LDS round trip).  Every lane of the wave is active at
+// each call site.
+template <int K>
+__device__ __forceinline__ int quad_xor_i32(int v)
+{
+    static_assert(K >= 1 && K <= 3, "quad partner");
+    // quad_perm selectors: lane l of each quad reads lane l ^ K
+    constexpr int ctrl = K == 1 ? 0xB1 : (K == 2 ? 0x4E : 0x1B);
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
+}
+template <int K>
+__device__ __forceinline__ double quad_xor_k(double v)
+{
+    const int lo = quad_xor_i32<K>(__double2loint(v));
+    const int hi = quad_xor_i32<K>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int K>
+__device__ __forceinline__ float quad_xor_k(float v)
+{
+    return __int_as_float(quad_xor_i32<K>(__float_as_int(v)));
+}
+template <class T>
+__device__ __forceinline__ T quad_xor(T v, int k)
+{
+    return k == 0 ? v : (k == 1 ? quad_xor_k<1>(v) : (k == 2 ? quad_xor_k<2>(v) : quad_xor_k<3>(v)));
+}
 
 __device__ __forceinline__ unsigned long long quad_or(unsigned long long v)
 {
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-#pragma unroll
-    for (int k = 1; k < kQuad; k <<= 1) {
-        lo |= __shfl_xor(lo, k, kQuad);
-        hi |= __shfl_xor(hi, k, kQuad);
-    }
-    return ((unsigned long long)hi << 32) | lo;
+    int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+    lo |= quad_xor_i32<1>(lo);
+    hi |= quad_xor_i32<1>(hi);
+    lo |= quad_xor_i32<2>(lo);
+    hi |= quad_xor_i32<2>(hi);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
 // Fixed-order sum over the quad: ((l0 + l1) + (l2 + l3)) on every lane.
 __device__ __forceinline__ double quad_sum(double v)
 {
-    v += __shfl_xor(v, 1, kQuad);
-    v += __shfl_xor(v, 2, kQuad);
+    v += quad_xor_k<1>(v);
+    v += quad_xor_k<2>(v);
     return v;
 }
 
@@ -129,16 +155,21 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long msk, int c)
 }
 
 // Cutoff mask of atom i computed by its quad: lane q tests slots q, q+4, ...
+// and keeps the displacement of its first slot in d_first (the bond that
+// lane owns first whenever the atom's first slots are all in the cutoff).
 __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi, int64_t i,
                                                                int64_t cap, int nnb, int q,
                                                                const int* __restrict__ nl,
                                                                const double4* __restrict__ xw,
-                                                               const Box& box, double rc2)
+                                                               const Box& box, double rc2,
+                                                               Disp& d_first)
 {
     unsigned long long msk = 0;
+    d_first = Disp{0.0, 0.0, 0.0, 0.0};
     for (int m = q; m < nnb; m += kQuad) {
         const int j = nl[(int64_t)m * cap + i];
         const Disp d = cut_disp(xi, xw[j], box);
+        if (m == q) d_first = d;
         if (d.r2 < rc2) msk |= 1ull << m;
     }
     return quad_or(msk);

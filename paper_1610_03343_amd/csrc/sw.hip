@@ -181,7 +181,8 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
     const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int nnb = valid ? min(nn[i], M) : 0;
-    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2);
+    Disp d_first;
+    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
@@ -203,9 +204,9 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
         if (c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
-            const int j = nl[(int64_t)m * cap + i];
             T r, phi, dphi;
-            sw_geometry(cut_disp(xi, xw[j], box), ux[s], uy[s], uz[s], r, ir[s]);
+            const Disp d = (s == 0 && m == q) ? d_first : cut_disp(xi, xw[nl[(int64_t)m * cap + i]], box);
+            sw_geometry(d, ux[s], uy[s], uz[s], r, ir[s]);
             sw_bond(p, r, ir[s], ex[s], qg[s], phi, dphi);
             u_i += 0.5 * (double)phi;
             gx[s] = T(0.5) * dphi * ux[s];
@@ -214,7 +215,9 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
         }
     }
     const int tmax = wave_partner_slots<SLOTS>(kc);
-    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+        if (t >= tmax) break;   // wave-uniform
 #pragma unroll
         for (int k = 0; k < kQuad; ++k) {
             const T fx = k ? quad_xor(ux[t], k) : ux[t];

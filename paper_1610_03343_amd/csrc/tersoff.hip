@@ -63,7 +63,39 @@ TersoffK<T> tersoff_constants(const TersoffParams& p)
 
 __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
-__device__ __forceinline__ double t_log(double x) { return log(x); }
+// Natural logarithm of a positive normal double for the bond order, from
+// ln x = e ln 2 + ln m with x = m 2^e, m in [sqrt(1/2), sqrt(2)), and the
+// series ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
+// |s| < 0.172, summed to s^21 (first omitted term below 1e-17 relative).
+// A few ulp, against the correctly rounded library log at about half the
+// arithmetic; (beta zeta)^n needs far less.
+__device__ __forceinline__ double t_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);               // x = m 2^e, m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * nr_rcp(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double lnm = 2.0 * s + 2.0 * s * s2 * p;
+    // ln 2 = ln2_hi + ln2_lo, ln2_hi with 32 significant bits (e * ln2_hi is
+    // exact for |e| < 2^21), ln2_lo the rounded remainder
+    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    const double de = (double)e;
+    return fma(de, ln2_hi, fma(de, ln2_lo, lnm));
+}
 __device__ __forceinline__ float t_log(float x) { return logf(x); }
 __device__ __forceinline__ double t_log1p(double x) { return log1p(x); }
 __device__ __forceinline__ float t_log1p(float x) { return log1pf(x); }
@@ -230,7 +262,8 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int nnb = valid ? min(nn[i], M) : 0;
-    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2);
+    Disp d_first;
+    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
@@ -251,8 +284,8 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
         if (c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
-            const int j = nl[(int64_t)m * cap + i];
-            bond_geometry(cut_disp(xi, xw[j], box), ux[s], uy[s], uz[s], rr[s], ir[s]);
+            const Disp d = (s == 0 && m == q) ? d_first : cut_disp(xi, xw[nl[(int64_t)m * cap + i]], box);
+            bond_geometry(d, ux[s], uy[s], uz[s], rr[s], ir[s]);
             cutoff_fc(p, rr[s], fc[s], dfc[s]);
         }
     }
@@ -264,7 +297,9 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     T g0[kQuad], dg0[kQuad];
 #pragma unroll
     for (int k = 0; k < kQuad; ++k) g0[k] = dg0[k] = T(0);
-    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+        if (t >= tmax) break;   // wave-uniform
 #pragma unroll
         for (int k = 0; k < kQuad; ++k) {
             const T ex = k ? quad_xor(ux[t], k) : ux[t];
@@ -315,7 +350,9 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
         gy[s] = T(0.5) * pd[s] * uy[s];
         gz[s] = T(0.5) * pd[s] * uz[s];
     }
-    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+        if (t >= tmax) break;   // wave-uniform
 #pragma unroll
         for (int k = 0; k < kQuad; ++k) {
             const T ex = k ? quad_xor(ux[t], k) : ux[t];
