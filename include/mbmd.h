@@ -170,11 +170,13 @@ mbmd_status mbmd_bind_workspace(mbmd_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Build the neighbour list of n atoms at device positions pos[3][n] and copy
  * it out: nn[n] (device, true count per atom) and nl[max_neighbors][n]
- * (device, slot-major, ascending atom index in each list; unused slots are
- * left untouched).  Atom j is listed for atom i iff j != i and the
- * minimum-image squared distance, evaluated in FP64 as
- * (dx*dx + dy*dy) + dz*dz with d <- d - L rint(d/L) and no fused multiply-add,
- * is below (cutoff + skin)^2. */
+ * (device, slot-major; unused slots are left untouched).  Atom j is listed
+ * for atom i iff j != i and the minimum-image squared distance, evaluated in
+ * FP64 as (dx*dx + dy*dy) + dz*dz with d <- d - L rint(d/L) and no fused
+ * multiply-add, is below (cutoff + skin)^2 (the Verlet list over a cell list
+ * of Section 2.1).  Each list holds the neighbours inside the potential
+ * cutoff first, then the others, each group by ascending atom index: a
+ * deterministic order, so every per-atom sum over the list is reproducible. */
 mbmd_status mbmd_neighbors(mbmd_ctx *ctx, int64_t n, const double box[3], const double *pos,
                            int32_t *nn, int32_t *nl);
 

@@ -366,7 +366,7 @@ hipError_t build(mbmd_ctx* c, int total_cells, int cur, bool readback = true)
     {
         ProfScope ps(c, P_BUILD);
         e = launch_build_neighbors(c->buf, c->segs, total_cells, cur, cutoff_of(c) + c->skin,
-                                   c->stream);
+                                   cutoff_of(c), c->stream);
     }
     if (!readback) {
         c->max_nn = kMaxSlots;

@@ -15,7 +15,8 @@
 //   xbuild[N]        double4 positions at the last list build
 //   nn[N]            int32 list count (true count, may exceed M on overflow)
 //   nl[M][N]         int32 neighbour index, slot-major (lane i reads nl[m*N+i]
-//                    coalesced), ascending index within each atom
+//                    coalesced); neighbours inside the potential cutoff at
+//                    build time first, each group by ascending index
 //   rev[M][N]        int32 slot of i inside the list of nl[m][i]
 //   mask[N]          uint64 bit m set iff slot m lies inside the potential cutoff
 //   dpart[M][N][3]   T: dU_i/dr_ij for list slot m (written for in-cutoff slots only)
@@ -195,10 +196,11 @@ hipError_t launch_batch_copy_out(const double4* xw, const double* vel, const dou
 // Copies xw[atom_off ..) back to pos[3][n].
 hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, double* pos_soa,
                                   hipStream_t s);
-// Builds the sorted lists and reverse slots of every segment with build != 0
-// and the largest count over them (maxnn).
+// Builds the lists and reverse slots of every segment with build != 0 and
+// the largest count of each (maxnn).  Lists hold the neighbours inside rcut
+// at build time first, each group by ascending index.
 hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
-                                  double rlist, hipStream_t s);
+                                  double rlist, double rcut, hipStream_t s);
 
 // overflow_pass = false: the fast four-lanes-per-atom pass over every atom;
 // true: the pass over the atoms the first one left over.  max_nn bounds the

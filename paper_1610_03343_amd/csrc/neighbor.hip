@@ -3,9 +3,10 @@
 // The neighbour list of atom i holds every j != i whose minimum-image squared
 // distance is below r_list^2 = (cutoff + skin)^2 (the Verlet list over a cell
 // list that the paper uses because f_C vanishes beyond the cutoff; Section
-// 2.1).  Entries are sorted by ascending index, so the list - and every sum
-// that runs over it - does not depend on the order in which atoms were
-// binned, which is the only place integer atomics appear.
+// 2.1).  Entries are ordered by a key of their own (inside the potential
+// cutoff at build time first, then by ascending index), so the list - and
+// every sum that runs over it - does not depend on the order in which atoms
+// were binned, which is the only place integer atomics appear.
 //
 // The inclusion test d = x_j - x_i, d <- d - L rint(d / L),
 // r^2 = (dx*dx + dy*dy) + dz*dz < r_list^2 is evaluated in FP64 with no
@@ -237,13 +238,13 @@ constexpr int kSearchBlock = kBlock / 2;
 // only those near the boundary take the exact unfused test above, whose
 // rounding error is many orders of magnitude below that margin.
 __device__ __forceinline__ bool in_list(const double4& a, const double4& b, const Box& box,
-                                        double rl2, double rl2_lo, double rl2_hi)
+                                        double rl2, double rl2_lo, double rl2_hi, double& r2)
 {
     double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
     dx -= box.L[0] * rint(dx * box.inv[0]);
     dy -= box.L[1] * rint(dy * box.inv[1]);
     dz -= box.L[2] * rint(dz * box.inv[2]);
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rl2_lo) return true;
     if (r2 > rl2_hi) return false;
     return list_r2(a, b, box) < rl2;
@@ -253,8 +254,14 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // LDS (column-major over the block so that neighbouring threads hit distinct
 // banks), then written out slot-major.  Search blocks hold kBlock atoms like
 // the other per-atom kernels but run as two halves of kSearchBlock threads.
+// The list is ordered by the key (r^2 >= rc2, j): the neighbours inside the
+// potential cutoff at build time first, each group by ascending index, so
+// the pairwise pass can stop at the last in-cutoff slot.  The grouping only
+// steers work (every step recomputes which slots are in the cutoff); the
+// order is a deterministic function of the positions.
 __global__ void __launch_bounds__(kSearchBlock)
-k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, double rl2_hi, int M,
+k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, double rl2_hi,
+         double rc2, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
          const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
          int* __restrict__ maxnn, unsigned* __restrict__ status)
@@ -290,26 +297,29 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
                     for (int p = start[cc]; p < e; ++p) {
                         const int j = cell_atoms[p];
                         if (j == (int)i) continue;
-                        if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi)) {
-                            // insertion into the sorted LDS list (capacity M)
+                        double r2;
+                        if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi, r2)) {
+                            // insertion into the LDS list (capacity M) ordered by key
+                            const unsigned key = (unsigned)j | (r2 < rc2 ? 0u : 0x80000000u);
                             int q = cnt < M ? cnt : M;
-                            while (q > 0 && buf[(q - 1) * kSearchBlock] > j) {
+                            while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
                                 if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
                                 --q;
                             }
-                            if (q < M) buf[q * kSearchBlock] = j;
+                            if (q < M) buf[q * kSearchBlock] = (int)key;
                             ++cnt;
                         }
                     }
                 }
             }
         }
-        // On overflow the stored entries are the M smallest indices; the
-        // status bit turns the call into an error.
+        // On overflow the stored entries are the M smallest keys; the status
+        // bit turns the call into an error.
         if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
         nn[i] = cnt;
         const int w = cnt < M ? cnt : M;
-        for (int m = 0; m < w; ++m) nl[(int64_t)m * cap + i] = buf[m * kSearchBlock];
+        for (int m = 0; m < w; ++m)
+            nl[(int64_t)m * cap + i] = buf[m * kSearchBlock] & 0x7fffffff;
     }
     // largest count of the block, one atomic per block
     int mx = cnt;
@@ -345,7 +355,7 @@ k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M,
 }
 
 hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
-                                  double rlist, hipStream_t s)
+                                  double rlist, double rcut, hipStream_t s)
 {
     if (S.nblk <= 0) return hipSuccess;
     if (!S.seg || S.nseg > b.seg_cap || total_cells > b.cell_cap) return hipErrorInvalidValue;
@@ -365,7 +375,8 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
     k_search<<<2 * S.nblk, kSearchBlock, lds, s>>>(S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10),
-                                                   rl2 * (1.0 + 1e-10), b.M, b.cap, b.cell_of,
+                                                   rl2 * (1.0 + 1e-10), rcut * rcut, b.M, b.cap,
+                                                   b.cell_of,
                                                    b.cell_start, b.cell_atoms, b.nn, b.nl,
                                                    b.maxnn, b.status);
     k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);

@@ -57,9 +57,9 @@ __device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_pair_gather(Segs S, int M, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
+k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
               double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
-              const int* __restrict__ nn, const int* __restrict__ nl,
+              const int* __restrict__ nl,
               const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
               const T* __restrict__ dpart, const double* __restrict__ U,
               double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
@@ -86,8 +86,9 @@ k_pair_gather(Segs S, int M, int64_t cap, int64_t os, StepArgs a, const double4*
     if (local < g.n) {
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
-        const int nnb = min(nn[i], M);
-        for (int m = 0; m < nnb; ++m) {
+        // the in-cutoff slots lead the list: stop after the last one
+        const int mend = msk ? 64 - __clzll((long long)msk) : 0;
+        for (int m = 0; m < mend; ++m) {
             if (!((msk >> m) & 1ull)) continue;
             const int j = nl[(int64_t)m * cap + i];
             const int rs = rev[(int64_t)m * cap + i];
@@ -295,7 +296,7 @@ hipError_t launch_pair_gather(const Buffers& b, const Segs& S, const StepArgs& a
     if (S.nblk <= 0) return hipSuccess;
     if (!segs_ready(S, b) || !b.F || !b.W || !b.J || !b.U) return hipErrorInvalidValue;
     k_pair_gather<T><<<S.nblk, kBlock, 0, s>>>(
-        S, b.M, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nn, b.nl, b.rev,
+        S, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nl, b.rev,
         b.mask, static_cast<const T*>(b.dpart), b.U, b.vel, b.F, b.W, b.J, b.ovf_count);
     return hipGetLastError();
 }

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workload as wl
-from gpu_util import (RLIST, TOL_FP64, TOL_MIXED_F, context, gpu_compute, min_image,
+from gpu_util import (PARAMS, RLIST, TOL_FP64, TOL_MIXED_F, context, gpu_compute, min_image,
                       oracle_compute, rel, to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -45,8 +45,17 @@ def test_neighbor_lists_bitexact(pot, name):
         nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
     onn, onl = oracle.neighbors(s.pos, s.box, RLIST[pot], M, method="brute")
     assert np.array_equal(nn, onn)
+    # exact as index sets; the library orders each list as the neighbours
+    # inside the potential cutoff first, then the others, each ascending
+    rc = PARAMS[pot]["S"] if pot == "tersoff" else PARAMS[pot]["a"] * PARAMS[pot]["sigma"]
     for i in range(s.n):
-        assert np.array_equal(nl[:nn[i], i], onl[i, :onn[i]]), i
+        got = nl[:nn[i], i]
+        assert np.array_equal(np.sort(got), onl[i, :onn[i]]), i
+        d = min_image(s.pos[got] - s.pos[i], s.box)
+        inside = np.sum(d * d, axis=1) < rc * rc
+        k = int(inside.sum())
+        assert inside[:k].all() and not inside[k:].any(), i
+        assert np.all(np.diff(got[:k]) > 0) and np.all(np.diff(got[k:]) > 0), i
 
 
 @pytest.mark.parametrize("pot", ["tersoff", "sw"])
