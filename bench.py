@@ -243,6 +243,14 @@ def bench_mixed(W, args):
             "max_abs_dF_eV_per_A": float((omx["F"] - o64["F"]).abs().max()),
             "max_abs_dU_i_eV": float((omx["U"] - o64["U"]).abs().max())})
     same = bool(torch.equal(pos, pos_mx) and torch.equal(vel, vel_mx))
+    # per-kernel durations of the mixed path (HIP events, separate pass)
+    W.ctx.set_profiling(True)
+    W.ctx.reset_profile()
+    W.run("mixed", min(args.profile_steps, steps))
+    prof = W.ctx.profile()
+    W.ctx.set_profiling(False)
+    kernels = {k: {"launches": c, "avg_us": round(1e3 * ms / c, 3)}
+               for k, (c, ms) in prof.items() if c}
     return {
         "value": n * steps / tmx, "unit": "atom-steps/s", "steps": steps,
         "ms_per_step": 1e3 * tmx / steps, "rebuilds": stmx["rebuilds"],
@@ -255,6 +263,7 @@ def bench_mixed(W, args):
         "energy_change_eV_per_atom": {"mixed": float((th_mx[-1, 14] - th_mx[0, 14]) / n),
                                       "fp64": float((th_64[-1, 14] - th_64[0, 14]) / n)},
         "chunked_run_bitwise_equal": same,
+        "kernels": kernels,
     }
 
 

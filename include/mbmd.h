@@ -204,6 +204,13 @@ mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
                          double dt_fs, int n_steps, int rebuild_every, double *U, double *F,
                          double *W, double *J, double *thermo);
 
+/* Wait for everything this context enqueued on its stream and report (and
+ * clear) the device status word: MBMD_ENONFINITE, MBMD_ENEIGH or
+ * MBMD_EINVAL (atom type) for a condition raised since the last report,
+ * MBMD_EDEVICE if the stream failed.  mbmd_compute and mbmd_nve_run already
+ * end with this; it is the completion point of the asynchronous batch calls. */
+mbmd_status mbmd_sync(mbmd_ctx *ctx);
+
 /* ---- serving batch ------------------------------------------------------
  *
  * Continuous batching of independent structures (the serving form of the

@@ -87,6 +87,7 @@ def _load():
         "mbmd_batch_finished": ([P, C.POINTER(I), I, C.POINTER(I)], I),
         "mbmd_batch_retire": ([P, I, P, P, P, P, P, P], I),
         "mbmd_batch_sync": ([P], I),
+        "mbmd_sync": ([P], I),
         "mbmd_batch_close": ([P], I),
     }
     for name, (args, res) in sig.items():
@@ -336,6 +337,10 @@ class Context:
             self._check(_lib.mbmd_batch_finished(self._h, arr, len(arr), C.byref(cnt)),
                         "mbmd_batch_finished")
         return list(arr[: cnt.value])
+
+    def sync(self):
+        """Wait for the context's stream; raises MbmdError on a device status."""
+        self._check(_lib.mbmd_sync(self._h), "mbmd_sync")
 
     def batch_sync(self):
         """Wait for the stream; raises MbmdError on a batch-wide error status."""

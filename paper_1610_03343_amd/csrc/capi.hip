@@ -1144,13 +1144,20 @@ mbmd_status mbmd_batch_retire(mbmd_ctx* c, int handle, double* pos, double* vel,
     return MBMD_OK;
 }
 
+mbmd_status mbmd_sync(mbmd_ctx* c)
+{
+    if (!c) return MBMD_EINVAL;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if (!c->ws) return MBMD_OK;   // nothing was ever enqueued
+    return finish(c);
+}
+
 mbmd_status mbmd_batch_sync(mbmd_ctx* c)
 {
     if (!c) return MBMD_EINVAL;
     if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    return finish(c);
+    return mbmd_sync(c);
 }
 
 }  // extern "C"

@@ -59,12 +59,18 @@ __device__ __forceinline__ T sw_power(T x, T e, int ie)
     return r;
 }
 
-// Per-bond quantities at length r (r < a sigma): E = exp(gamma sigma / (r - a sigma)),
+// Per-bond quantities at length r: E = exp(gamma sigma / (r - a sigma)),
 // qg = -d ln E / dr = gamma sigma / (r - a sigma)^2, the two-body term phi2(r)
-// and its derivative.
+// and its derivative.  The bond is inside the cutoff by the FP64 test on r^2;
+// r formed in the working precision can still round to a sigma or above, where
+// every term and derivative takes its limit 0 (the exponent would overflow).
 template <class T>
 __device__ __forceinline__ void sw_bond(const SWK<T>& p, T r, T ir, T& E, T& qg, T& phi, T& dphi)
 {
+    if (!(r < p.asig)) {
+        E = qg = phi = dphi = T(0);
+        return;
+    }
     const T idr = nr_rcp(r - p.asig);
     E = s_exp(p.gsig * idr);
     qg = p.gsig * idr * idr;

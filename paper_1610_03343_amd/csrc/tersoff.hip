@@ -30,6 +30,7 @@ struct TersoffK {
     // used below u_series = 2^-9 where the first omitted term, |a_6| u^6, is
     // below 2e-17 relative
     T u_series, a1, a2, a3, a4, a5;
+    T S;
 };
 
 template <class T>
@@ -48,6 +49,7 @@ TersoffK<T> tersoff_constants(const TersoffParams& p)
     k.d2 = (T)(p.d * p.d);
     k.h = (T)p.h;
     k.R = (T)p.R;
+    k.S = (T)p.S;
     k.pi_sr = (T)(3.14159265358979323846 / (p.S - p.R));
     const double a = -1.0 / (2.0 * p.n);
     double ak[6] = {1.0, 0, 0, 0, 0, 0};
@@ -102,12 +104,17 @@ __device__ __forceinline__ float t_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ void t_sincos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
 
-// f_C and f_C' for r below S (the caller only passes in-cutoff bonds).
+// f_C and f_C' (the caller only passes bonds inside the cutoff by the FP64
+// test on r^2; r formed in the working precision that rounds to S or above
+// takes the limit 0).
 template <class T>
 __device__ __forceinline__ void cutoff_fc(const TersoffK<T>& p, T r, T& fc, T& dfc)
 {
     if (r < p.R) {
         fc = T(1);
+        dfc = T(0);
+    } else if (!(r < p.S)) {
+        fc = T(0);
         dfc = T(0);
     } else {
         T s, c;

@@ -32,21 +32,19 @@ def _systems():
 SYSTEMS = _systems()
 
 
-@pytest.mark.parametrize("pot", ["tersoff", "sw"])
-@pytest.mark.parametrize("name", list(SYSTEMS))
-def test_neighbor_lists_bitexact(pot, name):
+def _check_lists(pot, s, max_neighbors=None):
+    """GPU lists against the oracle's brute-force lists: exact as index sets,
+    and ordered as the library states (neighbours inside the potential
+    cutoff first, then the others, each by ascending index)."""
     import oracle
     import torch
-    s = SYSTEMS[name]
-    with context(pot) as ctx:
+    with context(pot, max_neighbors=max_neighbors) as ctx:
         M = ctx.max_neighbors
         nn, nl = ctx.neighbors(to_dev(s.pos), s.box)
         torch.cuda.synchronize()
         nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
     onn, onl = oracle.neighbors(s.pos, s.box, RLIST[pot], M, method="brute")
     assert np.array_equal(nn, onn)
-    # exact as index sets; the library orders each list as the neighbours
-    # inside the potential cutoff first, then the others, each ascending
     rc = PARAMS[pot]["S"] if pot == "tersoff" else PARAMS[pot]["a"] * PARAMS[pot]["sigma"]
     for i in range(s.n):
         got = nl[:nn[i], i]
@@ -56,6 +54,20 @@ def test_neighbor_lists_bitexact(pot, name):
         k = int(inside.sum())
         assert inside[:k].all() and not inside[k:].any(), i
         assert np.all(np.diff(got[:k]) > 0) and np.all(np.diff(got[k:]) > 0), i
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_neighbor_lists_bitexact(pot, name):
+    _check_lists(pot, SYSTEMS[name])
+
+
+@pytest.mark.parametrize("pot,a", [("tersoff", 4.2), ("sw", 4.9)])
+def test_neighbor_lists_dense_lattice(pot, a):
+    """A compressed lattice with 5 to 8 atoms per search cell and lists of up
+    to 28 neighbours (capacity 32): exact index sets, stated order."""
+    _check_lists(pot, wl.silicon_crystal(6 if pot == "tersoff" else 5, seed=321, sigma=0.05, a=a),
+                 max_neighbors=32)
 
 
 @pytest.mark.parametrize("pot", ["tersoff", "sw"])
@@ -72,14 +84,39 @@ def test_compute_fp64_parity(pot, name):
 @pytest.mark.parametrize("pot,cells,a,M", [("tersoff", 2, 4.2, 32), ("sw", 3, 4.2, 64)])
 def test_compressed_lattice_overflow_path(pot, cells, a, M):
     """A compressed lattice puts 16 (Tersoff) or 28 (SW) neighbours inside
-    the cutoff, beyond the 8-neighbour register tile: every atom takes the
-    overflow kernel."""
+    the cutoff, beyond the fast site path (8 bonds for Tersoff, 12 for SW):
+    every atom takes the overflow kernel."""
     s = wl.silicon_crystal(cells, seed=41, sigma=0.05, a=a)
     ref = oracle_compute(pot, s)
     with context(pot, max_neighbors=M) as ctx:
         got = gpu_compute(ctx, s)
     for k in ("U", "F", "W", "J"):
         assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bond_at_the_cutoff_edge(pot, precision):
+    """A bond 1e-9 A inside the cutoff is in the list and in the cutoff mask
+    (FP64 test on r^2) while its length rounds to the cutoff in FP32: every
+    term takes its limit at the cutoff, so the forces stay finite and match
+    the oracle."""
+    rc = PARAMS[pot]["S"] if pot == "tersoff" else PARAMS[pot]["a"] * PARAMS[pot]["sigma"]
+    d = rc - 1e-9
+    pos = np.array([[6.0, 6.0, 6.0], [6.0 + d, 6.0, 6.0], [6.0, 8.3, 6.1], [8.1, 7.9, 6.4]])
+    rng = np.random.default_rng(9)
+    s = wl.System(pos=pos, vel=rng.normal(0, 0.01, size=(4, 3)), box=np.array([20.0, 20.0, 20.0]),
+                  seed=9)
+    ref = oracle_compute(pot, s)
+    with context(pot) as ctx:
+        got = gpu_compute(ctx, s, precision=precision)
+    for k in ("U", "F", "W", "J"):
+        assert np.all(np.isfinite(got[k])), k
+    if precision == "fp64":
+        for k in ("U", "F", "W", "J"):
+            assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+    else:
+        assert np.max(np.abs(got["F"] - ref["F"])) <= TOL_MIXED_F
 
 
 @pytest.mark.parametrize("pot", ["tersoff", "sw"])

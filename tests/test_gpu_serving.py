@@ -116,6 +116,49 @@ def test_batch_single_points_match_oracle(pot):
         ctx.batch_close()
 
 
+@pytest.mark.parametrize("pot,M", [("tersoff", 32), ("sw", 64)])
+def test_batch_with_overflow_structures_bitwise(pot, M):
+    """Compressed lattices, whose atoms exceed the fast site path, share the
+    batch with ordinary crystals: the batch's overflow pass (always enqueued
+    there) serves them, and every result equals the same structure alone."""
+    import torch
+    c = 2 if pot == "tersoff" else 3
+    systems = [wl.silicon_crystal(c, seed=51, sigma=0.05, a=4.2),
+               wl.silicon_crystal((3, 3, 2), seed=52, sigma=0.1),
+               wl.silicon_crystal(c, seed=53, sigma=0.05, a=4.4)]
+    nsteps = [3, 5, 0]
+    every = 5
+    alone = []
+    with context(pot, max_neighbors=M) as ctx:
+        ctx.set_rebuild_policy("fixed")
+        for s, k in zip(systems, nsteps):
+            alone.append(_alone(ctx, s, k, "fp64", every))
+    got = {}
+    with context(pot, max_neighbors=M) as ctx:
+        ctx.batch_open(4000, 4, every)
+        handles = {}
+        for idx, (s, k) in enumerate(zip(systems, nsteps)):
+            th = torch.empty(k + 1, 16, dtype=torch.float64, device="cuda:0")
+            handles[ctx.batch_add(to_dev(s.pos), to_dev(s.vel), s.box, wl.M_SI, 1.0, k,
+                                  thermo=th)] = idx
+        steps = 0
+        while handles:
+            ctx.batch_step("fp64")
+            steps += 1
+            for h in ctx.batch_finished():
+                idx = handles.pop(h)
+                out = ctx.batch_retire(h, systems[idx].n)
+                ctx.batch_sync()
+                got[idx] = {k: v.cpu().numpy() for k, v in out.items()}
+            assert steps < 50
+        ctx.batch_close()
+    for idx, a in enumerate(alone):
+        for k in ("U", "F", "W", "J", "pos", "vel"):
+            assert np.array_equal(a[k], got[idx][k]), (idx, k)
+        if "thermo" in a:
+            assert np.array_equal(a["thermo"], got[idx]["thermo"]), idx
+
+
 def test_batch_admission_limits_and_errors():
     import paper_1610_03343_amd as mb
     s = wl.silicon_crystal(2, seed=7)
@@ -144,8 +187,22 @@ def test_batch_admission_limits_and_errors():
         ctx.batch_step()
         assert ctx.batch_finished() == [h1]
         ctx.batch_retire(h1, s.n)
+        ctx.batch_sync()
         assert ctx.batch_capacity() == (150, 2, 150)
+        # a non-finite position is reported by the next sync, once
+        bad = s.pos.copy()
+        bad[3, 1] = np.nan
+        h3 = ctx.batch_add(to_dev(bad), to_dev(s.vel), s.box, wl.M_SI, 1.0, 0)
+        ctx.batch_step()
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.batch_sync()
+        assert e.value.code == mb.MBMD_ENONFINITE
+        ctx.batch_sync()
+        assert ctx.batch_finished() == [h3]
+        ctx.batch_retire(h3, s.n)
+        ctx.sync()
         ctx.batch_close()
+        ctx.sync()
 
 
 def test_serving_loop_trace_and_identity():
