@@ -127,6 +127,26 @@ def measured_traffic(kind: str):
                                                    "write": float(m.group(2))}
 
 
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "tersoff_512k_fp64_valu_counters.md")
+# wave64 VALU instruction issue: 4 cycles per instruction on each of
+# 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu_insts(kind: str):
+    """VALU instructions per launch of a kernel class from the committed
+    counter summary, or None if missing or taken on other kernel sources."""
+    try:
+        text = open(COUNTER_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(rf"^valu\s+{re.escape(kind)}:\s*insts_per_launch=([0-9.e+]+)", text, re.M)
+    return float(m.group(1)) if m else None
+
+
 def list_statistics(ctx, pos_dev, sysm, cutoff):
     """Mean list length, mean in-cutoff count K and mean K(K-1) of the
     GPU-built list at the input positions."""
@@ -441,6 +461,11 @@ def main():
                     "algorithmic_bytes_per_launch": round(dk["algorithmic_bytes_per_atom"] * n)}
     if traffic_parts:
         roofline["traffic_parts"] = traffic_parts
+    insts = measured_valu_insts(dom)
+    if insts is not None:
+        # share of the kernel's time the vector units spend issuing its
+        # counted VALU instructions (counters from the committed summary)
+        roofline["valu_issue_frac"] = round(insts / VALU_ISSUE_PER_S / (dk["avg_us"] * 1e-6), 4)
     log(f"dominant kernel {dom}: {dk['avg_us']} us, {achieved} {roofline['unit']}")
 
     if args.calib_copy_mib > 0:
