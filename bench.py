@@ -20,7 +20,12 @@ Also measured, as extra fields of the same line:
            oracle at step 0 and against the FP64 path on the mixed
            trajectory every --mixed-check steps, total-energy drift of both
            paths (eV/atom/ps, linear fit)
+  repeats  further timed FP64 runs: median/min/max and whether the outputs
+           (x, v, F, W, J, thermo) are the same bits every time
   sw_1m    Stillinger-Weber (1985) Si, 50x50x50 cells = 1,000,000 atoms, FP64
+  speed_vs_n  throughput of both potentials and precisions for crystals of
+           5^3 to 70^3 cells (1,000 to 2,744,000 atoms), and Tersoff FP64
+           with the list rebuilt every 5 steps
   serving  a Poisson request trace through the continuous-batching loop and
            through one structure per launch, p50/p99 latency to results on
            the host, both precisions, and an HBM-capped batch
@@ -361,6 +366,39 @@ def bench_serving(mb, wl, torch, args):
     return res
 
 
+def bench_sweep(mb, wl, torch, args):
+    """Throughput against system size: diamond crystals of n^3 cells
+    (N = 8 n^3), 300 K, sigma 0.05 A, both potentials and precisions, list
+    rebuilt every 20 steps, plus the Tersoff FP64 case rebuilt every 5."""
+    rows = []
+    sizes = [int(x) for x in args.sweep_cells.split(",") if x]
+    for n in sizes:
+        sysm = wl.silicon_crystal(n, seed=1100 + n, sigma=0.05)
+        for pot, prec, every in (("tersoff", "fp64", 20), ("tersoff", "mixed", 20),
+                                 ("sw", "fp64", 20), ("sw", "mixed", 20), ("tersoff", "fp64", 5)):
+            W = Workload(mb, wl, torch, sysm, pot, every, 0.5, 16 if pot == "tersoff" else 32)
+            t, _, _, _, _ = W.timed(prec, args.sweep_steps, args.sweep_steps // 10)
+            W.close()
+            rows.append({"cells": n, "atoms": sysm.n, "potential": pot, "precision": prec,
+                         "rebuild_every": every,
+                         "atom_steps_per_s": sysm.n * args.sweep_steps / t,
+                         "us_per_step": 1e6 * t / args.sweep_steps})
+        log(f"sweep: {n}^3 cells ({sysm.n} atoms) done")
+    return {"steps": args.sweep_steps, "rows": rows}
+
+
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def run_cpu_baseline(sysm, steps):
     import oracle
     import workload as wl
@@ -369,9 +407,11 @@ def run_cpu_baseline(sysm, steps):
     oracle.nve("tersoff", wl.TERSOFF_SI_1989, sysm.pos, sysm.vel, sysm.box, wl.M_SI, steps, 1.0,
                3.5, 20, 16, check_skin=False)
     dt = time.perf_counter() - t0
+    model, ncpu = host_cpu()
     return {"value": sysm.n * steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{sysm.n}-atom Tersoff Si, {steps} NVE steps (one list build, "
-                      f"{steps + 1} force evaluations), single thread, {dt:.1f} s"}
+                      f"{steps + 1} force evaluations), single thread, {dt:.1f} s",
+            "host_cpu": model, "host_logical_cpus": ncpu}
 
 
 def main():
@@ -388,6 +428,11 @@ def main():
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-cap-mib", type=int, default=64)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed FP64 runs for median/min/max and an output check")
+    ap.add_argument("--sweep-cells", default="5,10,15,20,30,40,50,60,70",
+                    help="cells per axis of the size sweep (empty: no sweep)")
+    ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sw", action="store_true")
@@ -420,6 +465,21 @@ def main():
     t64, st64, th64, _, _ = W.timed("fp64", args.steps, args.warmup)
     value = n * args.steps / t64
     log(f"FP64: {t64:.3f} s, {value:.4e} atom-steps/s, rebuilds {st64['rebuilds']}")
+    # repetitions: spread of the timing, and the same bits every time
+    rep_ms, digests = [1e3 * t64 / args.steps], []
+    for _ in range(args.repeats):
+        tr, _, thr, pr, vr = W.timed("fp64", args.steps, 0)
+        rep_ms.append(1e3 * tr / args.steps)
+        h = hashlib.sha256()
+        for a in (pr, vr, W.out["F"], W.out["W"], W.out["J"]):
+            h.update(a.cpu().numpy().tobytes())
+        h.update(thr.tobytes())
+        digests.append(h.hexdigest())
+    repeats = {"ms_per_step": [round(x, 4) for x in rep_ms],
+               "median_ms_per_step": round(sorted(rep_ms)[len(rep_ms) // 2], 4),
+               "min_ms_per_step": round(min(rep_ms), 4), "max_ms_per_step": round(max(rep_ms), 4),
+               "outputs_identical": len(set(digests)) <= 1}
+    log(f"repeats: {repeats}")
 
     # HIP-event profiled pass of the same workload: per-kernel durations
     psteps = min(args.profile_steps, args.steps)
@@ -484,6 +544,7 @@ def main():
     W.close()
     sw = None if args.no_sw else bench_sw(mb, wl, torch, args)
     serve = None if args.no_serving else bench_serving(mb, wl, torch, args)
+    sweep = bench_sweep(mb, wl, torch, args) if args.sweep_cells else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -510,11 +571,13 @@ def main():
                    "seed": 1002, "parallelism": "single_gpu",
                    "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4),
                    "mean_ordered_angles": round(k_kk, 4)},
+        "repeats": repeats,
         "fp64_run": {"rebuilds": st64["rebuilds"],
                      "energy_change_eV_per_atom": float((th64[-1, 14] - th64[0, 14]) / n)},
         "mixed": mixed,
         "sw_1m": sw,
         "serving": serve,
+        "speed_vs_n": sweep,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
