@@ -52,6 +52,11 @@ def _load():
         lib.ora_nve.argtypes = [C.c_int, P, C.c_long, _dp, C.c_double, _dp, _dp, C.c_int,
                                 C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                 _dp, _dp, _dp, _dp, P, C.POINTER(C.c_long)]
+        D = C.c_double
+        lib.ora_npt.argtypes = [C.c_int, P, C.c_long, _dp, D, _dp, _dp, C.c_int, D, D, C.c_int,
+                                C.c_int, D, D, D, D, D, _dp, _dp, _dp, _dp, _dp, _dp,
+                                C.POINTER(C.c_long)]
+        lib.ora_npt.restype = C.c_int
         lib.ora_wrap.argtypes = [C.c_long, _dp, _dp]
         lib.ora_wrap.restype = None
         for name in ("ora_tersoff_g", "ora_tersoff_g_literal", "ora_tersoff_b", "ora_tersoff_db"):
@@ -167,6 +172,51 @@ def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: fl
     if st:
         raise OracleError(st)
     return dict(pos=pos, vel=vel, U=U, F=F, W=W, J=J, thermo=thermo, builds=builds.value)
+
+
+# 1 eV/A^3 in GPa
+EV_PER_A3_IN_GPA = 160.21766208
+
+
+def npt(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: float,
+        rlist: float, rebuild_every: int, maxnb: int, T0: float, tau_T: float, P0_GPa: float,
+        tau_P: float, beta_per_GPa: float):
+    """Velocity-Verlet with Berendsen weak coupling (see ora_npt).  P0 in GPa,
+    compressibility beta in 1/GPa; tau_T, tau_P in fs (<= 0: that coupling
+    off).  Returns dict(pos, vel, box, U, F, W, J, thermo[n_steps+1, 16],
+    box_traj[n_steps+1, 3], builds)."""
+    lib = _load()
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    boxc = _f64(box).copy()
+    n = pos.shape[0]
+    U = np.zeros(n)
+    F = np.zeros((n, 3))
+    W = np.zeros((n, 9))
+    J = np.zeros((n, 3))
+    thermo = np.zeros((n_steps + 1, 16))
+    box_traj = np.zeros((n_steps + 1, 3))
+    if potential == "tersoff":
+        pr, pid = tersoff_params(params), 0
+    else:
+        pr, pid = sw_params(params), 1
+    builds = C.c_long(0)
+    st = lib.ora_npt(pid, C.cast(C.byref(pr), C.c_void_p), n, boxc, float(mass), pos, vel,
+                     int(n_steps), float(dt), float(rlist), int(rebuild_every), int(maxnb),
+                     float(T0), float(tau_T), float(P0_GPa) / EV_PER_A3_IN_GPA, float(tau_P),
+                     float(beta_per_GPa) * EV_PER_A3_IN_GPA, U, F, W, J, thermo, box_traj,
+                     C.byref(builds))
+    if st:
+        raise OracleError(st)
+    return dict(pos=pos, vel=vel, box=boxc, U=U, F=F, W=W, J=J, thermo=thermo,
+                box_traj=box_traj, builds=builds.value)
+
+
+def pressure_GPa(thermo_row, box):
+    """Pressure of a thermo row in a box: (2 E_kin + tr W) / (3 V), in GPa."""
+    row = np.asarray(thermo_row)
+    v = float(np.prod(box))
+    return (2.0 * row[1] + row[2] + row[6] + row[10]) / (3.0 * v) * EV_PER_A3_IN_GPA
 
 
 def tersoff_g(params, cs: float, literal: bool = False) -> float:

@@ -29,7 +29,11 @@
  *     (the paper names SW in Section 2.4 but prints no formula; the form is
  *     the 1985 one: two-body phi_2 split half/half, three-body h_ijk assigned
  *     wholly to its vertex atom i);
- *   - velocity-Verlet NVE integration (Section 3).
+ *   - velocity-Verlet NVE integration (Section 3);
+ *   - velocity-Verlet in the NPT ensemble with the Berendsen weak-coupling
+ *     thermostat and barostat, the ensemble of the paper's benchmarks
+ *     (Section 3; the paper names it without formulas: the scaling factors
+ *     are Berendsen's, applied after each step's second half-kick).
  *
  * Readings where the paper is silent (all also recorded in the design doc):
  *   - f_C, f_R, f_A are Tersoff's 1989 forms: f_R = A exp(-lambda r),
@@ -671,6 +675,100 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
     }
     free(G);
     free(xb);
+    free(nn);
+    free(nl);
+    if (n_builds) *n_builds = builds;
+    return st;
+}
+
+/* Pressure (eV/A^3) of a thermo row in a box of volume V: the kinetic part
+ * 2 E_kin / 3 plus a third of the trace of the total virial, over V. */
+static double row_pressure(const double *row, double volume)
+{
+    return (2.0 * row[1] + row[2] + row[6] + row[10]) / (3.0 * volume);
+}
+
+/* Velocity-Verlet with Berendsen weak coupling (NPT).  The step sequence of
+ * ora_nve, and after the thermo row of every step except the last:
+ *   lambda = sqrt(1 + (dt / tau_T) (T0 / T - 1))   (T from that row; 1 if
+ *            tau_T <= 0 or T <= 0),
+ *   mu = (1 - (beta dt / tau_P) (P0 - P))^(1/3)     (P from that row and the
+ *            current volume; 1 if tau_P <= 0),
+ *   v <- lambda v,  x <- mu x,  box <- mu box  (isotropic).
+ * P0 in eV/A^3, beta (compressibility) in A^3/eV.  box is updated in place;
+ * box_traj (or NULL) receives [n_steps + 1][3], the box each step's forces
+ * were evaluated in.  The list is built at step 0 and every rebuild_every
+ * steps (in the box of that moment).  With tau_T <= 0 and tau_P <= 0 the
+ * run is ora_nve's with check_skin off, operation for operation. */
+int ora_npt(int potential, const void *params, long n, double *box, double mass, double *pos,
+            double *vel, int n_steps, double dt, double rlist, int rebuild_every, int maxnb,
+            double T0, double tau_T, double P0, double tau_P, double beta, double *U,
+            double *F, double *W, double *J, double *thermo, double *box_traj, long *n_builds)
+{
+    if (n < 2 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !(mass > 0.0) || !thermo)
+        return ORA_EINVAL;
+    int st = check_box(box, rlist);
+    if (st) return st;
+    int *nn = (int *)malloc(sizeof(int) * (size_t)n);
+    int *nl = (int *)malloc(sizeof(int) * (size_t)n * maxnb);
+    double *G = (double *)malloc(sizeof(double) * (size_t)n * maxnb * 3);
+    if (!nn || !nl || !G) { free(nn); free(nl); free(G); return ORA_ENOMEM; }
+    ora_wrap(n, box, pos);
+    st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
+    long builds = 1;
+    int last_build = 0;
+    const double half = 0.5 * dt * ORA_KAPPA / mass;
+    for (int s = 0; s <= n_steps && !st; ++s) {
+        if (s > 0) {
+            for (long i = 0; i < n; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    vel[i * 3 + a] += half * F[i * 3 + a];
+                    pos[i * 3 + a] += dt * vel[i * 3 + a];
+                }
+            ora_wrap(n, box, pos);
+            if (s - last_build == rebuild_every) {
+                st = check_box(box, rlist);
+                if (!st) st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
+                if (st) break;
+                last_build = s;
+                ++builds;
+            }
+        }
+        /* J pairs r(s) with v(s): at step 0 the evaluation forms it from the
+         * given velocities, later from the captured partials after the
+         * second half-kick (as in ora_nve) */
+        st = evaluate(potential, params, n, box, pos, s == 0 ? vel : NULL, nn, nl, maxnb, U, F,
+                      W, J, G);
+        if (st) break;
+        if (s > 0) {
+            for (long i = 0; i < n; ++i)
+                for (int a = 0; a < 3; ++a) vel[i * 3 + a] += half * F[i * 3 + a];
+            st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, NULL, J, NULL);
+            if (st) break;
+        }
+        double *row = &thermo[(size_t)s * 16];
+        thermo_row(n, mass, U, vel, W, J, row);
+        if (box_traj)
+            for (int a = 0; a < 3; ++a) box_traj[(size_t)s * 3 + a] = box[a];
+        if (s == n_steps) break;
+        /* weak coupling */
+        const double T = row[15];
+        double lambda = 1.0, mu = 1.0;
+        if (tau_T > 0.0 && T > 0.0) lambda = sqrt(1.0 + dt / tau_T * (T0 / T - 1.0));
+        if (tau_P > 0.0) {
+            const double P = row_pressure(row, box[0] * box[1] * box[2]);
+            const double mu3 = 1.0 - beta * dt / tau_P * (P0 - P);
+            if (!(mu3 > 0.0)) { st = ORA_EINVAL; break; }
+            mu = cbrt(mu3);
+        }
+        for (long i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                vel[i * 3 + a] *= lambda;
+                pos[i * 3 + a] *= mu;
+            }
+        for (int a = 0; a < 3; ++a) box[a] *= mu;
+    }
+    free(G);
     free(nn);
     free(nl);
     if (n_builds) *n_builds = builds;

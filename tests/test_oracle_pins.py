@@ -539,3 +539,78 @@ def test_sw_nve_conserves_energy(oracle_mod):
     r = oracle_mod.nve("sw", SP, s.pos, s.vel, s.box, wl.M_SI, 60, 1.0, RL_S, 20, 48)
     e = r["thermo"][:, 14]
     assert np.abs(e - e[0]).max() / s.n < 1e-4
+
+
+# ---- NPT with Berendsen weak coupling (the paper's benchmark ensemble) ----
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_npt_without_coupling_is_nve(oracle_mod, pot):
+    """Both couplings off: the NPT run is the NVE run operation for
+    operation (scaling by exactly 1), so every output matches bit for bit."""
+    s = wl.silicon_crystal(3, seed=5, sigma=0.05)
+    p, rl = (TP, RL_T) if pot == "tersoff" else (SP, RL_S)
+    a = oracle_mod.nve(pot, p, s.pos, s.vel, s.box, wl.M_SI, 30, 1.0, rl, 10, 48,
+                       check_skin=False)
+    b = oracle_mod.npt(pot, p, s.pos, s.vel, s.box, wl.M_SI, 30, 1.0, rl, 10, 48,
+                       300.0, 0.0, 0.0, 0.0, 0.0)
+    for k in ("pos", "vel", "U", "F", "W", "J", "thermo"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(b["box"], s.box)
+    assert np.array_equal(b["box_traj"], np.tile(s.box, (31, 1)))
+
+
+@pytest.mark.parametrize("pot,a", [("tersoff", 5.40), ("tersoff", 5.47), ("sw", 5.45)])
+def test_npt_pressure_is_minus_dU_dV(oracle_mod, pot, a):
+    """At rest, the pressure the coupling uses, (2 E_kin + tr W) / (3 V),
+    equals -dU/dV of the total energy under isotropic scaling of the
+    positions and the box (central difference)."""
+    s = wl.silicon_crystal(3, seed=6, sigma=0.04, a=a)
+    p, rl = (TP, RL_T) if pot == "tersoff" else (SP, RL_S)
+    zero = np.zeros_like(s.vel)
+    r = oracle_mod.npt(pot, p, s.pos, zero, s.box, wl.M_SI, 0, 1.0, rl, 10, 48,
+                       300.0, 0.0, 0.0, 0.0, 0.0)
+    p_row = oracle_mod.pressure_GPa(r["thermo"][0], s.box)
+
+    def energy(scale):
+        pos, box = s.pos * scale, s.box * scale
+        nn, nl = lists(oracle_mod, pot, pos, box, 48)
+        return evaluate(oracle_mod, pot, pos, box, nn, nl)["U"].sum()
+
+    h = 1e-5
+    v0 = float(np.prod(s.box))
+    dU = energy(1 + h) - energy(1 - h)
+    dV = v0 * ((1 + h) ** 3 - (1 - h) ** 3)
+    p_fd = -dU / dV * oracle_mod.EV_PER_A3_IN_GPA
+    assert abs(p_row - p_fd) < 1e-6 * max(1.0, abs(p_fd)), (p_row, p_fd)
+
+
+@pytest.mark.parametrize("t0", [150.0, 300.0])
+def test_npt_thermostat_relaxes_temperature(oracle_mod, t0):
+    """A crystal started at 600 K (it settles near 500 K uncoupled), coupled
+    to t0 with a 20 fs time constant and no barostat, ends near t0."""
+    s = wl.silicon_crystal(3, seed=7, sigma=0.05, temperature=600.0)
+    r = oracle_mod.npt("tersoff", TP, s.pos, s.vel, s.box, wl.M_SI, 400, 1.0, RL_T, 10, 48,
+                       t0, 20.0, 0.0, 0.0, 0.0)
+    t_end = r["thermo"][-150:, 15].mean()
+    assert abs(t_end - t0) < 0.1 * t0, t_end
+    free = oracle_mod.npt("tersoff", TP, s.pos, s.vel, s.box, wl.M_SI, 400, 1.0, RL_T, 10, 48,
+                          t0, 0.0, 0.0, 0.0, 0.0)
+    assert free["thermo"][-150:, 15].mean() > 400.0
+
+
+@pytest.mark.parametrize("a", [5.38, 5.49])
+def test_npt_barostat_moves_toward_target_pressure(oracle_mod, a):
+    """Compressed (positive pressure) and expanded (negative pressure)
+    crystals coupled to 0 GPa: the box grows or shrinks accordingly and the
+    pressure magnitude falls."""
+    s = wl.silicon_crystal(3, seed=8, sigma=0.03, temperature=50.0, a=a)
+    r = oracle_mod.npt("tersoff", TP, s.pos, s.vel, s.box, wl.M_SI, 300, 1.0, RL_T, 10, 48,
+                       50.0, 100.0, 0.0, 100.0, 0.01)
+    p0 = oracle_mod.pressure_GPa(r["thermo"][0], r["box_traj"][0])
+    p_end = np.mean([oracle_mod.pressure_GPa(r["thermo"][k], r["box_traj"][k])
+                     for k in range(250, 301)])
+    grew = r["box_traj"][-1, 0] > r["box_traj"][0, 0]
+    assert grew == (p0 > 0), (p0, r["box_traj"][[0, -1], 0])
+    assert abs(p_end) < 0.5 * abs(p0), (p0, p_end)
+    # isotropic: the three edges keep their ratios
+    assert np.allclose(r["box_traj"][-1] / r["box_traj"][0], r["box"][0] / s.box[0], rtol=1e-12)
