@@ -204,6 +204,39 @@ mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
                          double dt_fs, int n_steps, int rebuild_every, double *U, double *F,
                          double *W, double *J, double *thermo);
 
+/* Berendsen weak coupling (Berendsen et al. 1984): the NPT ensemble, at
+ * 300 K and 0 Pa, in which the paper times its runs (Section 3).  The paper
+ * prints no coupling formula or constants; the isotropic form below is
+ * Berendsen's.  A tau <= 0 switches that coupling off. */
+typedef struct {
+    double T0_K;           /* target temperature (K), >= 0 */
+    double tau_T_fs;       /* thermostat time constant (fs); >= dt when on */
+    double P0_GPa;         /* target pressure (GPa) */
+    double tau_P_fs;       /* barostat time constant (fs) */
+    double beta_per_GPa;   /* isothermal compressibility (1/GPa), >= 0 */
+} mbmd_berendsen;
+
+/* n_steps of velocity-Verlet with Berendsen weak coupling, otherwise as
+ * mbmd_nve_run under MBMD_REBUILD_FIXED (whatever the context's policy).
+ * After the second half-kick of step s (s < n_steps) the thermo row gives
+ * the kinetic temperature T and the pressure P = (2 E_kin + tr W) / (3 V)
+ * from the per-atom virials; velocities are scaled by
+ * lambda = sqrt(1 + dt/tau_T (T0/T - 1)) (1 when T = 0) and positions and
+ * the three box edges by mu = (1 - beta dt/tau_P (P0 - P))^(1/3) before the
+ * first half-kick of step s + 1.  box[3] (host) gives the initial box and
+ * receives the final one; the list is rebuilt on the current box every
+ * rebuild_every steps, and MBMD_EBOX is returned if an edge has shrunk
+ * below 2 (cutoff + skin) by then.  thermo (device, required) receives the
+ * [n_steps + 1][16] rows of mbmd_nve_run; box_traj (device, or NULL) the
+ * [n_steps + 1][3] box edges each row was evaluated in.  MBMD_EINVAL for
+ * out-of-range coupling constants, or if 1 - beta dt/tau_P (P0 - P) <= 0
+ * at some step (that step's mu is taken as 1 and the run completes). */
+mbmd_status mbmd_npt_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, double box[3],
+                         double mass_amu, double *pos, double *vel, const int32_t *types,
+                         double dt_fs, int n_steps, int rebuild_every,
+                         const mbmd_berendsen *coupling, double *U, double *F, double *W,
+                         double *J, double *thermo, double *box_traj);
+
 /* Wait for everything this context enqueued on its stream and report (and
  * clear) the device status word: MBMD_ENONFINITE, MBMD_ENEIGH or
  * MBMD_EINVAL (atom type) for a condition raised since the last report,

@@ -51,6 +51,11 @@ class mbmd_run_stats(C.Structure):
                 ("max_displacement", C.c_double)]
 
 
+class mbmd_berendsen(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("T0_K", "tau_T_fs", "P0_GPa", "tau_P_fs", "beta_per_GPa")]
+
+
 class mbmd_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char_p), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -79,6 +84,8 @@ def _load():
         "mbmd_neighbors": ([P, I64, P, P, P, P], I),
         "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
+        "mbmd_npt_run": ([P, I, I64, P, D, P, P, P, D, I, I, C.POINTER(mbmd_berendsen), P, P,
+                          P, P, P, P], I),
         "mbmd_batch_open": ([P, I64, I, I], I),
         "mbmd_batch_workspace_size": ([P, I64, I, C.POINTER(C.c_size_t)], I),
         "mbmd_batch_capacity": ([P, C.POINTER(I64), C.POINTER(I), C.POINTER(I64)], I),
@@ -282,6 +289,39 @@ class Context:
             "mbmd_nve_run")
         if th is not None:
             out["thermo"] = th
+        return out
+
+    def npt_run(self, pos, vel, box, mass, dt, n_steps, rebuild_every=20, T0=300.0,
+                tau_T=100.0, P0_GPa=0.0, tau_P=1000.0, beta_per_GPa=0.0102, types=None,
+                precision="fp64", thermo=None, box_traj=True, out=None):
+        """Velocity-Verlet with Berendsen weak coupling (mbmd_npt_run); tau <= 0
+        switches a coupling off.  Advances pos/vel in place; returns dict(U, F,
+        W, J, thermo, box (final edges, numpy)[, box_traj])."""
+        import numpy as np
+        n = pos.shape[1]
+        out = self._outputs(n, out)
+        th = thermo if isinstance(thermo, torch.Tensor) else torch.empty(
+            n_steps + 1, THERMO_COLS, dtype=torch.float64, device=self.device)
+        bt = None
+        if box_traj is True:
+            bt = torch.empty(n_steps + 1, 3, dtype=torch.float64, device=self.device)
+        elif isinstance(box_traj, torch.Tensor):
+            bt = box_traj
+        k = mbmd_berendsen(float(T0), float(tau_T), float(P0_GPa), float(tau_P),
+                           float(beta_per_GPa))
+        b = _box(box)
+        self._check(_lib.mbmd_npt_run(
+            self._h, _prec(precision), n, b, float(mass), _dptr(pos, (3, n), "pos"),
+            _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32), float(dt),
+            int(n_steps), int(rebuild_every), C.byref(k), _dptr(out["U"], (n,), "U"),
+            _dptr(out["F"], (3, n), "F"), _dptr(out["W"], (9, n), "W"),
+            _dptr(out["J"], (3, n), "J"), _dptr(th, (n_steps + 1, THERMO_COLS), "thermo"),
+            _dptr(bt, (n_steps + 1, 3), "box_traj") if bt is not None else None),
+            "mbmd_npt_run")
+        out["thermo"] = th
+        out["box"] = np.array([b[0], b[1], b[2]])
+        if bt is not None:
+            out["box_traj"] = bt
         return out
 
     # -- serving batch --------------------------------------------------------

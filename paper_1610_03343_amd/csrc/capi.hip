@@ -16,15 +16,20 @@ using namespace mbmd;
 
 namespace {
 // Kernel classes timed by the optional HIP-event profile.
-enum ProfKind { P_STAGE, P_BUILD, P_PARTIALS, P_PARTIALS_OVF, P_GATHER, P_THERMO, P_KINDS };
+enum ProfKind {
+    P_STAGE, P_BUILD, P_PARTIALS, P_PARTIALS_OVF, P_GATHER, P_THERMO, P_NPT_FOLD, P_NPT_DRIFT,
+    P_KINDS
+};
 const char* const kProfNames[P_KINDS] = {"stage_positions", "neighbor_build", "site_partials",
-                                         "site_partials_overflow", "pair_gather", "thermo_fold"};
+                                         "site_partials_overflow", "pair_gather", "thermo_fold",
+                                         "npt_fold", "npt_drift"};
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
 };
 
 constexpr double kKappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
+constexpr double kGPaPerEvA3 = 160.21766208;   // 1 eV/A^3 in GPa
 
 // One structure admitted to the serving batch.
 struct Slot {
@@ -190,6 +195,7 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     t.maxnn = (int*)take(sizeof(int) * segs);
     t.phase[0] = (int*)take(sizeof(int) * segs);
     t.phase[1] = (int*)take(sizeof(int) * segs);
+    t.coupling = (double*)take(sizeof(double) * 2 * segs);
     t.seg = (Seg*)take(sizeof(Seg) * segs);
     t.seg_cap = segs;
     if (state) {
@@ -334,6 +340,9 @@ mbmd_status status_to_code(mbmd_ctx* c, unsigned st)
 {
     if (st & ST_TYPES) return fail(c, MBMD_EINVAL, "atom type other than 0%s");
     if (st & ST_NONFINITE) return fail(c, MBMD_ENONFINITE, "non-finite position%s");
+    if (st & ST_BAROSTAT)
+        return fail(c, MBMD_EINVAL,
+                    "barostat factor 1 - beta dt/tau_P (P0 - P) <= 0; lower beta dt/tau_P%s");
     if (st & ST_NEIGH_OVERFLOW)
         return fail(c, MBMD_ENEIGH, "neighbour list capacity exceeded; raise max_neighbors%s");
     if (st & ST_ASYMMETRIC) return fail(c, MBMD_EDEVICE, "internal: asymmetric neighbour data%s");
@@ -409,7 +418,7 @@ hipError_t partials(mbmd_ctx* c, int cur)
 // (integrator per segment phase); flips the phase buffers.
 template <class T>
 hipError_t force_step(mbmd_ctx* c, int cur, bool check, unsigned long long* slot,
-                      double* part_row)
+                      double* part_row, bool hold = false)
 {
     // the site pass reads the phases too: point both passes at this step's
     set_phase_pointers(c);
@@ -420,6 +429,7 @@ hipError_t force_step(mbmd_ctx* c, int cur, bool check, unsigned long long* slot
     a.skin_half2 = 0.25 * c->skin * c->skin;
     a.disp_slot = slot;
     a.part_row = part_row;
+    a.hold = hold;
     if (e == hipSuccess) {
         ProfScope ps(c, P_GATHER);
         e = launch_pair_gather<T>(c->buf, c->segs, a, c->stream);
@@ -625,6 +635,69 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     if (e != hipSuccess) return hip_fail(c, e, "nve launch");
     s = finish(c);
     st.max_displacement = std::sqrt(committed_max2);
+    c->stats = st;
+    return s;
+}
+
+
+// Velocity-Verlet with Berendsen weak coupling: per step, the scaling and
+// first half-kick and drift (from step 1), a fixed-schedule rebuild on the
+// box of that step (read back from the device, whose fold scales it), the
+// force evaluation with the second half-kick, then the fold that forms the
+// thermo row and the next step's factors.
+template <class T>
+mbmd_status npt_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double* pos,
+                     double* vel, const int32_t* types, double dt, int n_steps, int every,
+                     const NptArgs& na, double* U, double* F, double* W, double* J,
+                     double* thermo, double* box_traj, double* box_out)
+{
+    int cells = 0;
+    mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
+                                 &cells);
+    if (s != MBMD_OK) return s;
+    const Buffers& b = c->buf;
+    const double rlist = cutoff_of(c) + c->skin;
+    mbmd_run_stats st{};
+    st.steps = n_steps;
+    st.max_displacement = -1.0;
+    int last_build = 0;
+    hipError_t e = build(c, cells, 0);
+    st.rebuilds = 1;
+    Seg dev_seg{};
+    for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
+        if (step > 0) {
+            ProfScope ps(c, P_NPT_DRIFT);
+            e = launch_npt_drift(b, c->segs, 0, c->stream);
+        }
+        if (e == hipSuccess && step > 0 && step - last_build == every) {
+            e = hipMemcpyAsync(&dev_seg, b.seg, sizeof(Seg), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) break;
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(dev_seg.box.L[a]) || !(dev_seg.box.L[a] >= 2.0 * rlist))
+                    return fail(c, MBMD_EBOX,
+                                "barostat shrank a box edge below 2 (cutoff + skin)%s");
+            Seg g = make_seg(dev_seg.box, rlist, 0, (int)n, n_steps, mass, dt, nullptr);
+            g.build = 1;
+            c->segs_host.assign(1, g);
+            e = upload_segs(c, &cells);
+            if (e == hipSuccess) e = build(c, cells, 0);
+            last_build = step;
+            ++st.rebuilds;
+        }
+        if (e == hipSuccess) e = force_step<T>(c, 0, false, nullptr, ring_row(c, step), true);
+        if (e == hipSuccess) {
+            ProfScope ps(c, P_NPT_FOLD);
+            e = launch_npt_fold(b, c->segs, step, step, step == n_steps, na, thermo, box_traj,
+                                c->stream);
+        }
+    }
+    if (e == hipSuccess) e = launch_store_positions(b.xw[0], 0, n, pos, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&dev_seg, b.seg, sizeof(Seg), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "npt launch");
+    s = finish(c);
+    for (int a = 0; a < 3; ++a) box_out[a] = dev_seg.box.L[a];
     c->stats = st;
     return s;
 }
@@ -990,6 +1063,44 @@ mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const doub
                                U, F, W, J, thermo);
     return nve_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every, U,
                             F, W, J, thermo);
+}
+
+mbmd_status mbmd_npt_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, double box[3],
+                         double mass_amu, double* pos, double* vel, const int32_t* types,
+                         double dt_fs, int n_steps, int rebuild_every,
+                         const mbmd_berendsen* coupling, double* U, double* F, double* W,
+                         double* J, double* thermo, double* box_traj)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
+    if (!std::isfinite(mass_amu) || !(mass_amu > 0.0) || !std::isfinite(dt_fs) ||
+        !(dt_fs > 0.0) || n_steps < 0 || rebuild_every < 1)
+        return fail(c, MBMD_EINVAL, "need mass > 0, dt > 0, n_steps >= 0, rebuild_every >= 1%s");
+    if (!coupling) return fail(c, MBMD_EINVAL, "coupling is NULL%s");
+    const mbmd_berendsen& k = *coupling;
+    if (!std::isfinite(k.T0_K) || k.T0_K < 0.0 || !std::isfinite(k.P0_GPa) ||
+        !std::isfinite(k.beta_per_GPa) || k.beta_per_GPa < 0.0 || !std::isfinite(k.tau_T_fs) ||
+        !std::isfinite(k.tau_P_fs) || (k.tau_T_fs > 0.0 && k.tau_T_fs < dt_fs))
+        return fail(c, MBMD_EINVAL,
+                    "need finite T0 >= 0, P0, beta >= 0, tau_T, tau_P; tau_T >= dt when on%s");
+    if (n == 0) return MBMD_OK;
+    if (!pos || !vel || !U || !F || !W || !J || !thermo)
+        return fail(c, MBMD_EINVAL, "null device pointer%s");
+    NptArgs na{};
+    na.T0 = k.T0_K;
+    na.tau_T = k.tau_T_fs;
+    na.P0 = k.P0_GPa / kGPaPerEvA3;
+    na.tau_P = k.tau_P_fs;
+    na.beta = k.beta_per_GPa * kGPaPerEvA3;
+    na.dt = dt_fs;
+    if (prec == MBMD_MIXED)
+        return npt_impl<float>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
+                               na, U, F, W, J, thermo, box_traj, box);
+    return npt_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
+                            na, U, F, W, J, thermo, box_traj, box);
 }
 
 // ---- serving batch ----------------------------------------------------------

@@ -34,6 +34,7 @@ enum : unsigned {
     ST_NONFINITE = 1u << 2,        // non-finite position
     ST_ASYMMETRIC = 1u << 3,       // list or cutoff mask not symmetric (internal)
     ST_TYPES = 1u << 4,            // an atom type other than 0
+    ST_BAROSTAT = 1u << 5,         // Berendsen box factor mu^3 <= 0 (mu set to 1)
 };
 
 constexpr int kBlock = 256;          // threads per block of every per-atom kernel
@@ -134,6 +135,7 @@ struct Buffers {
     unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
     int* maxnn;              // [segments] largest list count of the last build
     int* phase[2];           // per segment step index (double-buffered)
+    double* coupling;        // [segments][2] Berendsen lambda, mu for the next drift
     Seg* seg;                // segment table
     int seg_cap;
     double* vel;             // velocities [3][ostride]
@@ -220,11 +222,20 @@ struct StepArgs {
     double skin_half2;       // (skin/2)^2
     unsigned long long* disp_slot;  // receives (atomic max) the squared displacement, as bits
     double* part_row;        // this step's row of block partials (null: no thermo)
+    bool hold;               // second half-kick only: no drift, positions stay in
+                             // buffer cur (the weak-coupling loop drifts separately)
+};
+
+// Berendsen weak coupling in the library's units: T0 in K, P0 in eV/A^3,
+// beta in A^3/eV, times in fs; tau <= 0 switches that coupling off.
+struct NptArgs {
+    double T0, tau_T, P0, tau_P, beta, dt;
 };
 
 // Per segment, from its phase p and nsteps: second half-kick iff p > 0;
-// first half-kick and drift into the other buffer iff p < nsteps, else the
-// positions are copied forward unchanged; segments with p > nsteps are idle.
+// first half-kick and drift into the other buffer iff p < nsteps and not
+// a.hold, else the positions are copied forward unchanged (not at all under
+// a.hold); segments with p > nsteps are idle.
 template <class T>
 hipError_t launch_pair_gather(const Buffers& b, const Segs& S, const StepArgs& a, hipStream_t s);
 
@@ -237,5 +248,14 @@ hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int firs
 // `ring_row`.
 hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring_row,
                                        hipStream_t s);
+// Weak coupling, segment 0: folds ring row `ring_row` into thermo row `step`
+// and box_traj row `step` (if not null); unless `last`, forms the thermostat
+// and barostat factors from that row, stores them in b.coupling and scales
+// the segment's box (b.seg) by mu.
+hipError_t launch_npt_fold(const Buffers& b, const Segs& S, int ring_row, int step, bool last,
+                           const NptArgs& a, double* thermo, double* box_traj, hipStream_t s);
+// Weak coupling: v <- lambda v + (dt/2) kappa F / m, x <- wrap(mu x + dt v)
+// in the (already scaled) box, in place in position buffer `cur`.
+hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_t s);
 
 }  // namespace mbmd

@@ -76,7 +76,7 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
         S.phase_out[sid] = phase > g.nsteps ? phase : phase + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;   // consumed by the partials pass
     if (phase > g.nsteps) return;              // finished segment, kept for retrieval
-    const bool kick_before = phase > 0, advance = phase < g.nsteps;
+    const bool kick_before = phase > 0, advance = !a.hold && phase < g.nsteps;
     const Box box = g.box;
     const int local = (lb - g.blk) * kBlock + threadIdx.x;
     const int64_t i = g.atom_off + local;
@@ -172,7 +172,7 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
                 vel[os + i] = v[1];
                 vel[2 * os + i] = v[2];
             }
-            xw_next[i] = xi;
+            if (!a.hold) xw_next[i] = xi;
         }
     }
 
@@ -206,19 +206,14 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     if (threadIdx.x < kPartialCols) a.part_row[(int64_t)lb * kPartialCols + threadIdx.x] = lds_tot[threadIdx.x];
 }
 
-// One block per step of one segment: folds that step's block partials of the
-// segment, in block order, into its thermo row: 0 E_pot, 1 E_kin, 2..10 W,
-// 11..13 J, 14 E_pot + E_kin, 15 kinetic temperature (k_B in eV/K, 3N - 3
-// degrees of freedom).
-__global__ void __launch_bounds__(kBlock)
-k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int sid, int first,
-              int ring0, double* __restrict__ thermo)
+// Sums one segment's block partials of one step (ring row rowp), in block
+// order, into its thermo row: 0 E_pot, 1 E_kin, 2..10 W, 11..13 J,
+// 14 E_pot + E_kin, 15 kinetic temperature (k_B in eV/K, 3N - 3 degrees of
+// freedom).  Called by every thread of the block; thread 0 writes the row.
+__device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp, const Seg& g,
+                                                 double (*lds)[kPartialCols], double* lds_tot,
+                                                 double* __restrict__ row)
 {
-    __shared__ double lds[kBlock / 64][kPartialCols];
-    __shared__ double lds_tot[kPartialCols];
-    const Seg& g = S.seg[sid];
-    const int k = first + blockIdx.x;
-    const double* rowp = part_b + (int64_t)((ring0 + k) % kThermoRing) * blk_cap * kPartialCols;
     const int b0 = g.blk, b1 = g.blk + blocks_for(g.n);
     double vals[kPartialCols];
 #pragma unroll
@@ -230,13 +225,24 @@ k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int si
     }
     block_sum_cols(vals, lds, lds_tot);
     if (threadIdx.x == 0) {
-        double* row = thermo + (int64_t)k * kThermoCols;
         const double n = (double)g.n;
 #pragma unroll
         for (int c = 0; c < kPartialCols; ++c) row[c] = lds_tot[c];
         row[14] = lds_tot[0] + lds_tot[1];
         row[15] = g.n > 1 ? 2.0 * lds_tot[1] / ((3.0 * n - 3.0) * 8.617333262e-5) : 0.0;
     }
+}
+
+// One block per step of one segment: row k = first + blockIdx.x.
+__global__ void __launch_bounds__(kBlock)
+k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int sid, int first,
+              int ring0, double* __restrict__ thermo)
+{
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    const int k = first + blockIdx.x;
+    const double* rowp = part_b + (int64_t)((ring0 + k) % kThermoRing) * blk_cap * kPartialCols;
+    fold_segment_row(rowp, S.seg[sid], lds, lds_tot, thermo + (int64_t)k * kThermoCols);
 }
 
 hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int first, int count,
@@ -260,24 +266,7 @@ k_thermo_fold_segments(const double* __restrict__ part_b, int64_t blk_cap, Segs 
     const int k = S.phase_in[sid];
     if (!g.thermo || k > g.nsteps) return;
     const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
-    const int b0 = g.blk, b1 = g.blk + blocks_for(g.n);
-    double vals[kPartialCols];
-#pragma unroll
-    for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
-        const double* p = rowp + (int64_t)b * kPartialCols;
-#pragma unroll
-        for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
-    }
-    block_sum_cols(vals, lds, lds_tot);
-    if (threadIdx.x == 0) {
-        double* row = g.thermo + (int64_t)k * kThermoCols;
-        const double n = (double)g.n;
-#pragma unroll
-        for (int c = 0; c < kPartialCols; ++c) row[c] = lds_tot[c];
-        row[14] = lds_tot[0] + lds_tot[1];
-        row[15] = g.n > 1 ? 2.0 * lds_tot[1] / ((3.0 * n - 3.0) * 8.617333262e-5) : 0.0;
-    }
+    fold_segment_row(rowp, g, lds, lds_tot, g.thermo + (int64_t)k * kThermoCols);
 }
 
 hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring_row,
@@ -287,6 +276,102 @@ hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring
     if (!segs_ready(S, b)) return hipErrorInvalidValue;
     k_thermo_fold_segments<<<S.nseg, kBlock, 0, s>>>(b.part_b, b.blk_cap, S,
                                                       ring_row % kThermoRing);
+    return hipGetLastError();
+}
+
+// ---- Berendsen weak coupling ---------------------------------------------
+//
+// After the second half-kick of step s the thermo row gives the kinetic
+// temperature T and the pressure P = (2 E_kin + tr W) / (3 V) (the virial
+// theorem with the per-atom virials W_i of Section 2.3).  Velocities are then
+// scaled by lambda = sqrt(1 + dt/tau_T (T0/T - 1)) and positions and box
+// edges by mu = (1 - beta dt/tau_P (P0 - P))^(1/3) before the first
+// half-kick of step s + 1.  The fold forms both factors in one thread and
+// scales the segment's box in device memory, so the step loop never waits
+// for the host.  The arithmetic is kept unfused, as a plain IEEE evaluation
+// of these expressions in this order.
+__global__ void __launch_bounds__(kBlock)
+k_npt_fold(const double* __restrict__ rowp, Segs S, Seg* __restrict__ seg_rw, NptArgs a,
+           int step, int last, double* __restrict__ coupling, double* __restrict__ thermo,
+           double* __restrict__ box_traj, unsigned* __restrict__ status)
+{
+#pragma clang fp contract(off)
+    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    double* row = thermo + (int64_t)step * kThermoCols;
+    fold_segment_row(rowp, S.seg[0], lds, lds_tot, row);
+    if (threadIdx.x != 0) return;
+    const Box box = S.seg[0].box;
+    if (box_traj)
+        for (int c = 0; c < 3; ++c) box_traj[(int64_t)step * 3 + c] = box.L[c];
+    if (last) return;
+    const double T = row[15];
+    double lambda = 1.0, mu = 1.0;
+    if (a.tau_T > 0.0 && T > 0.0) lambda = sqrt(1.0 + a.dt / a.tau_T * (a.T0 / T - 1.0));
+    if (a.tau_P > 0.0) {
+        const double volume = box.L[0] * box.L[1] * box.L[2];
+        const double P = (2.0 * row[1] + row[2] + row[6] + row[10]) / (3.0 * volume);
+        const double mu3 = 1.0 - a.beta * a.dt / a.tau_P * (a.P0 - P);
+        if (mu3 > 0.0) {
+            mu = cbrt(mu3);
+        } else {
+            atomicOr(status, ST_BAROSTAT);
+        }
+    }
+    coupling[0] = lambda;
+    coupling[1] = mu;
+    Box nb;
+    for (int c = 0; c < 3; ++c) {
+        nb.L[c] = box.L[c] * mu;
+        nb.inv[c] = 1.0 / nb.L[c];
+    }
+    seg_rw[0].box = nb;
+}
+
+hipError_t launch_npt_fold(const Buffers& b, const Segs& S, int ring_row, int step, bool last,
+                           const NptArgs& a, double* thermo, double* box_traj, hipStream_t s)
+{
+    if (!segs_ready(S, b) || S.nseg != 1 || !thermo || !b.coupling) return hipErrorInvalidValue;
+    const double* rowp = b.part_b + (int64_t)(ring_row % kThermoRing) * b.blk_cap * kPartialCols;
+    k_npt_fold<<<1, kBlock, 0, s>>>(rowp, S, b.seg, a, step, last ? 1 : 0, b.coupling, thermo,
+                                    box_traj, b.status);
+    return hipGetLastError();
+}
+
+// Scaling by the factors of the previous step, then that step's first
+// half-kick and drift, with the forces it left in F; the positions are
+// wrapped into the scaled box.  No neighbour is read, so the update is in
+// place.
+__global__ void __launch_bounds__(kBlock)
+k_npt_drift(Segs S, int64_t os, const double* __restrict__ coupling, double4* __restrict__ xw,
+            double* __restrict__ vel, const double* __restrict__ F)
+{
+#pragma clang fp contract(off)
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const int local = (lb - g.blk) * kBlock + threadIdx.x;
+    if (local >= g.n) return;
+    const int64_t i = g.atom_off + local;
+    const double lambda = coupling[2 * sid], mu = coupling[2 * sid + 1];
+    const double4 xi = xw[i];
+    double x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double v = vel[c * os + i] * lambda;
+        v = v + g.half_dt_acc * F[c * os + i];
+        vel[c * os + i] = v;
+        x[c] = x[c] * mu;
+        x[c] = wrap_coord(x[c] + g.dt * v, g.box.L[c]);
+    }
+    xw[i] = make_double4(x[0], x[1], x[2], xi.w);
+}
+
+hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_t s)
+{
+    if (S.nblk <= 0) return hipSuccess;
+    if (!segs_ready(S, b) || !b.vel || !b.F || !b.coupling) return hipErrorInvalidValue;
+    k_npt_drift<<<S.nblk, kBlock, 0, s>>>(S, b.ostride, b.coupling, b.xw[cur], b.vel, b.F);
     return hipGetLastError();
 }
 

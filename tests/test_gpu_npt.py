@@ -1,0 +1,200 @@
+"""Berendsen weak coupling (mbmd_npt_run) against the oracle's ora_npt.
+
+With both couplings off the run is velocity-Verlet NVE under the fixed
+rebuild schedule, and must equal mbmd_nve_run bit for bit.  With coupling
+on, trajectories, thermo rows and the box path are compared with the
+oracle within ten times the oracle's own divergence under a one-ulp
+perturbation of the initial state (the bound of the NVE trajectory tests).
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workload as wl
+from gpu_util import PARAMS, RLIST, context, min_image, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# coupling constants of the runs below: thermostat towards 600 K, barostat
+# towards 1 GPa at silicon's compressibility (1 / 98 GPa)
+COUPLINGS = {
+    "both": dict(T0=600.0, tau_T=20.0, P0_GPa=1.0, tau_P=50.0, beta_per_GPa=0.0102),
+    "thermostat": dict(T0=600.0, tau_T=20.0, P0_GPa=0.0, tau_P=0.0, beta_per_GPa=0.0),
+    "barostat": dict(T0=0.0, tau_T=0.0, P0_GPa=-2.0, tau_P=50.0, beta_per_GPa=0.0102),
+}
+OFF = dict(T0=0.0, tau_T=0.0, P0_GPa=0.0, tau_P=0.0, beta_per_GPa=0.0)
+
+
+def _oracle_npt(pot, s, pos, vel, n_steps, rebuild, k):
+    import oracle
+    return oracle.npt(pot, PARAMS[pot], pos, vel, s.box, wl.M_SI, n_steps, 1.0, RLIST[pot],
+                      rebuild, 64, k["T0"], k["tau_T"], k["P0_GPa"], k["tau_P"],
+                      k["beta_per_GPa"])
+
+
+def _chaos_tolerance(pot, s, n_steps, rebuild, k):
+    """Ten times the oracle's divergence when every coordinate and velocity
+    component of the initial state is moved by one ulp."""
+    a = _oracle_npt(pot, s, s.pos, s.vel, n_steps, rebuild, k)
+    rng = np.random.default_rng(99)
+    p2 = np.nextafter(s.pos, np.where(rng.uniform(size=s.pos.shape) < 0.5, -np.inf, np.inf))
+    v2 = np.nextafter(s.vel, np.where(rng.uniform(size=s.vel.shape) < 0.5, -np.inf, np.inf))
+    b = _oracle_npt(pot, s, p2, v2, n_steps, rebuild, k)
+    tol = dict(
+        x=max(10 * np.max(np.abs(min_image(a["pos"] - b["pos"], a["box"]))), 1e-13),
+        v=max(10 * np.max(np.abs(a["vel"] - b["vel"])), 1e-15),
+        th=np.maximum(10 * np.max(np.abs(a["thermo"] - b["thermo"]), axis=0),
+                      1e-12 * np.max(np.abs(a["thermo"]), axis=0)),
+        box=max(10 * np.max(np.abs(a["box_traj"] - b["box_traj"])),
+                1e-14 * float(np.max(s.box))),
+    )
+    return a, tol
+
+
+def _system(pot):
+    return wl.tersoff_small() if pot == "tersoff" else wl.silicon_crystal(3, seed=21)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_npt_without_coupling_equals_nve(pot, precision):
+    """Both couplings off: the separate drift kernel must reproduce the fused
+    NVE step bit for bit (same unfused arithmetic in the same order)."""
+    import torch
+    s = _system(pot)
+    steps, every = 30, 7
+    with context(pot) as ctx:
+        ctx.set_rebuild_policy("fixed")
+        p1, v1 = to_dev(s.pos), to_dev(s.vel)
+        a = ctx.nve_run(p1, v1, s.box, wl.M_SI, 1.0, steps, rebuild_every=every,
+                        precision=precision)
+        nve_builds = ctx.run_stats()["rebuilds"]
+        p2, v2 = to_dev(s.pos), to_dev(s.vel)
+        b = ctx.npt_run(p2, v2, s.box, wl.M_SI, 1.0, steps, rebuild_every=every,
+                        precision=precision, **OFF)
+        npt_builds = ctx.run_stats()["rebuilds"]
+        torch.cuda.synchronize()
+        assert npt_builds == nve_builds
+        assert torch.equal(p1, p2) and torch.equal(v1, v2)
+        for key in ("U", "F", "W", "J", "thermo"):
+            assert torch.equal(a[key], b[key]), key
+        bt = b["box_traj"].cpu().numpy()
+    assert np.array_equal(b["box"], s.box)
+    assert np.array_equal(bt, np.tile(s.box, (steps + 1, 1)))
+
+
+@pytest.mark.parametrize("mode", list(COUPLINGS))
+@pytest.mark.parametrize("pot,steps", [("tersoff", 100), ("sw", 60)])
+def test_npt_trajectory_parity(pot, steps, mode):
+    """Positions, velocities, thermo rows, the box path and the final box
+    against ora_npt; step 0 is a single point (FP64 parity)."""
+    import torch
+    s = _system(pot)
+    k = COUPLINGS[mode]
+    every = 10
+    ref, tol = _chaos_tolerance(pot, s, steps, every, k)
+    with context(pot) as ctx:
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        out = ctx.npt_run(pos, vel, s.box, wl.M_SI, 1.0, steps, rebuild_every=every, **k)
+        torch.cuda.synchronize()
+        gp, gv = pos.cpu().numpy().T, vel.cpu().numpy().T
+        th = out["thermo"].cpu().numpy()
+        bt = out["box_traj"].cpu().numpy()
+        builds = ctx.run_stats()["rebuilds"]
+    assert builds == ref["builds"]
+    print(f"{mode}: box {s.box[0]:.6f} -> gpu {out['box'][0]:.9f}, oracle {ref['box'][0]:.9f} A; "
+          f"T {th[0, 15]:.1f} -> {th[-1, 15]:.1f} K; tolerances x {tol['x']:.2e} A, "
+          f"v {tol['v']:.2e} A/fs, box {tol['box']:.2e} A")
+    assert rel(th[0], ref["thermo"][0]) <= 1e-12
+    assert np.max(np.abs(bt - ref["box_traj"])) <= tol["box"]
+    assert np.max(np.abs(out["box"] - ref["box"])) <= tol["box"]
+    assert np.max(np.abs(min_image(gp - ref["pos"], ref["box"]))) <= tol["x"]
+    assert np.max(np.abs(gv - ref["vel"])) <= tol["v"]
+    assert np.all(np.abs(th - ref["thermo"]) <= tol["th"][None, :])
+    # the couplings act: the barostat moves the box, the thermostat heats
+    if k["tau_P"] > 0:
+        assert abs(out["box"][0] - s.box[0]) > 1e3 * tol["box"]
+    else:
+        assert np.array_equal(out["box"], s.box)
+    if k["tau_T"] > 0:
+        assert th[-20:, 15].mean() > th[0, 15]
+
+
+def test_npt_mixed_tracks_fp64():
+    """Mixed path: the box path and temperature follow the FP64 run.  Bounds:
+    a force error of 1e-4 eV/A per atom moves the pressure of 512 atoms in
+    10,246 A^3 by at most 6.4e-4 GPa, and the box by at most
+    steps * beta dt/tau_P * dP / 3 = 2.2e-6 relative over 50 steps; the
+    velocities by at most steps * dt kappa/m * 1e-4 = 1.7e-6 A/fs, 0.1 % of
+    their thermal size, so T within 0.2 % (taken as 1 K at 600 K)."""
+    import torch
+    s = wl.tersoff_small()
+    k = COUPLINGS["both"]
+    res = {}
+    with context("tersoff") as ctx:
+        for prec in ("fp64", "mixed"):
+            pos, vel = to_dev(s.pos), to_dev(s.vel)
+            out = ctx.npt_run(pos, vel, s.box, wl.M_SI, 1.0, 50, rebuild_every=10,
+                              precision=prec, **k)
+            torch.cuda.synchronize()
+            res[prec] = (out["box_traj"].cpu().numpy(), out["thermo"].cpu().numpy())
+    db = np.max(np.abs(res["mixed"][0] - res["fp64"][0]) / res["fp64"][0])
+    dT = np.max(np.abs(res["mixed"][1][:, 15] - res["fp64"][1][:, 15]))
+    print(f"mixed vs fp64 over 50 NPT steps: box {db:.2e} relative, T {dT:.3e} K")
+    assert db <= 1e-5
+    assert dT <= 1.0
+
+
+def test_npt_errors():
+    """Argument checks, a barostat factor that would be imaginary, and a box
+    squeezed below two list radii before a rebuild."""
+    import torch
+    import paper_1610_03343_amd as mb
+    s = wl.tersoff_small()
+    with context("tersoff") as ctx:
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        with pytest.raises(mb.MbmdError) as e:   # tau_T shorter than dt
+            ctx.npt_run(pos, vel, s.box, wl.M_SI, 1.0, 5, T0=300.0, tau_T=0.5)
+        assert e.value.code == mb.MBMD_EINVAL
+        with pytest.raises(mb.MbmdError) as e:   # negative compressibility
+            ctx.npt_run(pos, vel, s.box, wl.M_SI, 1.0, 5, beta_per_GPa=-1.0)
+        assert e.value.code == mb.MBMD_EINVAL
+        # thermo is required by the C ABI
+        n = s.n
+        z = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda:0")
+        U, F, W, J = z(n), z(3, n), z(9, n), z(3, n)
+        k = mb.mbmd_berendsen(300.0, 100.0, 0.0, 1000.0, 0.0102)
+        box = (C.c_double * 3)(*s.box)
+        st = mb.lib().mbmd_npt_run(ctx._h, 0, n, box, wl.M_SI, C.c_void_p(pos.data_ptr()),
+                                   C.c_void_p(vel.data_ptr()), None, 1.0, 5, 10, C.byref(k),
+                                   C.c_void_p(U.data_ptr()), C.c_void_p(F.data_ptr()),
+                                   C.c_void_p(W.data_ptr()), C.c_void_p(J.data_ptr()), None,
+                                   None)
+        assert st == mb.MBMD_EINVAL
+        # 1 - beta dt/tau_P (P0 - P) < 0 at every step: reported, box kept
+        pos, vel = to_dev(s.pos), to_dev(s.vel)
+        bt = torch.zeros(6, 3, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.npt_run(pos, vel, s.box, wl.M_SI, 1.0, 5, T0=0.0, tau_T=0.0, P0_GPa=1e5,
+                        tau_P=1.0, beta_per_GPa=1.0, box_traj=bt)
+        assert e.value.code == mb.MBMD_EINVAL
+        torch.cuda.synchronize()
+        assert np.array_equal(bt.cpu().numpy(), np.tile(s.box, (6, 1)))
+        assert torch.isfinite(pos).all() and torch.isfinite(vel).all()
+    # a 64-atom crystal with a list radius just under half its edge: one
+    # compressing step (mu ~ 0.965) takes the edge below 2 r_list, and the
+    # rebuild at step 2 must refuse it
+    s2 = wl.silicon_crystal(2, seed=11, sigma=0.05)
+    skin = 0.5 * s2.box[0] - 3.0 - 0.02
+    with context("tersoff", max_neighbors=64, skin=skin) as ctx:
+        pos, vel = to_dev(s2.pos), to_dev(s2.vel)
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.npt_run(pos, vel, s2.box, wl.M_SI, 1.0, 6, rebuild_every=2, T0=0.0, tau_T=0.0,
+                        P0_GPa=100.0, tau_P=10.0, beta_per_GPa=0.01)
+        assert e.value.code == mb.MBMD_EBOX
+        # the context stays usable
+        out = ctx.npt_run(to_dev(s2.pos), to_dev(s2.vel), s2.box, wl.M_SI, 1.0, 4,
+                          rebuild_every=2, **OFF)
+        torch.cuda.synchronize()
+        assert np.array_equal(out["box"], s2.box)
