@@ -292,6 +292,60 @@ def bench_mixed(W, args):
     }
 
 
+# Berendsen constants of the NPT timing (the paper gives none): 300 K and
+# 0 Pa as in its timings, tau_T = 100 fs, tau_P = 1 ps, silicon's isothermal
+# compressibility 1 / (98 GPa)
+NPT_COUPLING = dict(T0=300.0, tau_T=100.0, P0_GPa=0.0, tau_P=1000.0, beta_per_GPa=0.0102)
+
+
+def bench_npt(W, args, nve_ms_per_step):
+    """The paper's own benchmark ensemble on the headline input: Berendsen
+    NPT at 300 K and 0 Pa, both precisions."""
+    torch, mb, wl = W.torch, W.mb, W.wl
+    n, steps = W.n, args.npt_steps
+
+    def pressure_gpa(row, box):
+        # (2 E_kin + tr W) / (3 V), eV/A^3 -> GPa
+        return (2.0 * row[1] + row[2] + row[6] + row[10]) / (3.0 * float(box.prod())) * 160.21766208
+
+    res = {}
+    for prec in ("fp64", "mixed"):
+        run = lambda k, pos, vel: W.ctx.npt_run(pos, vel, W.s.box, wl.M_SI, 1.0, k, W.every,
+                                                precision=prec, out=W.out, **NPT_COUPLING)
+        if args.warmup > 0:
+            run(args.warmup, W.pos0.clone(), W.vel0.clone())
+        pos, vel = W.pos0.clone(), W.vel0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = run(steps, pos, vel)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = W.ctx.run_stats()
+        th = out["thermo"].cpu().numpy()
+        bt = out["box_traj"].cpu().numpy()
+        p_gpa = [pressure_gpa(th[k], bt[k]) for k in (0, steps)]
+        log(f"NPT {prec}: {t:.3f} s, {n * steps / t:.4e} atom-steps/s")
+        res[prec] = {"value": n * steps / t, "unit": "atom-steps/s", "steps": steps,
+                     "ms_per_step": 1e3 * t / steps, "rebuilds": st["rebuilds"],
+                     "T_K": [round(float(th[0, 15]), 3), round(float(th[-1, 15]), 3)],
+                     "P_GPa": [round(p, 5) for p in p_gpa],
+                     "box_edge_A": [float(bt[0, 0]), float(bt[-1, 0])]}
+    psteps = min(args.profile_steps, steps)
+    W.ctx.set_profiling(True)
+    W.ctx.reset_profile()
+    W.ctx.npt_run(W.pos0.clone(), W.vel0.clone(), W.s.box, wl.M_SI, 1.0, psteps, W.every,
+                  out=W.out, **NPT_COUPLING)
+    prof = W.ctx.profile()
+    W.ctx.set_profiling(False)
+    res["kernels"] = {k: {"launches": c, "avg_us": round(1e3 * ms / c, 3)}
+                      for k, (c, ms) in prof.items() if c}
+    res["fp64_vs_nve_time"] = round(res["fp64"]["ms_per_step"] / nve_ms_per_step, 4)
+    res["coupling"] = NPT_COUPLING
+    res["config"] = {"workload": "tersoff_si_diamond_40x40x40_512000_atoms_npt_berendsen",
+                     "atoms": n, "rebuild_every": W.every, "dt_fs": 1.0}
+    return res
+
+
 def bench_sw(mb, wl, torch, args):
     log("generating the 1,000,000-atom SW Si input (seed 1003)")
     s = wl.sw_1m()
@@ -424,6 +478,7 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=10000)
     ap.add_argument("--mixed-check", type=int, default=1000)
     ap.add_argument("--sw-steps", type=int, default=1000)
+    ap.add_argument("--npt-steps", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -436,6 +491,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sw", action="store_true")
+    ap.add_argument("--no-npt", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200,
                     help="steps of the HIP-event profiled pass used for the roofline")
@@ -541,6 +597,7 @@ def main():
         del a, b
 
     mixed = None if args.no_mixed else bench_mixed(W, args)
+    npt = None if args.no_npt else bench_npt(W, args, 1e3 * t64 / args.steps)
     W.close()
     sw = None if args.no_sw else bench_sw(mb, wl, torch, args)
     serve = None if args.no_serving else bench_serving(mb, wl, torch, args)
@@ -575,6 +632,7 @@ def main():
         "fp64_run": {"rebuilds": st64["rebuilds"],
                      "energy_change_eV_per_atom": float((th64[-1, 14] - th64[0, 14]) / n)},
         "mixed": mixed,
+        "npt": npt,
         "sw_1m": sw,
         "serving": serve,
         "speed_vs_n": sweep,
