@@ -237,6 +237,24 @@ mbmd_status mbmd_npt_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, double b
                          const mbmd_berendsen *coupling, double *U, double *F, double *W,
                          double *J, double *thermo, double *box_traj);
 
+/* Green-Kubo analysis of the total heat current J = sum_i J_i (the
+ * potential part of Section 2.3, whose purpose is thermal-conductivity
+ * calculations; the Green-Kubo relation itself is the textbook one).
+ * thermo (device, [n_rows][16], as written by mbmd_nve_run or mbmd_npt_run,
+ * one row per dt_fs) is sampled at rows 0, e, 2e, ... (e = sample_every),
+ * S = (n_rows - 1)/e + 1 samples.  hac (device, [max_lag][3]) receives
+ * C_a(k) = 1/(S - k) sum_{t=0}^{S-k-1} J_a(t) J_a(t + k) for k < max_lag
+ * and a = x, y, z (every time origin used), in (eV A/fs)^2; kappa (device,
+ * [max_lag][3], or NULL) the running conductivity in W/(m K),
+ * kappa_a(K) = e dt / (k_B T^2 V) [C_a(0)/2 + C_a(1) + ... + C_a(K)/2]
+ * (trapezoid rule, kappa_a(0) = 0), with V = volume_A3 and T = T_K.
+ * Needs 1 <= max_lag <= S; MBMD_EINVAL otherwise.  The context allocates
+ * (and keeps) a scratch of 8 (3 S + min(64, ceil(S/1024)) 3 max_lag) bytes.
+ * Synchronous; the result bits do not depend on the run. */
+mbmd_status mbmd_green_kubo(mbmd_ctx *ctx, const double *thermo, int64_t n_rows,
+                            int sample_every, int max_lag, double dt_fs, double volume_A3,
+                            double T_K, double *hac, double *kappa);
+
 /* Wait for everything this context enqueued on its stream and report (and
  * clear) the device status word: MBMD_ENONFINITE, MBMD_ENEIGH or
  * MBMD_EINVAL (atom type) for a condition raised since the last report,

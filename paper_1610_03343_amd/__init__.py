@@ -86,6 +86,7 @@ def _load():
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
         "mbmd_npt_run": ([P, I, I64, P, D, P, P, P, D, I, I, C.POINTER(mbmd_berendsen), P, P,
                           P, P, P, P], I),
+        "mbmd_green_kubo": ([P, P, I64, I, I, D, D, D, P, P], I),
         "mbmd_batch_open": ([P, I64, I, I], I),
         "mbmd_batch_workspace_size": ([P, I64, I, C.POINTER(C.c_size_t)], I),
         "mbmd_batch_capacity": ([P, C.POINTER(I64), C.POINTER(I), C.POINTER(I64)], I),
@@ -322,6 +323,23 @@ class Context:
         out["box"] = np.array([b[0], b[1], b[2]])
         if bt is not None:
             out["box_traj"] = bt
+        return out
+
+    def green_kubo(self, thermo, sample_every, max_lag, dt, volume, T, kappa=True):
+        """Heat-current autocorrelation and running Green-Kubo conductivity
+        (mbmd_green_kubo) from thermo rows on the device; returns dict(hac,
+        kappa) of (max_lag, 3) device tensors."""
+        n_rows = thermo.shape[0]
+        hac = torch.empty(max_lag, 3, dtype=torch.float64, device=self.device)
+        kap = torch.empty(max_lag, 3, dtype=torch.float64, device=self.device) if kappa else None
+        self._check(_lib.mbmd_green_kubo(
+            self._h, _dptr(thermo, (n_rows, THERMO_COLS), "thermo"), int(n_rows),
+            int(sample_every), int(max_lag), float(dt), float(volume), float(T),
+            _dptr(hac, (max_lag, 3), "hac"),
+            _dptr(kap, (max_lag, 3), "kappa") if kap is not None else None), "mbmd_green_kubo")
+        out = {"hac": hac}
+        if kap is not None:
+            out["kappa"] = kap
         return out
 
     # -- serving batch --------------------------------------------------------

@@ -30,6 +30,8 @@ struct ProfRec {
 
 constexpr double kKappa = 9.64853321567e-3;   // eV/(A amu) in A/fs^2
 constexpr double kGPaPerEvA3 = 160.21766208;   // 1 eV/A^3 in GPa
+constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
+constexpr double kWPerMKPerEvFsAK = 1.602176634e6;   // eV/(fs A K) in W/(m K)
 
 // One structure admitted to the serving batch.
 struct Slot {
@@ -88,6 +90,8 @@ struct mbmd_ctx {
     std::vector<Seg> segs_host;  // segment table of the current launch set
     Segs segs{};
     Batch* batch = nullptr;
+    void* gk_ws = nullptr;       // Green-Kubo scratch (own allocation)
+    size_t gk_bytes = 0;
     std::string err;
     bool profiling = false;
     std::vector<ProfRec> prof_pending;
@@ -870,6 +874,10 @@ void mbmd_destroy(mbmd_ctx* c)
         (void)hipSetDevice(c->device);
         (void)hipFree(c->ws);
     }
+    if (c->gk_ws) {
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->gk_ws);
+    }
     free_batch(c);
     delete c;
 }
@@ -1101,6 +1109,41 @@ mbmd_status mbmd_npt_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, double box
                                na, U, F, W, J, thermo, box_traj, box);
     return npt_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
                             na, U, F, W, J, thermo, box_traj, box);
+}
+
+mbmd_status mbmd_green_kubo(mbmd_ctx* c, const double* thermo, int64_t n_rows, int sample_every,
+                            int max_lag, double dt_fs, double volume_A3, double T_K, double* hac,
+                            double* kappa)
+{
+    if (!c) return MBMD_EINVAL;
+    if (!thermo || !hac) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    if (n_rows < 1 || sample_every < 1 || max_lag < 1)
+        return fail(c, MBMD_EINVAL, "need n_rows >= 1, sample_every >= 1, max_lag >= 1%s");
+    const int64_t S = (n_rows - 1) / sample_every + 1;
+    if (max_lag > S) return fail(c, MBMD_EINVAL, "max_lag exceeds the number of samples%s");
+    if (!(dt_fs > 0.0) || !(volume_A3 > 0.0) || !(T_K > 0.0) || !std::isfinite(dt_fs) ||
+        !std::isfinite(volume_A3) || !std::isfinite(T_K))
+        return fail(c, MBMD_EINVAL, "need finite dt, volume and temperature > 0%s");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const size_t need = gk_scratch_bytes(S, max_lag);
+    if (c->gk_bytes < need) {
+        if (c->gk_ws) (void)hipFree(c->gk_ws);
+        c->gk_ws = nullptr;
+        c->gk_bytes = 0;
+        if (hipMalloc(&c->gk_ws, need) != hipSuccess) {
+            c->gk_ws = nullptr;
+            return fail(c, MBMD_ENOMEM, "hipMalloc of the correlation scratch failed%s");
+        }
+        c->gk_bytes = need;
+    }
+    const double dtau = dt_fs * sample_every;
+    const double scale = dtau / (kBoltzmannEv * T_K * T_K * volume_A3) * kWPerMKPerEvFsAK;
+    e = launch_green_kubo(thermo, S, sample_every, max_lag, scale, (double*)c->gk_ws, hac, kappa,
+                          c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "green-kubo launch");
+    return MBMD_OK;
 }
 
 // ---- serving batch ----------------------------------------------------------

@@ -254,6 +254,14 @@ hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring
 // the segment's box (b.seg) by mu.
 hipError_t launch_npt_fold(const Buffers& b, const Segs& S, int ring_row, int step, bool last,
                            const NptArgs& a, double* thermo, double* box_traj, hipStream_t s);
+// Green-Kubo: heat-current autocorrelation hac[max_lag][3] and running
+// conductivity kappa[max_lag][3] (null: not formed, scaled by `scale`) from
+// S samples, thermo rows 0, every, 2 every, ... (columns 11..13).  scratch
+// holds gk_scratch_bytes(S, max_lag) bytes of device memory.
+size_t gk_scratch_bytes(int64_t S, int max_lag);
+hipError_t launch_green_kubo(const double* thermo, int64_t S, int every, int max_lag,
+                             double scale, double* scratch, double* hac, double* kappa,
+                             hipStream_t s);
 // Weak coupling: v <- lambda v + (dt/2) kappa F / m, x <- wrap(mu x + dt v)
 // in the (already scaled) box, in place in position buffer `cur`.
 hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_t s);
