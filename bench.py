@@ -346,6 +346,64 @@ def bench_npt(W, args, nve_ms_per_step):
     return res
 
 
+def bench_green_kubo(mb, wl, torch, args):
+    """Green-Kubo from the per-step heat current: an NVE run of an 8000-atom
+    crystal, its running conductivity, and the correlation kernel timed on
+    a 1,000,000-sample synthetic series with 10,000 lags."""
+    import numpy as np
+    log("green-kubo: generating the 8,000-atom Tersoff Si input (seed 1004)")
+    s = wl.silicon_crystal(10, seed=1004)
+    W = Workload(mb, wl, torch, s, "tersoff", 20, 0.5, 16)
+    steps, every, lags = args.gk_steps, 5, 2000
+    t, st, _, _, _ = W.timed("fp64", steps, 1000)
+    thermo = torch.empty(steps + 1, mb.THERMO_COLS, dtype=torch.float64, device=W.dev)
+    W.run("fp64", steps, thermo=thermo)
+    th_host = thermo.cpu().numpy()
+    T = float(th_host[:, 15].mean())
+    V = float(np.prod(s.box))
+    gk_t = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = W.ctx.green_kubo(thermo, every, lags, 1.0, V, T)
+        gk_t.append(time.perf_counter() - t0)
+    kap = out["kappa"].cpu().numpy()
+    tail = kap[int(0.8 * lags):]
+    log(f"green-kubo: NVE {steps} steps in {t:.2f} s; kappa(last 20% of 10 ps) "
+        f"{tail.mean(axis=0)} W/(m K)")
+    W.close()
+    # the correlation kernel at a larger size
+    S, K = 1_000_000, 10_000
+    g = torch.Generator(device=W.dev).manual_seed(1005)
+    big = torch.randn(S, mb.THERMO_COLS, dtype=torch.float64, device=W.dev, generator=g)
+    ctx = mb.Context(0)
+    ctx.green_kubo(big, 1, K, 1.0, 1.0, 300.0)
+    big_t = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.green_kubo(big, 1, K, 1.0, 1.0, 300.0)
+        big_t.append(time.perf_counter() - t0)
+    ctx.close()
+    del big
+    fma = 3 * (K * S - K * (K - 1) // 2)
+    tb = min(big_t)
+    log(f"green-kubo: {S} samples x {K} lags in {1e3 * tb:.2f} ms, "
+        f"{2 * fma / tb / 1e12:.2f} TFLOP/s")
+    return {"md": {"workload": "tersoff_si_diamond_10x10x10_8000_atoms_nve", "atoms": s.n,
+                   "steps": steps, "dt_fs": 1.0, "seed": 1004, "seconds": t,
+                   "atom_steps_per_s": s.n * steps / t, "rebuilds": st["rebuilds"],
+                   "mean_T_K": T},
+            "analysis": {"sample_every": every, "lags": lags, "window_ps": lags * every * 1e-3,
+                         "call_ms": round(1e3 * min(gk_t), 3),
+                         "kappa_last20pct_W_per_mK": [float(x) for x in tail.mean(axis=0)],
+                         "note": "one short run: a statistical estimate, not a converged value"},
+            "correlator": {"samples": S, "lags": K, "call_ms": round(1e3 * tb, 3),
+                           "algorithmic_fma": fma,
+                           "achieved_TFLOPs": round(2 * fma / tb / 1e12, 3),
+                           "peak_fp64_TFLOPs": FP64_VECTOR_PEAK_TFLOPS}}
+
+
 def bench_sw(mb, wl, torch, args):
     log("generating the 1,000,000-atom SW Si input (seed 1003)")
     s = wl.sw_1m()
@@ -479,6 +537,7 @@ def main():
     ap.add_argument("--mixed-check", type=int, default=1000)
     ap.add_argument("--sw-steps", type=int, default=1000)
     ap.add_argument("--npt-steps", type=int, default=1000)
+    ap.add_argument("--gk-steps", type=int, default=100000)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -492,6 +551,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sw", action="store_true")
     ap.add_argument("--no-npt", action="store_true")
+    ap.add_argument("--no-gk", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200,
                     help="steps of the HIP-event profiled pass used for the roofline")
@@ -601,6 +661,7 @@ def main():
     W.close()
     sw = None if args.no_sw else bench_sw(mb, wl, torch, args)
     serve = None if args.no_serving else bench_serving(mb, wl, torch, args)
+    gkr = None if args.no_gk else bench_green_kubo(mb, wl, torch, args)
     sweep = bench_sweep(mb, wl, torch, args) if args.sweep_cells else None
 
     cpu = None
@@ -633,6 +694,7 @@ def main():
                      "energy_change_eV_per_atom": float((th64[-1, 14] - th64[0, 14]) / n)},
         "mixed": mixed,
         "npt": npt,
+        "green_kubo": gkr,
         "sw_1m": sw,
         "serving": serve,
         "speed_vs_n": sweep,
