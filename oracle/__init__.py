@@ -28,6 +28,11 @@ class _Tersoff(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("A", "B", "lam", "mu", "beta", "n", "c", "d", "h", "R", "S")]
 
 
+class _TersoffMulti(C.Structure):
+    _fields_ = [("ntypes", C.c_int), ("types", C.c_void_p), ("elem", C.c_void_p),
+                ("chi", C.c_void_p)]
+
+
 class _SW(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("epsilon", "sigma", "a", "lam", "gamma", "A", "B", "p", "q")]
 
@@ -49,13 +54,16 @@ def _load():
             fn.argtypes = [C.c_long, _dp, _dp, P, _ip, _ip, C.c_int, C.POINTER(st),
                            _dp, _dp, _dp, _dp, P, P, P, P]
             fn.restype = C.c_int
-        lib.ora_nve.argtypes = [C.c_int, P, C.c_long, _dp, C.c_double, _dp, _dp, C.c_int,
+        lib.ora_nve.argtypes = [C.c_int, P, C.c_long, _dp, C.c_double, P, _dp, _dp, C.c_int,
                                 C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                 _dp, _dp, _dp, _dp, P, C.POINTER(C.c_long)]
         D = C.c_double
-        lib.ora_npt.argtypes = [C.c_int, P, C.c_long, _dp, D, _dp, _dp, C.c_int, D, D, C.c_int,
-                                C.c_int, D, D, D, D, D, _dp, _dp, _dp, _dp, _dp, _dp,
+        lib.ora_npt.argtypes = [C.c_int, P, C.c_long, _dp, D, P, _dp, _dp, C.c_int, D, D,
+                                C.c_int, C.c_int, D, D, D, D, D, _dp, _dp, _dp, _dp, _dp, _dp,
                                 C.POINTER(C.c_long)]
+        lib.ora_tersoff_multi.argtypes = [C.c_long, _dp, _dp, P, _ip, C.c_int, P, P, _ip, _ip,
+                                          C.c_int, _dp, _dp, _dp, _dp, P, P, P, P]
+        lib.ora_tersoff_multi.restype = C.c_int
         lib.ora_npt.restype = C.c_int
         lib.ora_wrap.argtypes = [C.c_long, _dp, _dp]
         lib.ora_wrap.restype = None
@@ -135,6 +143,58 @@ def _force(name, params, pos, box, nn, nl, vel=None, want_g=False):
     return out
 
 
+class _MultiArgs:
+    """Keeps the ctypes arrays of a multicomponent parameter set alive."""
+
+    def __init__(self, multi):
+        elems = multi["elems"]
+        nt = len(elems)
+        self.types = np.ascontiguousarray(multi["types"], dtype=np.int32)
+        self.elem = (_Tersoff * nt)(*[tersoff_params(e) for e in elems])
+        chi = multi.get("chi")
+        self.chi = None if chi is None else np.ascontiguousarray(chi, dtype=np.float64).reshape(nt, nt)
+        self.nt = nt
+        self.struct = _TersoffMulti(nt, self.types.ctypes.data_as(C.c_void_p),
+                                    C.cast(self.elem, C.c_void_p), _ptr(self.chi))
+
+
+def tersoff_multi(multi, pos, box, nn, nl, vel=None, want_g=False):
+    """Multicomponent Tersoff (ora_tersoff_multi).  multi = dict(elems=[param
+    dicts], chi=(nt, nt) array or None, types=(n,) ints).  Returns the outputs
+    of tersoff()."""
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    m = _MultiArgs(multi)
+    maxnb = nl.shape[1]
+    nl = np.ascontiguousarray(nl, dtype=np.int32)
+    nn = np.ascontiguousarray(nn, dtype=np.int32)
+    velc = None if vel is None else _f64(vel)
+    U, F, W, J = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 9)), np.zeros((n, 3))
+    Fp, WL, JL = np.zeros((n, 3)), np.zeros((n, 9)), np.zeros((n, 3))
+    G = np.zeros((n, maxnb, 3)) if want_g else None
+    st = lib.ora_tersoff_multi(n, _f64(box), pos, _ptr(velc), m.types, m.nt, C.cast(m.elem, C.c_void_p),
+                               _ptr(m.chi), nn, nl, maxnb, U, F, W, J, _ptr(Fp), _ptr(WL),
+                               _ptr(JL), _ptr(G))
+    if st:
+        raise OracleError(st)
+    out = dict(U=U, F=F, W=W, J=J, Fpair=Fp, WL=WL, JL=JL)
+    if want_g:
+        out["G"] = G
+    return out
+
+
+def _potential(potential, params):
+    """(id, ctypes parameter struct, keep-alive) for the integrators."""
+    if potential == "tersoff":
+        pr = tersoff_params(params)
+        return 0, pr, None
+    if potential == "tersoff_multi":
+        m = _MultiArgs(params)
+        return 2, m.struct, m
+    return 1, sw_params(params), None
+
+
 def tersoff(params, pos, box, nn, nl, vel=None, want_g=False):
     """Per-atom U, F (Algorithm 1 scatter), W, J (pairwise), Fpair, WL, JL[, G]."""
     return _force("ora_tersoff", params, pos, box, nn, nl, vel, want_g)
@@ -146,11 +206,13 @@ def sw(params, pos, box, nn, nl, vel=None, want_g=False):
 
 def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: float,
         rlist: float, rebuild_every: int, maxnb: int, skin: float = 0.5,
-        check_skin: bool = True):
+        check_skin: bool = True, masses=None):
     """Velocity-Verlet NVE.  Returns dict(pos, vel, U, F, W, J,
     thermo[n_steps+1, 16], builds).  The list is rebuilt every rebuild_every
     steps and, with check_skin, before any step whose positions moved more
-    than skin/2 from the last build."""
+    than skin/2 from the last build.  potential: "tersoff", "sw" or
+    "tersoff_multi" (params as for tersoff_multi); masses: per-atom masses
+    replacing `mass`."""
     lib = _load()
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
@@ -160,12 +222,11 @@ def nve(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: fl
     W = np.zeros((n, 9))
     J = np.zeros((n, 3))
     thermo = np.zeros((n_steps + 1, 16))
-    if potential == "tersoff":
-        pr, pid = tersoff_params(params), 0
-    else:
-        pr, pid = sw_params(params), 1
+    pid, pr, keep = _potential(potential, params)
+    mz = None if masses is None else _f64(masses)
     builds = C.c_long(0)
-    st = lib.ora_nve(pid, C.cast(C.byref(pr), C.c_void_p), n, _f64(box), float(mass), pos, vel,
+    st = lib.ora_nve(pid, C.cast(C.byref(pr), C.c_void_p), n, _f64(box), float(mass), _ptr(mz),
+                     pos, vel,
                      int(n_steps), float(dt), float(rlist), float(skin), int(rebuild_every),
                      int(bool(check_skin)), int(maxnb), U, F, W, J, _ptr(thermo),
                      C.byref(builds))
@@ -180,11 +241,11 @@ EV_PER_A3_IN_GPA = 160.21766208
 
 def npt(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: float,
         rlist: float, rebuild_every: int, maxnb: int, T0: float, tau_T: float, P0_GPa: float,
-        tau_P: float, beta_per_GPa: float):
+        tau_P: float, beta_per_GPa: float, masses=None):
     """Velocity-Verlet with Berendsen weak coupling (see ora_npt).  P0 in GPa,
     compressibility beta in 1/GPa; tau_T, tau_P in fs (<= 0: that coupling
-    off).  Returns dict(pos, vel, box, U, F, W, J, thermo[n_steps+1, 16],
-    box_traj[n_steps+1, 3], builds)."""
+    off); potential and masses as for nve().  Returns dict(pos, vel, box, U,
+    F, W, J, thermo[n_steps+1, 16], box_traj[n_steps+1, 3], builds)."""
     lib = _load()
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
@@ -196,12 +257,11 @@ def npt(potential: str, params, pos, vel, box, mass: float, n_steps: int, dt: fl
     J = np.zeros((n, 3))
     thermo = np.zeros((n_steps + 1, 16))
     box_traj = np.zeros((n_steps + 1, 3))
-    if potential == "tersoff":
-        pr, pid = tersoff_params(params), 0
-    else:
-        pr, pid = sw_params(params), 1
+    pid, pr, keep = _potential(potential, params)
+    mz = None if masses is None else _f64(masses)
     builds = C.c_long(0)
-    st = lib.ora_npt(pid, C.cast(C.byref(pr), C.c_void_p), n, boxc, float(mass), pos, vel,
+    st = lib.ora_npt(pid, C.cast(C.byref(pr), C.c_void_p), n, boxc, float(mass), _ptr(mz), pos,
+                     vel,
                      int(n_steps), float(dt), float(rlist), int(rebuild_every), int(maxnb),
                      float(T0), float(tau_T), float(P0_GPa) / EV_PER_A3_IN_GPA, float(tau_P),
                      float(beta_per_GPa) * EV_PER_A3_IN_GPA, U, F, W, J, thermo, box_traj,

@@ -342,16 +342,21 @@ static void stress_current(long n, const double *WL, const double *vel, double *
         }
 }
 
-/* Tersoff, conventional Algorithm 1 with capture.
+/* Tersoff, conventional Algorithm 1 with capture, for nt atom types.
+ * P[ti*nt + tj] holds the parameters of the ordered pair (i, j): A, B, lambda,
+ * mu, R, S of the pair (bond i-j terms, and f_C(r_ik) when used as the pair
+ * (i, k)) and beta, n, c, d, h of the centre atom i; chi[ti*nt + tj] (or NULL:
+ * 1) multiplies b_ij.  types == NULL means every atom is type 0.
  * In:  pos[n*3] (wrapped), vel[n*3] or NULL, nn[n], nl[n*maxnb] (symmetric,
- *      ascending), p.
+ *      ascending).
  * Out: U[n], F[n*3] (scatter), W[n*9], J[n*3] (pairwise, the paper's), and
  *      optionally Fpair[n*3] = sum_j F_ij, WL[n*9] (LAMMPS form), JL[n*3]
  *      (stress-based), G[n*maxnb*3] = dU_i/dr_{NL_im}.  NULL skips an output. */
-int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
-                const int *nn, const int *nl, int maxnb, const ora_tersoff_t *p,
-                double *U, double *F, double *W, double *J,
-                double *Fpair, double *WL, double *JL, double *Gout)
+static int tersoff_core(long n, const double *box, const double *pos, const double *vel,
+                        const int *types, int nt, const ora_tersoff_t *P, const double *chi,
+                        const int *nn, const int *nl, int maxnb,
+                        double *U, double *F, double *W, double *J,
+                        double *Fpair, double *WL, double *JL, double *Gout)
 {
     for (long i = 0; i < n; ++i)
         if (nn[i] > maxnb) return ORA_ENEIGH;
@@ -366,8 +371,11 @@ int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
     }
     for (long i = 0; i < n; ++i) {
         int cnt = nn[i];
+        const int ti = types ? types[i] : 0;
         for (int m = 0; m < cnt; ++m) {
             long j = nl[i * maxnb + m];
+            const int tj = types ? types[j] : 0;
+            const ora_tersoff_t *p = &P[ti * nt + tj];
             double rij[3];
             min_image(box, &pos[i * 3], &pos[j * 3], rij);
             double r = sqrt(dot3(rij, rij));
@@ -378,14 +386,19 @@ int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
             for (int q = 0; q < cnt; ++q) {
                 if (q == m) continue;
                 long k = nl[i * maxnb + q];
+                const ora_tersoff_t *pk = &P[ti * nt + (types ? types[k] : 0)];
                 double rik[3];
                 min_image(box, &pos[i * 3], &pos[k * 3], rik);
                 double rk = sqrt(dot3(rik, rik));
-                if (rk >= p->S) continue;
+                if (rk >= pk->S) continue;
                 double cs = dot3(rij, rik) / (r * rk);
-                zeta += t_fc(p, rk) * t_g(p, cs);
+                zeta += t_fc(pk, rk) * t_g(pk, cs);
             }
             double b = t_b(p, zeta), db = t_db(p, zeta);
+            if (chi) {
+                b *= chi[ti * nt + tj];
+                db *= chi[ti * nt + tj];
+            }
             double fc = t_fc(p, r), dfc = t_dfc(p, r);
             double fr = t_fr(p, r), dfr = t_dfr(p, r);
             double fa = t_fa(p, r), dfa = t_dfa(p, r);
@@ -415,12 +428,13 @@ int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
             for (int q = 0; q < cnt; ++q) {                        /* lines 11-25 */
                 if (q == m) continue;
                 long k = nl[i * maxnb + q];
+                const ora_tersoff_t *pk = &P[ti * nt + (types ? types[k] : 0)];
                 double rik[3];
                 min_image(box, &pos[i * 3], &pos[k * 3], rik);
                 double rk = sqrt(dot3(rik, rik));
-                if (rk >= p->S) continue;
+                if (rk >= pk->S) continue;
                 double gi[3], gj[3], gk[3];
-                t_grad_fcg(p, rij, r, rik, rk, gi, gj, gk);
+                t_grad_fcg(pk, rij, r, rik, rk, gi, gj, gk);
                 double fi[3], fj[3], fk[3];
                 for (int a = 0; a < 3; ++a) {
                     fi[a] = pref * gi[a];
@@ -450,6 +464,58 @@ int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
     if (!Gout) free(G);
     free(wl);
     return st;
+}
+
+/* Single-element Tersoff (the form the paper prints in Section 2.1). */
+int ora_tersoff(long n, const double *box, const double *pos, const double *vel,
+                const int *nn, const int *nl, int maxnb, const ora_tersoff_t *p,
+                double *U, double *F, double *W, double *J,
+                double *Fpair, double *WL, double *JL, double *Gout)
+{
+    return tersoff_core(n, box, pos, vel, NULL, 1, p, NULL, nn, nl, maxnb, U, F, W, J, Fpair,
+                        WL, JL, Gout);
+}
+
+/* Tersoff's multicomponent form (Tersoff 1989, the potential the paper
+ * cites; the paper states its method covers several atom types, Section
+ * 2.1): per-element parameters elem[nt] with the mixing rules
+ *   A_ij = sqrt(A_i A_j), B_ij = sqrt(B_i B_j), lambda_ij = (lambda_i + lambda_j)/2,
+ *   mu_ij = (mu_i + mu_j)/2, R_ij = sqrt(R_i R_j), S_ij = sqrt(S_i S_j),
+ * b_ij = chi_ij (1 + beta_i^n_i zeta_ij^n_i)^(-1/(2 n_i)), zeta_ij summing
+ * f_C(r_ik) with the (i, k) cutoff and g with atom i's c, d, h.  chi[nt*nt]
+ * (NULL: all 1) must be symmetric; types[n] in [0, nt). */
+int ora_tersoff_multi(long n, const double *box, const double *pos, const double *vel,
+                      const int *types, int nt, const ora_tersoff_t *elem, const double *chi,
+                      const int *nn, const int *nl, int maxnb,
+                      double *U, double *F, double *W, double *J,
+                      double *Fpair, double *WL, double *JL, double *Gout)
+{
+    if (nt < 1 || nt > 8 || !elem || !types) return ORA_EINVAL;
+    for (long i = 0; i < n; ++i)
+        if (types[i] < 0 || types[i] >= nt) return ORA_EINVAL;
+    if (chi)
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b)
+                if (chi[a * nt + b] != chi[b * nt + a]) return ORA_EINVAL;
+    ora_tersoff_t P[64];
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const ora_tersoff_t *x = &elem[a], *y = &elem[b];
+            ora_tersoff_t *q = &P[a * nt + b];
+            q->A = sqrt(x->A * y->A);
+            q->B = sqrt(x->B * y->B);
+            q->lam = 0.5 * (x->lam + y->lam);
+            q->mu = 0.5 * (x->mu + y->mu);
+            q->R = sqrt(x->R * y->R);
+            q->S = sqrt(x->S * y->S);
+            q->beta = x->beta;
+            q->n = x->n;
+            q->c = x->c;
+            q->d = x->d;
+            q->h = x->h;
+        }
+    return tersoff_core(n, box, pos, vel, types, nt, P, chi, nn, nl, maxnb, U, F, W, J, Fpair,
+                        WL, JL, Gout);
 }
 
 /* ----------------------------------------------------- Stillinger-Weber */
@@ -578,6 +644,14 @@ int ora_sw(long n, const double *box, const double *pos, const double *vel,
 #define ORA_KAPPA 9.64853321567e-3     /* eV/(A amu) in A/fs^2 */
 #define ORA_KB 8.617333262e-5          /* eV/K */
 
+/* Parameters of potential 2 (multicomponent Tersoff) for the integrators. */
+typedef struct {
+    int ntypes;
+    const int *types;
+    const ora_tersoff_t *elem;
+    const double *chi;
+} ora_tersoff_multi_t;
+
 static int evaluate(int potential, const void *params, long n, const double *box,
                     const double *pos, const double *vel, const int *nn, const int *nl,
                     int maxnb, double *U, double *F, double *W, double *J, double *G)
@@ -585,18 +659,25 @@ static int evaluate(int potential, const void *params, long n, const double *box
     if (potential == 0)
         return ora_tersoff(n, box, pos, vel, nn, nl, maxnb, (const ora_tersoff_t *)params,
                            U, F, W, J, NULL, NULL, NULL, G);
+    if (potential == 2) {
+        const ora_tersoff_multi_t *m = (const ora_tersoff_multi_t *)params;
+        return ora_tersoff_multi(n, box, pos, vel, m->types, m->ntypes, m->elem, m->chi, nn, nl,
+                                 maxnb, U, F, W, J, NULL, NULL, NULL, G);
+    }
     return ora_sw(n, box, pos, vel, nn, nl, maxnb, (const ora_sw_t *)params,
                   U, F, W, J, NULL, NULL, NULL, G);
 }
 
-static void thermo_row(long n, double mass, const double *U, const double *vel,
-                       const double *W, const double *J, double *row)
+/* masses: per-atom masses, or NULL for `mass` on every atom. */
+static void thermo_row(long n, double mass, const double *masses, const double *U,
+                       const double *vel, const double *W, const double *J, double *row)
 {
     memset(row, 0, sizeof(double) * 16);
     double ep = 0.0, ek = 0.0;
     for (long i = 0; i < n; ++i) {
+        const double m = masses ? masses[i] : mass;
         ep += U[i];
-        ek += 0.5 * mass * dot3(&vel[i * 3], &vel[i * 3]) / ORA_KAPPA;
+        ek += 0.5 * m * dot3(&vel[i * 3], &vel[i * 3]) / ORA_KAPPA;
         for (int c = 0; c < 9; ++c) row[2 + c] += W[i * 9 + c];
         for (int c = 0; c < 3; ++c) row[11 + c] += J[i * 3 + c];
     }
@@ -626,12 +707,21 @@ static double max_disp2(long n, const double *box, const double *pos, const doub
     return worst;
 }
 
-int ora_nve(int potential, const void *params, long n, const double *box, double mass,
-            double *pos, double *vel, int n_steps, double dt, double rlist, double skin,
-            int rebuild_every, int check_skin, int maxnb, double *U, double *F, double *W,
-            double *J, double *thermo, long *n_builds)
+static int masses_ok(long n, double mass, const double *masses)
 {
-    if (n < 1 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !(mass > 0.0))
+    if (!masses) return mass > 0.0;
+    for (long i = 0; i < n; ++i)
+        if (!(masses[i] > 0.0)) return 0;
+    return 1;
+}
+
+/* masses: per-atom masses (amu), or NULL for `mass` on every atom. */
+int ora_nve(int potential, const void *params, long n, const double *box, double mass,
+            const double *masses, double *pos, double *vel, int n_steps, double dt,
+            double rlist, double skin, int rebuild_every, int check_skin, int maxnb, double *U,
+            double *F, double *W, double *J, double *thermo, long *n_builds)
+{
+    if (n < 1 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !masses_ok(n, mass, masses))
         return ORA_EINVAL;
     int st = check_box(box, rlist);
     if (st) return st;
@@ -647,14 +737,15 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
     int last_build = 0;
     double lim = 0.25 * skin * skin;
     if (!st) st = evaluate(potential, params, n, box, pos, vel, nn, nl, maxnb, U, F, W, J, G);
-    if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[0]);
-    double half = 0.5 * dt * ORA_KAPPA / mass;
+    if (!st && thermo) thermo_row(n, mass, masses, U, vel, W, J, &thermo[0]);
     for (int s = 1; s <= n_steps && !st; ++s) {
-        for (long i = 0; i < n; ++i)
+        for (long i = 0; i < n; ++i) {
+            const double half = 0.5 * dt * ORA_KAPPA / (masses ? masses[i] : mass);
             for (int a = 0; a < 3; ++a) {
                 vel[i * 3 + a] += half * F[i * 3 + a];
                 pos[i * 3 + a] += dt * vel[i * 3 + a];
             }
+        }
         ora_wrap(n, box, pos);
         if (s - last_build == rebuild_every ||
             (check_skin && max_disp2(n, box, pos, xb) > lim)) {
@@ -668,10 +759,12 @@ int ora_nve(int potential, const void *params, long n, const double *box, double
          * is formed from the captured partials after the second half-kick. */
         st = evaluate(potential, params, n, box, pos, NULL, nn, nl, maxnb, U, F, W, J, G);
         if (st) break;
-        for (long i = 0; i < n; ++i)
+        for (long i = 0; i < n; ++i) {
+            const double half = 0.5 * dt * ORA_KAPPA / (masses ? masses[i] : mass);
             for (int a = 0; a < 3; ++a) vel[i * 3 + a] += half * F[i * 3 + a];
+        }
         st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, NULL, J, NULL);
-        if (!st && thermo) thermo_row(n, mass, U, vel, W, J, &thermo[(size_t)s * 16]);
+        if (!st && thermo) thermo_row(n, mass, masses, U, vel, W, J, &thermo[(size_t)s * 16]);
     }
     free(G);
     free(xb);
@@ -700,12 +793,14 @@ static double row_pressure(const double *row, double volume)
  * were evaluated in.  The list is built at step 0 and every rebuild_every
  * steps (in the box of that moment).  With tau_T <= 0 and tau_P <= 0 the
  * run is ora_nve's with check_skin off, operation for operation. */
-int ora_npt(int potential, const void *params, long n, double *box, double mass, double *pos,
-            double *vel, int n_steps, double dt, double rlist, int rebuild_every, int maxnb,
-            double T0, double tau_T, double P0, double tau_P, double beta, double *U,
-            double *F, double *W, double *J, double *thermo, double *box_traj, long *n_builds)
+int ora_npt(int potential, const void *params, long n, double *box, double mass,
+            const double *masses, double *pos, double *vel, int n_steps, double dt,
+            double rlist, int rebuild_every, int maxnb, double T0, double tau_T, double P0,
+            double tau_P, double beta, double *U, double *F, double *W, double *J,
+            double *thermo, double *box_traj, long *n_builds)
 {
-    if (n < 2 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 || !(mass > 0.0) || !thermo)
+    if (n < 2 || n_steps < 0 || rebuild_every < 1 || maxnb < 1 ||
+        !masses_ok(n, mass, masses) || !thermo)
         return ORA_EINVAL;
     int st = check_box(box, rlist);
     if (st) return st;
@@ -717,14 +812,15 @@ int ora_npt(int potential, const void *params, long n, double *box, double mass,
     st = ora_neighbors_cells(n, box, pos, rlist, maxnb, nn, nl);
     long builds = 1;
     int last_build = 0;
-    const double half = 0.5 * dt * ORA_KAPPA / mass;
     for (int s = 0; s <= n_steps && !st; ++s) {
         if (s > 0) {
-            for (long i = 0; i < n; ++i)
+            for (long i = 0; i < n; ++i) {
+                const double half = 0.5 * dt * ORA_KAPPA / (masses ? masses[i] : mass);
                 for (int a = 0; a < 3; ++a) {
                     vel[i * 3 + a] += half * F[i * 3 + a];
                     pos[i * 3 + a] += dt * vel[i * 3 + a];
                 }
+            }
             ora_wrap(n, box, pos);
             if (s - last_build == rebuild_every) {
                 st = check_box(box, rlist);
@@ -741,13 +837,15 @@ int ora_npt(int potential, const void *params, long n, double *box, double mass,
                       W, J, G);
         if (st) break;
         if (s > 0) {
-            for (long i = 0; i < n; ++i)
+            for (long i = 0; i < n; ++i) {
+                const double half = 0.5 * dt * ORA_KAPPA / (masses ? masses[i] : mass);
                 for (int a = 0; a < 3; ++a) vel[i * 3 + a] += half * F[i * 3 + a];
+            }
             st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, NULL, J, NULL);
             if (st) break;
         }
         double *row = &thermo[(size_t)s * 16];
-        thermo_row(n, mass, U, vel, W, J, row);
+        thermo_row(n, mass, masses, U, vel, W, J, row);
         if (box_traj)
             for (int a = 0; a < 3; ++a) box_traj[(size_t)s * 3 + a] = box[a];
         if (s == n_steps) break;

@@ -35,6 +35,21 @@ TERSOFF_SI_1989 = dict(
     c=100390.0, d=16.217, h=-0.59825, R=2.7, S=3.0,
 )
 
+# Tersoff's multicomponent parameter sets (Tersoff 1989, Table I), with the
+# chi of each unlike pair; the silicon set is the one above.
+TERSOFF_C_1989 = dict(
+    A=1393.6, B=346.74, lam=3.4879, mu=2.2119, beta=1.5724e-7, n=0.72751,
+    c=38049.0, d=4.3484, h=-0.57058, R=1.8, S=2.1,
+)
+TERSOFF_GE_1989 = dict(
+    A=1769.0, B=419.23, lam=2.4451, mu=1.7047, beta=9.0166e-7, n=0.75627,
+    c=106430.0, d=15.652, h=-0.43884, R=2.8, S=3.1,
+)
+CHI_SI_C_1989 = 0.9776
+CHI_SI_GE_1989 = 1.00061
+M_C = 12.011
+M_GE = 72.630
+
 # Stillinger-Weber (1985) silicon parameters; cutoff a*sigma = 3.77118 A.
 SW_SI_1985 = dict(
     epsilon=2.1683, sigma=2.0951, a=1.80, lam=21.0, gamma=1.20,
@@ -70,21 +85,31 @@ def wrap_positions(pos: np.ndarray, box: np.ndarray) -> np.ndarray:
 
 
 def maxwell_boltzmann(n: int, temperature: float, rng: np.random.Generator,
-                      mass: float = M_SI) -> np.ndarray:
+                      mass=M_SI) -> np.ndarray:
     """Velocities (Angstrom/fs) at exactly `temperature`.
 
     Per-component Gaussian with sigma = sqrt(k_B T kappa / m), centre-of-mass
     velocity removed, then rescaled so that the kinetic temperature with
-    3N - 3 degrees of freedom equals `temperature`.
+    3N - 3 degrees of freedom equals `temperature`.  `mass` is a scalar or
+    one mass per atom.
     """
     if n == 0:
         return np.zeros((0, 3))
-    sig = math.sqrt(K_B * temperature * KAPPA / mass)
-    v = rng.normal(0.0, sig, size=(n, 3))
+    m = np.broadcast_to(np.asarray(mass, dtype=np.float64), (n,))
+    uniform = bool(np.all(m == m[0]))
+    if uniform:
+        sig = math.sqrt(K_B * temperature * KAPPA / float(m[0]))
+        v = rng.normal(0.0, sig, size=(n, 3))
+    else:
+        v = rng.normal(0.0, 1.0, size=(n, 3)) * np.sqrt(K_B * temperature * KAPPA / m)[:, None]
     if n > 1:
-        v -= v.mean(axis=0)
         dof = 3 * n - 3
-        ekin = 0.5 * mass * float(np.sum(v * v)) / KAPPA
+        if uniform:
+            v -= v.mean(axis=0)
+            ekin = 0.5 * float(m[0]) * float(np.sum(v * v)) / KAPPA
+        else:
+            v -= (m[:, None] * v).sum(axis=0) / m.sum()
+            ekin = 0.5 * float(np.sum(m[:, None] * v * v)) / KAPPA
         t_now = 2.0 * ekin / (dof * K_B)
         if t_now > 0:
             v *= math.sqrt(temperature / t_now)
@@ -101,6 +126,7 @@ class System:
     box: np.ndarray
     seed: int
     meta: dict = field(default_factory=dict)
+    type_ids: np.ndarray | None = None     # None: every atom type 0
 
     @property
     def n(self) -> int:
@@ -108,7 +134,9 @@ class System:
 
     @property
     def types(self) -> np.ndarray:
-        return np.zeros(self.n, dtype=np.int32)
+        if self.type_ids is None:
+            return np.zeros(self.n, dtype=np.int32)
+        return self.type_ids
 
 
 def silicon_crystal(cells, seed: int, sigma: float = 0.05, temperature: float = 300.0,
@@ -138,6 +166,37 @@ def silicon_crystal(cells, seed: int, sigma: float = 0.05, temperature: float = 
     return System(np.ascontiguousarray(pos), np.ascontiguousarray(vel), box, seed,
                   dict(cells=(nx, ny, nz), sigma=sigma, temperature=temperature,
                        vacancy_fraction=vacancy_fraction, a=a))
+
+
+def binary_crystal(cells, seed: int, a: float, masses=(M_SI, M_C), arrangement="zincblende",
+                   fraction: float = 0.5, sigma: float = 0.05,
+                   temperature: float = 300.0) -> System:
+    """Two-element crystal on the diamond lattice, types 0 and 1.
+
+    zincblende: basis sites 0-3 (the fcc sublattice) type 0, sites 4-7 type 1;
+    random: each site type 1 with probability `fraction`.  Draw order from
+    one PCG64 stream seeded with `seed`: types (random only), displacements,
+    velocities (Maxwell-Boltzmann with each atom's mass).
+    """
+    if isinstance(cells, int):
+        cells = (cells, cells, cells)
+    nx, ny, nz = (int(c) for c in cells)
+    pos, box = diamond_lattice(nx, ny, nz, a)
+    rng = np.random.default_rng(seed)
+    if arrangement == "zincblende":
+        types = np.tile(np.array([0, 0, 0, 0, 1, 1, 1, 1], dtype=np.int32), nx * ny * nz)
+    elif arrangement == "random":
+        types = (rng.uniform(size=pos.shape[0]) < fraction).astype(np.int32)
+    else:
+        raise ValueError(arrangement)
+    if sigma > 0.0:
+        pos = pos + rng.normal(0.0, sigma, size=pos.shape)
+    pos = wrap_positions(pos, box)
+    m = np.asarray(masses, dtype=np.float64)[types]
+    vel = maxwell_boltzmann(pos.shape[0], temperature, rng, mass=m)
+    return System(np.ascontiguousarray(pos), np.ascontiguousarray(vel), box, seed,
+                  dict(cells=(nx, ny, nz), a=a, arrangement=arrangement, sigma=sigma,
+                       temperature=temperature, masses=tuple(masses)), type_ids=types)
 
 
 def cluster(n: int, seed: int, box_side: float = 60.0, min_dist: float = 2.05,
