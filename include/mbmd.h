@@ -23,8 +23,10 @@
  *    is a HOST array of edge lengths, each at least 2 * (cutoff + skin).
  *  - Positions may be given unwrapped; positions returned are wrapped into
  *    [0, L).
- *  - types may be NULL (all atoms of the one species); otherwise every entry
- *    must be 0 (single-element potentials).
+ *  - types (device int32 [n]) may be NULL (every atom type 0); otherwise
+ *    every entry must lie in [0, ntypes) of the potential: 1 for SW and the
+ *    single-element Tersoff, ntypes of mbmd_set_tersoff_multi (else
+ *    MBMD_EINVAL).
  *  - Every call enqueues its work on the context's stream and returns after
  *    synchronising that stream, with the device status folded into the
  *    return code.  Outputs are unspecified when a call fails.
@@ -123,8 +125,29 @@ void mbmd_destroy(mbmd_ctx *ctx);
  * the next call on it). */
 const char *mbmd_last_error(const mbmd_ctx *ctx);
 
-/* Select the Tersoff potential with parameters *p (copied). */
+/* Select the Tersoff potential with parameters *p (copied): one element,
+ * every atom type 0. */
 mbmd_status mbmd_set_tersoff(mbmd_ctx *ctx, const mbmd_tersoff_params *p);
+
+/* Select Tersoff's multicomponent form (Tersoff 1989, the potential the
+ * paper cites; Section 2.1 states that the method covers several atom
+ * types) for ntypes (1..4) elements: elem[ntypes] (copied) with the mixing
+ * rules A_ij = sqrt(A_i A_j), B_ij = sqrt(B_i B_j), lambda_ij = (lambda_i +
+ * lambda_j)/2, mu_ij = (mu_i + mu_j)/2, R_ij = sqrt(R_i R_j), S_ij =
+ * sqrt(S_i S_j) for the bond terms f_C, f_R, f_A of a pair, and atom i's
+ * beta, n, c, d, h in b_ij and g_ijk; b_ij is multiplied by chi[ti][tj]
+ * (chi: [ntypes][ntypes], symmetric, positive; NULL: all 1).  Atom types come
+ * from the types arrays of mbmd_compute/nve_run/npt_run (NULL: all 0) and
+ * must lie in [0, ntypes) (else MBMD_EINVAL).  The serving batch treats every
+ * atom as type 0. */
+mbmd_status mbmd_set_tersoff_multi(mbmd_ctx *ctx, int ntypes, const mbmd_tersoff_params *elem,
+                                   const double *chi);
+
+/* Per-type masses (amu) used by mbmd_nve_run and mbmd_npt_run when their
+ * mass_amu is 0: mass_amu[ntypes] (copied), ntypes in 1..4; ntypes = 0
+ * clears them.  A run with mass 0 needs a mass for every atom type of the
+ * potential (MBMD_EINVAL otherwise). */
+mbmd_status mbmd_set_type_masses(mbmd_ctx *ctx, int ntypes, const double *mass_amu);
 
 /* Select the Stillinger-Weber potential with parameters *p (copied). */
 mbmd_status mbmd_set_sw(mbmd_ctx *ctx, const mbmd_sw_params *p);

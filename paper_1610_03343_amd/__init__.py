@@ -72,6 +72,8 @@ def _load():
         "mbmd_last_error": ([P], C.c_char_p),
         "mbmd_set_tersoff": ([P, C.POINTER(mbmd_tersoff_params)], I),
         "mbmd_set_sw": ([P, C.POINTER(mbmd_sw_params)], I),
+        "mbmd_set_tersoff_multi": ([P, I, P, P], I),
+        "mbmd_set_type_masses": ([P, I, P], I),
         "mbmd_set_neighbor": ([P, D, I], I),
         "mbmd_get_max_neighbors": ([P, C.POINTER(I)], I),
         "mbmd_set_rebuild_policy": ([P, I], I),
@@ -184,6 +186,29 @@ class Context:
     def set_tersoff(self, params: dict):
         st = tersoff_struct(params)
         self._check(_lib.mbmd_set_tersoff(self._h, C.byref(st)), "mbmd_set_tersoff")
+
+    def set_tersoff_multi(self, elems, chi=None):
+        """Multicomponent Tersoff: elems = [param dict per type], chi an
+        (ntypes, ntypes) symmetric array or None (all 1)."""
+        nt = len(elems)
+        arr = (mbmd_tersoff_params * nt)(*[tersoff_struct(e) for e in elems])
+        ch = None
+        if chi is not None:
+            flat = [float(x) for row in chi for x in row]
+            if len(flat) != nt * nt:
+                raise ValueError("chi must be ntypes x ntypes")
+            ch = (C.c_double * (nt * nt))(*flat)
+        self._check(_lib.mbmd_set_tersoff_multi(self._h, nt, C.cast(arr, C.c_void_p),
+                                                C.cast(ch, C.c_void_p) if ch else None),
+                    "mbmd_set_tersoff_multi")
+
+    def set_type_masses(self, masses):
+        """Per-type masses (amu) for runs with mass 0; None or [] clears."""
+        m = [float(x) for x in (masses or [])]
+        arr = (C.c_double * max(len(m), 1))(*m) if m else None
+        self._check(_lib.mbmd_set_type_masses(self._h, len(m),
+                                              C.cast(arr, C.c_void_p) if arr else None),
+                    "mbmd_set_type_masses")
 
     def set_sw(self, params: dict):
         st = sw_struct(params)

@@ -69,7 +69,9 @@ struct mbmd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int potential = -1;          // 0 Tersoff, 1 SW
-    TersoffParams tp{};
+    TersoffTable ttab{};         // Tersoff elements and chi (nt = 1: single element)
+    double tmass[kMaxTypes] = {};    // per-type masses (amu) for mass_amu == 0
+    int n_tmass = 0;
     SWParams sp{};
     double skin = 0.5;
     int max_nb = 0;              // 0: potential default
@@ -153,7 +155,23 @@ int resolved_M(const mbmd_ctx* c)
 
 double cutoff_of(const mbmd_ctx* c)
 {
-    return c->potential == 1 ? c->sp.a * c->sp.sigma : c->tp.S;
+    if (c->potential == 1) return c->sp.a * c->sp.sigma;
+    double s = 0.0;   // sqrt(S_a S_b) never exceeds the larger S
+    for (int a = 0; a < c->ttab.nt; ++a) s = std::max(s, c->ttab.elem[a].S);
+    return s;
+}
+
+// Atom types the current potential knows (SW: one).
+int ntypes_of(const mbmd_ctx* c) { return c->potential == 0 ? c->ttab.nt : 1; }
+
+// Per-type integrator factors from the context's type masses.
+void apply_type_masses(const mbmd_ctx* c, double dt, Seg& g)
+{
+    g.typed_mass = 1;
+    for (int a = 0; a < c->n_tmass; ++a) {
+        g.hdt_t[a] = 0.5 * dt * kKappa / c->tmass[a];
+        g.kin_t[a] = 0.5 * c->tmass[a] / kKappa;
+    }
 }
 
 // Lays out every device array for `cap` atoms, M slots and `segs` segments
@@ -296,9 +314,9 @@ Seg make_seg(const Box& box, double rlist, int atom_off, int n, int nsteps, doub
     g.atom_off = atom_off;
     g.n = n;
     g.nsteps = nsteps;
+    g.dt = dt;
     if (mass > 0.0) {
         g.half_dt_acc = 0.5 * dt * kKappa / mass;
-        g.dt = dt;
         g.kin_scale = 0.5 * mass / kKappa;
     }
     g.thermo = thermo;
@@ -411,7 +429,7 @@ hipError_t partials(mbmd_ctx* c, int cur)
             e = launch_sw_partials<T>(c->buf, c->segs, cur, c->sp, pass == 1, c->max_nn,
                                       c->stream);
         else
-            e = launch_tersoff_partials<T>(c->buf, c->segs, cur, c->tp, pass == 1, c->max_nn,
+            e = launch_tersoff_partials<T>(c->buf, c->segs, cur, c->ttab, pass == 1, c->max_nn,
                                            c->stream);
         if (e != hipSuccess) return e;
     }
@@ -453,7 +471,8 @@ double* ring_row(mbmd_ctx* c, int row)
 // positions into buffer 0.
 mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
                          const int32_t* types, int nsteps, double mass, double dt, double* vel,
-                         double* U, double* F, double* W, double* J, int* total_cells)
+                         double* U, double* F, double* W, double* J, int* total_cells,
+                         bool dt_run = false)
 {
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     mbmd_status s = ensure_workspace(c, n, 1, false);
@@ -466,6 +485,9 @@ mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* p
     b.J = J;
     b.ostride = n;
     Seg g = make_seg(box, cutoff_of(c) + c->skin, 0, (int)n, nsteps, mass, dt, nullptr);
+    // dynamics with mass 0: per-type masses (the entry points check that
+    // every type has one)
+    if (vel && dt_run && mass == 0.0) apply_type_masses(c, dt, g);
     g.build = 1;
     c->segs_host.assign(1, g);
     c->pp = 0;
@@ -475,7 +497,8 @@ mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* p
     if (e == hipSuccess) e = launch_fill_int(b.phase[0], 1, 0, c->stream);
     if (e == hipSuccess) {
         ProfScope ps(c, P_STAGE);
-        e = launch_load_positions(pos, types, n, box, 0, b.xw[0], b.status, c->stream);
+        e = launch_load_positions(pos, types, ntypes_of(c), n, box, 0, b.xw[0], b.status,
+                                  c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "staging positions");
     return MBMD_OK;
@@ -530,7 +553,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
 {
     int cells = 0;
     mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
-                                 &cells);
+                                 &cells, true);
     if (s != MBMD_OK) return s;
     const Buffers& b = c->buf;
     mbmd_run_stats st{};
@@ -657,7 +680,7 @@ mbmd_status npt_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
 {
     int cells = 0;
     mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
-                                 &cells);
+                                 &cells, true);
     if (s != MBMD_OK) return s;
     const Buffers& b = c->buf;
     const double rlist = cutoff_of(c) + c->skin;
@@ -682,6 +705,7 @@ mbmd_status npt_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
                     return fail(c, MBMD_EBOX,
                                 "barostat shrank a box edge below 2 (cutoff + skin)%s");
             Seg g = make_seg(dev_seg.box, rlist, 0, (int)n, n_steps, mass, dt, nullptr);
+            if (mass == 0.0) apply_type_masses(c, dt, g);
             g.build = 1;
             c->segs_host.assign(1, g);
             e = upload_segs(c, &cells);
@@ -884,16 +908,75 @@ void mbmd_destroy(mbmd_ctx* c)
 
 const char* mbmd_last_error(const mbmd_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+bool tersoff_params_ok(const mbmd_tersoff_params* p)
+{
+    const double v[] = {p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return p->R > 0.0 && p->S > p->R && p->n > 0.0 && p->beta > 0.0 && p->d != 0.0;
+}
+
+mbmd_status mbmd_set_tersoff_multi(mbmd_ctx* c, int ntypes, const mbmd_tersoff_params* elem,
+                                   const double* chi)
+{
+    if (!c || !elem) return MBMD_EINVAL;
+    if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
+    if (ntypes < 1 || ntypes > kMaxTypes)
+        return fail(c, MBMD_EINVAL, "ntypes must be in 1..4%s");
+    for (int a = 0; a < ntypes; ++a)
+        if (!tersoff_params_ok(&elem[a]))
+            return fail(c, MBMD_EINVAL,
+                        "Tersoff parameters need finite values, 0 < R < S, n > 0, beta > 0, d != 0%s");
+    if (chi)
+        for (int a = 0; a < ntypes; ++a)
+            for (int b = 0; b < ntypes; ++b) {
+                const double x = chi[a * ntypes + b];
+                if (!std::isfinite(x) || !(x > 0.0) || x != chi[b * ntypes + a])
+                    return fail(c, MBMD_EINVAL, "chi must be finite, positive and symmetric%s");
+            }
+    TersoffTable t{};
+    t.nt = ntypes;
+    for (int a = 0; a < ntypes; ++a) {
+        const mbmd_tersoff_params* p = &elem[a];
+        t.elem[a] = TersoffParams{p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h,
+                                  p->R, p->S};
+        for (int b = 0; b < ntypes; ++b) t.chi[a * kMaxTypes + b] = chi ? chi[a * ntypes + b] : 1.0;
+    }
+    c->ttab = t;
+    c->potential = 0;
+    c->laid_cap = -1;
+    return MBMD_OK;
+}
+
+mbmd_status mbmd_set_type_masses(mbmd_ctx* c, int ntypes, const double* mass_amu)
+{
+    if (!c) return MBMD_EINVAL;
+    if (ntypes == 0) {
+        c->n_tmass = 0;
+        return MBMD_OK;
+    }
+    if (ntypes < 0 || ntypes > kMaxTypes || !mass_amu)
+        return fail(c, MBMD_EINVAL, "ntypes must be in 0..4 with a mass array%s");
+    for (int a = 0; a < ntypes; ++a)
+        if (!std::isfinite(mass_amu[a]) || !(mass_amu[a] > 0.0))
+            return fail(c, MBMD_EINVAL, "masses must be finite and positive%s");
+    for (int a = 0; a < ntypes; ++a) c->tmass[a] = mass_amu[a];
+    c->n_tmass = ntypes;
+    return MBMD_OK;
+}
+
 mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
 {
     if (!c || !p) return MBMD_EINVAL;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
-    const double v[] = {p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
-    for (double x : v)
-        if (!std::isfinite(x)) return fail(c, MBMD_EINVAL, "non-finite Tersoff parameter%s");
-    if (!(p->R > 0.0) || !(p->S > p->R) || !(p->n > 0.0) || !(p->beta > 0.0) || p->d == 0.0)
-        return fail(c, MBMD_EINVAL, "Tersoff parameters need 0 < R < S, n > 0, beta > 0, d != 0%s");
-    c->tp = TersoffParams{p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
+    if (!tersoff_params_ok(p))
+        return fail(c, MBMD_EINVAL,
+                    "Tersoff parameters need finite values, 0 < R < S, n > 0, beta > 0, d != 0%s");
+    c->ttab = TersoffTable{};
+    c->ttab.nt = 1;
+    c->ttab.elem[0] =
+        TersoffParams{p->A, p->B, p->lambda, p->mu, p->beta, p->n, p->c, p->d, p->h, p->R, p->S};
+    c->ttab.chi[0] = 1.0;
     c->potential = 0;
     c->laid_cap = -1;
     return MBMD_OK;
@@ -1061,9 +1144,11 @@ mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const doub
     mbmd_status s = common_checks(c, n, box, &b);
     if (s != MBMD_OK) return s;
     if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
-    if (!std::isfinite(mass_amu) || !(mass_amu > 0.0) || !std::isfinite(dt_fs) || n_steps < 0 ||
+    if (!std::isfinite(mass_amu) || mass_amu < 0.0 || !std::isfinite(dt_fs) || n_steps < 0 ||
         rebuild_every < 1)
-        return fail(c, MBMD_EINVAL, "need mass > 0, finite dt, n_steps >= 0, rebuild_every >= 1%s");
+        return fail(c, MBMD_EINVAL, "need mass >= 0, finite dt, n_steps >= 0, rebuild_every >= 1%s");
+    if (mass_amu == 0.0 && c->n_tmass < ntypes_of(c))
+        return fail(c, MBMD_EINVAL, "mass 0 needs a type mass for every atom type%s");
     if (n == 0) return MBMD_OK;
     if (!pos || !vel || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
     if (prec == MBMD_MIXED)
@@ -1084,9 +1169,11 @@ mbmd_status mbmd_npt_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, double box
     mbmd_status s = common_checks(c, n, box, &b);
     if (s != MBMD_OK) return s;
     if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
-    if (!std::isfinite(mass_amu) || !(mass_amu > 0.0) || !std::isfinite(dt_fs) ||
+    if (!std::isfinite(mass_amu) || mass_amu < 0.0 || !std::isfinite(dt_fs) ||
         !(dt_fs > 0.0) || n_steps < 0 || rebuild_every < 1)
-        return fail(c, MBMD_EINVAL, "need mass > 0, dt > 0, n_steps >= 0, rebuild_every >= 1%s");
+        return fail(c, MBMD_EINVAL, "need mass >= 0, dt > 0, n_steps >= 0, rebuild_every >= 1%s");
+    if (mass_amu == 0.0 && c->n_tmass < ntypes_of(c))
+        return fail(c, MBMD_EINVAL, "mass 0 needs a type mass for every atom type%s");
     if (!coupling) return fail(c, MBMD_EINVAL, "coupling is NULL%s");
     const mbmd_berendsen& k = *coupling;
     if (!std::isfinite(k.T0_K) || k.T0_K < 0.0 || !std::isfinite(k.P0_GPa) ||

@@ -9,7 +9,7 @@
 // else shares the launch.
 //
 // Data layout in device memory (N atom capacity, M list slots per atom):
-//   xw[2][N]         double4 {x, y, z, 0}: wrapped positions, atom-major
+//   xw[2][N]         double4 {x, y, z, type}: wrapped positions, atom-major
 //                    so a neighbour gather is one 32-byte access; two buffers
 //                    because the drift writes while neighbours are still read
 //   xbuild[N]        double4 positions at the last list build
@@ -47,6 +47,7 @@ constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
 constexpr int kMaxChunk = 256;       // steps enqueued between two checks of the skin
 constexpr int kThermoRing = 256;     // per-step rows of block partials kept before a fold
+constexpr int kMaxTypes = 4;         // atom types of the multicomponent Tersoff form
 
 struct Box {
     double L[3];
@@ -66,8 +67,23 @@ struct Seg {
     double half_dt_acc;     // dt/2 kappa/m
     double dt;
     double kin_scale;       // m / (2 kappa)
+    int typed_mass;         // nonzero: per-type masses below replace the two above
+    double hdt_t[kMaxTypes];    // dt/2 kappa/m_t
+    double kin_t[kMaxTypes];    // m_t / (2 kappa)
     double* thermo;         // batch: [nsteps + 1][16] thermo rows of this structure, or null
 };
+
+// Integrator factors of atom i of segment g (type from the position's w).
+__device__ __forceinline__ void atom_mass_factors(const Seg& g, double w, double& hdt, double& kin)
+{
+    hdt = g.half_dt_acc;
+    kin = g.kin_scale;
+    if (g.typed_mass) {
+        const int t = (int)w;
+        hdt = g.hdt_t[t];
+        kin = g.kin_t[t];
+    }
+}
 
 // Device view of the segment table.
 struct Segs {
@@ -103,6 +119,13 @@ __device__ __forceinline__ int seg_of_atom(const Segs& S, int64_t i)
 
 struct TersoffParams {                // the 1989 single-element form
     double A, B, lam, mu, beta, n, c, d, h, R, S;
+};
+// Tersoff's multicomponent form: per-element parameters and the bond-order
+// factor chi of each type pair (nt = 1, chi = 1: the single-element form).
+struct TersoffTable {
+    int nt;
+    TersoffParams elem[kMaxTypes];
+    double chi[kMaxTypes * kMaxTypes];
 };
 struct SWParams {                     // the 1985 form
     double epsilon, sigma, a, lam, gamma, A, B, p, q;
@@ -179,9 +202,11 @@ __host__ __device__ inline int quad_blocks_for(int64_t n) { return (int)((n + kQ
 // ---- launchers (host) -----------------------------------------------------
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 // Wraps positions pos[3][n] into xw[atom_off ..).
-hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
-                                 Box box, int atom_off, double4* xw, unsigned* status,
-                                 hipStream_t s);
+// Types (null: all 0) go to the w component; a type outside [0, ntypes)
+// raises ST_TYPES and is stored as 0.
+hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int ntypes,
+                                 int64_t n, Box box, int atom_off, double4* xw,
+                                 unsigned* status, hipStream_t s);
 // Serving batch: wraps positions pos[3][n] into xw[atom_off ..) and copies
 // velocities vel[3][n] into vel_dst (row stride `stride`) at atom_off.
 hipError_t launch_batch_admit(const double* pos, const double* vel, int64_t n, Box box,
@@ -210,7 +235,7 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
 // can exceed the fast path.
 template <class T>
 hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
-                                   const TersoffParams& p, bool overflow_pass, int max_nn,
+                                   const TersoffTable& tab, bool overflow_pass, int max_nn,
                                    hipStream_t s);
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SWParams& p,

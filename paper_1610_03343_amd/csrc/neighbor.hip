@@ -43,8 +43,9 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s)
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ types, int64_t n,
-                 Box box, int atom_off, double4* __restrict__ xw, unsigned* __restrict__ status)
+k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ types, int ntypes,
+                 int64_t n, Box box, int atom_off, double4* __restrict__ xw,
+                 unsigned* __restrict__ status)
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -53,18 +54,22 @@ k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ typ
         atomicOr(status, ST_NONFINITE);
         x = y = z = 0.0;
     }
-    if (types && types[i] != 0) atomicOr(status, ST_TYPES);
+    int t = types ? types[i] : 0;
+    if (t < 0 || t >= ntypes) {
+        atomicOr(status, ST_TYPES);
+        t = 0;
+    }
     xw[atom_off + i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
-                                    wrap_coord(z, box.L[2]), 0.0);
+                                    wrap_coord(z, box.L[2]), (double)t);
 }
 
-hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int64_t n,
-                                 Box box, int atom_off, double4* xw, unsigned* status,
-                                 hipStream_t s)
+hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int ntypes,
+                                 int64_t n, Box box, int atom_off, double4* xw,
+                                 unsigned* status, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_load_positions<<<blocks_for(n), kBlock, 0, s>>>(pos_soa, types, n, box, atom_off, xw,
-                                                      status);
+    k_load_positions<<<blocks_for(n), kBlock, 0, s>>>(pos_soa, types, ntypes, n, box, atom_off,
+                                                      xw, status);
     return hipGetLastError();
 }
 

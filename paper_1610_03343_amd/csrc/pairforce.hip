@@ -116,6 +116,8 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
             }
         }
         ui = U[i];
+        double hdt, kin;
+        atom_mass_factors(g, xi.w, hdt, kin);
         // The integrator arithmetic is kept unfused so that it rounds exactly
         // like a plain IEEE evaluation of v += (dt/2) a and x += dt v.
         if (vel) {
@@ -125,12 +127,12 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
             v[2] = vel[2 * os + i];
             if (kick_before) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] += g.half_dt_acc * f[c];
+                for (int c = 0; c < 3; ++c) v[c] += hdt * f[c];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 jj[c] = mm[3 * c + 0] * v[0] + mm[3 * c + 1] * v[1] + mm[3 * c + 2] * v[2];
-            ekin = g.kin_scale * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            ekin = kin * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         }
         // Outputs are not read again by the step loop: streaming stores keep
         // them from evicting the partials and positions that neighbours of
@@ -148,7 +150,7 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
             double vn[3], x[3] = {xi.x, xi.y, xi.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                vn[c] = v[c] + g.half_dt_acc * f[c];
+                vn[c] = v[c] + hdt * f[c];
                 x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
             }
             vel[i] = vn[0];
@@ -355,11 +357,13 @@ k_npt_drift(Segs S, int64_t os, const double* __restrict__ coupling, double4* __
     const int64_t i = g.atom_off + local;
     const double lambda = coupling[2 * sid], mu = coupling[2 * sid + 1];
     const double4 xi = xw[i];
+    double hdt, kin;
+    atom_mass_factors(g, xi.w, hdt, kin);
     double x[3] = {xi.x, xi.y, xi.z};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         double v = vel[c * os + i] * lambda;
-        v = v + g.half_dt_acc * F[c * os + i];
+        v = v + hdt * F[c * os + i];
         vel[c * os + i] = v;
         x[c] = x[c] * mu;
         x[c] = wrap_coord(x[c] + g.dt * v, g.box.L[c]);

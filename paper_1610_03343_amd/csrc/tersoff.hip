@@ -19,39 +19,57 @@
 // g is evaluated as 1 + c^2 t^2 / (d^2 (d^2 + t^2)), t = h - cos (identical to
 // the printed 1 + c^2/d^2 - c^2/(d^2 + t^2) without its large cancellation);
 // db/dzeta is 0 at zeta = 0, where it multiplies an empty sum.
+//
+// Several atom types (the generality the paper claims for its method in
+// Section 2.1, with Tersoff's 1989 multicomponent form): the bond terms of
+// bond c use the parameters of the type pair (i, c) (A, B, lambda, mu, R, S
+// mixed from the two elements), g, beta and n those of atom i, and b_c is
+// multiplied by chi of the pair.  The formulas above hold unchanged with
+// f_R, f_A, f_C and their derivatives per bond.  The single-type kernels
+// read every constant from the kernel arguments (uniform registers); the
+// multi-type ones copy the table to LDS and index it by type.
+#include <cmath>
+
 #include "partials_common.h"
 
 namespace mbmd {
 
+// Constants of a centre atom's element: the angular term and the bond order.
 template <class T>
-struct TersoffK {
-    T A, B, lam, mu, beta, n, inv2n, c2, c2_d2, d2, h, R, pi_sr;
+struct TCenter {
+    T beta, n, inv2n, c2, c2_d2, d2, h;
     // b = (1 + u)^a, a = -1/(2n): binomial series coefficients a_k = C(a, k),
     // used below u_series = 2^-9 where the first omitted term, |a_6| u^6, is
     // below 2e-17 relative
     T u_series, a1, a2, a3, a4, a5;
-    T S;
+};
+// Constants of a bond's type pair: f_R, f_A, f_C and the bond-order factor.
+template <class T>
+struct TPair {
+    T A, B, lam, mu, R, S, pi_sr, chi;
+};
+// Kernel-argument table: entry [0] alone for one type; [ti] and
+// [ti * kMaxTypes + tj] otherwise.  S2 is the FP64 cutoff squared per pair
+// (the in-cutoff test on r^2, the same for (i, j) and (j, i)).
+template <class T>
+struct TersoffKM {
+    TCenter<T> c[kMaxTypes];
+    TPair<T> p[kMaxTypes * kMaxTypes];
+    double S2[kMaxTypes * kMaxTypes];
 };
 
 template <class T>
-TersoffK<T> tersoff_constants(const TersoffParams& p)
+TCenter<T> center_constants(const TersoffParams& e)
 {
-    TersoffK<T> k;
-    k.A = (T)p.A;
-    k.B = (T)p.B;
-    k.lam = (T)p.lam;
-    k.mu = (T)p.mu;
-    k.beta = (T)p.beta;
-    k.n = (T)p.n;
-    k.inv2n = (T)(1.0 / (2.0 * p.n));
-    k.c2 = (T)(p.c * p.c);
-    k.c2_d2 = (T)(p.c * p.c / (p.d * p.d));
-    k.d2 = (T)(p.d * p.d);
-    k.h = (T)p.h;
-    k.R = (T)p.R;
-    k.S = (T)p.S;
-    k.pi_sr = (T)(3.14159265358979323846 / (p.S - p.R));
-    const double a = -1.0 / (2.0 * p.n);
+    TCenter<T> k;
+    k.beta = (T)e.beta;
+    k.n = (T)e.n;
+    k.inv2n = (T)(1.0 / (2.0 * e.n));
+    k.c2 = (T)(e.c * e.c);
+    k.c2_d2 = (T)(e.c * e.c / (e.d * e.d));
+    k.d2 = (T)(e.d * e.d);
+    k.h = (T)e.h;
+    const double a = -1.0 / (2.0 * e.n);
     double ak[6] = {1.0, 0, 0, 0, 0, 0};
     for (int j = 1; j < 6; ++j) ak[j] = ak[j - 1] * (a - (j - 1)) / j;
     k.a1 = (T)ak[1];
@@ -61,6 +79,64 @@ TersoffK<T> tersoff_constants(const TersoffParams& p)
     k.a5 = (T)ak[5];
     k.u_series = (T)0x1p-9;
     return k;
+}
+
+// The constants of type pair (a, b): Tersoff's 1989 mixing rules (geometric
+// means for A, B, R, S; arithmetic means for lambda, mu), which give the
+// element's own values, exactly, for a == b (sqrt(x * x) = |x| in IEEE
+// arithmetic).
+template <class T>
+TPair<T> pair_constants(const TersoffTable& tab, int a, int b, double* S_out)
+{
+    const TersoffParams& x = tab.elem[a];
+    const TersoffParams& y = tab.elem[b];
+    const double R = std::sqrt(x.R * y.R);
+    const double S = std::sqrt(x.S * y.S);
+    TPair<T> k;
+    k.A = (T)std::sqrt(x.A * y.A);
+    k.B = (T)std::sqrt(x.B * y.B);
+    k.lam = (T)(0.5 * (x.lam + y.lam));
+    k.mu = (T)(0.5 * (x.mu + y.mu));
+    k.R = (T)R;
+    k.S = (T)S;
+    k.pi_sr = (T)(3.14159265358979323846 / (S - R));
+    k.chi = (T)tab.chi[a * kMaxTypes + b];
+    *S_out = S;
+    return k;
+}
+
+template <class T>
+TersoffKM<T> tersoff_table(const TersoffTable& tab)
+{
+    TersoffKM<T> k{};
+    for (int a = 0; a < tab.nt; ++a) {
+        k.c[a] = center_constants<T>(tab.elem[a]);
+        for (int b = 0; b < tab.nt; ++b) {
+            double S;
+            k.p[a * kMaxTypes + b] = pair_constants<T>(tab, a, b, &S);
+            k.S2[a * kMaxTypes + b] = S * S;
+        }
+    }
+    return k;
+}
+
+// Multi-type kernels: the table in LDS, filled by the whole block.
+template <class T>
+struct TersoffLds {
+    TCenter<T> c[kMaxTypes];
+    TPair<T> p[kMaxTypes * kMaxTypes];
+    double S2[kMaxTypes * kMaxTypes];
+};
+
+template <class T>
+__device__ __forceinline__ void fill_lds_table(const TersoffKM<T>& K, TersoffLds<T>& L)
+{
+    if (threadIdx.x < kMaxTypes) L.c[threadIdx.x] = K.c[threadIdx.x];
+    if (threadIdx.x < kMaxTypes * kMaxTypes) {
+        L.p[threadIdx.x] = K.p[threadIdx.x];
+        L.S2[threadIdx.x] = K.S2[threadIdx.x];
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ double t_exp(double x) { return exp(x); }
@@ -108,7 +184,7 @@ __device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(
 // test on r^2; r formed in the working precision that rounds to S or above
 // takes the limit 0).
 template <class T>
-__device__ __forceinline__ void cutoff_fc(const TersoffK<T>& p, T r, T& fc, T& dfc)
+__device__ __forceinline__ void cutoff_fc(const TPair<T>& p, T r, T& fc, T& dfc)
 {
     if (r < p.R) {
         fc = T(1);
@@ -125,7 +201,7 @@ __device__ __forceinline__ void cutoff_fc(const TersoffK<T>& p, T r, T& fc, T& d
 }
 
 template <class T>
-__device__ __forceinline__ void angular_g(const TersoffK<T>& p, T cs, T& g, T& dg)
+__device__ __forceinline__ void angular_g(const TCenter<T>& p, T cs, T& g, T& dg)
 {
     const T t = p.h - cs;
     const T iq = nr_rcp(p.d2 + t * t);
@@ -137,7 +213,7 @@ __device__ __forceinline__ void angular_g(const TersoffK<T>& p, T cs, T& g, T& d
 // b = (1 + u)^(-1/(2n)) is summed as its binomial series when u is small
 // (the usual case: u ~ 1e-4 in the crystal) and through exp/log1p otherwise.
 template <class T>
-__device__ __forceinline__ void bond_order(const TersoffK<T>& p, T zeta, T& b, T& db)
+__device__ __forceinline__ void bond_order(const TCenter<T>& p, T zeta, T& b, T& db)
 {
     b = T(1);
     db = T(0);
@@ -164,28 +240,51 @@ __device__ __forceinline__ void bond_geometry(const Disp& d, T& ux, T& uy, T& uz
     uz = dz * ir;
 }
 
-template <class T, int MAXC, bool FIXED>
-__device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, int64_t cap,
-                                             const double4& xi, unsigned long long msk, int cnt,
+// Per-bond constants: the table entry of type pair (ti, tj), or entry 0.
+template <class T, bool MULTI>
+__device__ __forceinline__ const TPair<T>& pair_of(const TersoffKM<T>& K, const TersoffLds<T>& L,
+                                                   int tp)
+{
+    if constexpr (MULTI) return L.p[tp];
+    else return K.p[0];
+}
+template <class T, bool MULTI>
+__device__ __forceinline__ const TCenter<T>& center_of(const TersoffKM<T>& K,
+                                                       const TersoffLds<T>& L, int ti)
+{
+    if constexpr (MULTI) return L.c[ti];
+    else return K.c[0];
+}
+
+// One thread, any number of bonds (the overflow pass).  tp of bond c is the
+// table index ti * kMaxTypes + tj.
+template <class T, int MAXC, bool FIXED, bool MULTI>
+__device__ __forceinline__ void tersoff_site(const TersoffKM<T>& K, const TersoffLds<T>& L,
+                                             int64_t i, int64_t cap, const double4& xi,
+                                             unsigned long long msk, int cnt,
                                              const int* __restrict__ nl,
                                              const double4* __restrict__ xw, const Box& box,
                                              double* __restrict__ U, T* __restrict__ dpart)
 {
     T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], fc[MAXC], dfc[MAXC], zp[MAXC], pd[MAXC];
-    int slot[MAXC];
+    int slot[MAXC], tp[MAXC];
+    const int ti = MULTI ? (int)xi.w : 0;
+    const TCenter<T>& pc = center_of<T, MULTI>(K, L, ti);
     unsigned long long rem = msk;
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         ux[c] = uy[c] = uz[c] = rr[c] = fc[c] = dfc[c] = zp[c] = pd[c] = T(0);
         slot[c] = 0;
+        tp[c] = 0;
         if (c < cnt) {
             const int m = __builtin_ctzll(rem);
             slot[c] = m;
             rem &= rem - 1;
-            const int j = nl[(int64_t)m * cap + i];
+            const double4 xj = xw[nl[(int64_t)m * cap + i]];
+            if (MULTI) tp[c] = ti * kMaxTypes + (int)xj.w;
             T ir;
-            bond_geometry(cut_disp(xi, xw[j], box), ux[c], uy[c], uz[c], rr[c], ir);
-            cutoff_fc(p, rr[c], fc[c], dfc[c]);
+            bond_geometry(cut_disp(xi, xj, box), ux[c], uy[c], uz[c], rr[c], ir);
+            cutoff_fc(pair_of<T, MULTI>(K, L, tp[c]), rr[c], fc[c], dfc[c]);
         }
     }
     // zeta_c over unordered pairs: g(cos_ce) is shared by zeta_c and zeta_e.
@@ -196,7 +295,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
             if (e < cnt) {
                 const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
                 T g, dg;
-                angular_g(p, cs, g, dg);
+                angular_g(pc, cs, g, dg);
                 zp[c] += fc[e] * g;
                 zp[e] += fc[c] * g;
             }
@@ -208,12 +307,17 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         if (c < cnt) {
+            const TPair<T>& pp = pair_of<T, MULTI>(K, L, tp[c]);
             T b, db;
-            bond_order(p, zp[c], b, db);
-            const T fr = p.A * t_exp(-p.lam * rr[c]);
-            const T fa = p.B * t_exp(-p.mu * rr[c]);
+            bond_order(pc, zp[c], b, db);
+            if (MULTI) {
+                b *= pp.chi;
+                db *= pp.chi;
+            }
+            const T fr = pp.A * t_exp(-pp.lam * rr[c]);
+            const T fa = pp.B * t_exp(-pp.mu * rr[c]);
             u_i += (double)(fc[c] * (fr - b * fa));
-            pd[c] = dfc[c] * (fr - b * fa) + fc[c] * (-p.lam * fr + b * p.mu * fa);
+            pd[c] = dfc[c] * (fr - b * fa) + fc[c] * (-pp.lam * fr + b * pp.mu * fa);
             zp[c] = fc[c] * fa * db;
         }
     }
@@ -229,7 +333,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
                 if (e != c && e < cnt) {
                     const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
                     T g, dg;
-                    angular_g(p, cs, g, dg);
+                    angular_g(pc, cs, g, dg);
                     const T a = T(-0.5) * (zp[c] * fc[e] + zp[e] * fc[c]) * dg * ir;
                     const T bb = T(-0.5) * zp[e] * dfc[c] * g;
                     dx += a * (ux[e] - cs * ux[c]) + bb * ux[c];
@@ -245,32 +349,61 @@ __device__ __forceinline__ void tersoff_site(const TersoffK<T>& p, int64_t i, in
     }
 }
 
+// Cutoff mask of atom i with a cutoff per type pair (the multi-type form of
+// quad_cutoff_mask); also returns the type of the lane's first-slot
+// neighbour.
+__device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
+    const double4& xi, int ti, int64_t i, int64_t cap, int nnb, int q, const int* __restrict__ nl,
+    const double4* __restrict__ xw, const Box& box, const double* S2, Disp& d_first, int& t_first)
+{
+    unsigned long long msk = 0;
+    d_first = Disp{0.0, 0.0, 0.0, 0.0};
+    t_first = 0;
+    for (int m = q; m < nnb; m += kQuad) {
+        const double4 xj = xw[nl[(int64_t)m * cap + i]];
+        const int tj = (int)xj.w;
+        const Disp d = cut_disp(xi, xj, box);
+        if (m == q) {
+            d_first = d;
+            t_first = tj;
+        }
+        if (d.r2 < S2[ti * kMaxTypes + tj]) msk |= 1ull << m;
+    }
+    return quad_or(msk);
+}
+
 // Quad site pass: four lanes per atom, lane q owning bonds q and q + 4.  The
 // arithmetic is the one of tersoff_site, distributed over the quad: each lane
 // forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
 // bonds' unit vectors, f_C and P from the other lanes.  Atoms with more than
 // kQuad * SLOTS in-cutoff bonds go to the overflow list.
-template <class T, int SLOTS>
+template <class T, int SLOTS, bool MULTI>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
+k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
                     const double4* __restrict__ xw, const int* __restrict__ nn,
                     const int* __restrict__ nl, unsigned long long* __restrict__ mask,
                     double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
                     int* __restrict__ ovf_list)
 {
+    __shared__ TersoffLds<T> L;
     const int q = threadIdx.x & (kQuad - 1);
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
     if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    if (MULTI) fill_lds_table(K, L);
     const Box box = g.box;
     const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
     const int64_t i = g.atom_off + local;
     const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const int ti = MULTI ? (int)xi.w : 0;
     const int nnb = valid ? min(nn[i], M) : 0;
     Disp d_first;
-    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
+    int t_first = 0;
+    const unsigned long long msk =
+        MULTI ? quad_cutoff_mask_typed(xi, ti, i, cap, nnb, q, nl, xw, box, L.S2, d_first, t_first)
+              : quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, K.S2[0], d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
@@ -278,22 +411,32 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
         if (ovf) ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
     }
     const int kc = (valid && !ovf) ? cnt : 0;   // bonds handled by this quad
+    const TCenter<T>& pc = center_of<T, MULTI>(K, L, ti);
 
     T ux[SLOTS], uy[SLOTS], uz[SLOTS], rr[SLOTS], ir[SLOTS],
         fc[SLOTS], dfc[SLOTS], zp[SLOTS], pd[SLOTS];
-    int slot[SLOTS];
+    int slot[SLOTS], tp[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         ux[s] = uy[s] = uz[s] = fc[s] = dfc[s] = zp[s] = pd[s] = T(0);
         rr[s] = ir[s] = T(1);
         slot[s] = 0;
+        tp[s] = 0;
         if (c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
-            const Disp d = (s == 0 && m == q) ? d_first : cut_disp(xi, xw[nl[(int64_t)m * cap + i]], box);
+            Disp d;
+            if (s == 0 && m == q) {
+                d = d_first;
+                if (MULTI) tp[s] = ti * kMaxTypes + t_first;
+            } else {
+                const double4 xj = xw[nl[(int64_t)m * cap + i]];
+                d = cut_disp(xi, xj, box);
+                if (MULTI) tp[s] = ti * kMaxTypes + (int)xj.w;
+            }
             bond_geometry(d, ux[s], uy[s], uz[s], rr[s], ir[s]);
-            cutoff_fc(p, rr[s], fc[s], dfc[s]);
+            cutoff_fc(pair_of<T, MULTI>(K, L, tp[s]), rr[s], fc[s], dfc[s]);
         }
     }
     const int tmax = wave_partner_slots<SLOTS>(kc);
@@ -320,7 +463,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
                     T g, dg;
-                    angular_g(p, cs, g, dg);
+                    angular_g(pc, cs, g, dg);
                     zp[s] += ef * g;
                     if (s == 0 && t == 0) {
                         g0[k] = g;
@@ -336,12 +479,17 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
     for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         if (c < kc) {
+            const TPair<T>& pp = pair_of<T, MULTI>(K, L, tp[s]);
             T b, db;
-            bond_order(p, zp[s], b, db);
-            const T fr = p.A * t_exp(-p.lam * rr[s]);
-            const T fa = p.B * t_exp(-p.mu * rr[s]);
+            bond_order(pc, zp[s], b, db);
+            if (MULTI) {
+                b *= pp.chi;
+                db *= pp.chi;
+            }
+            const T fr = pp.A * t_exp(-pp.lam * rr[s]);
+            const T fa = pp.B * t_exp(-pp.mu * rr[s]);
             u_i += (double)(fc[s] * (fr - b * fa));
-            pd[s] = dfc[s] * (fr - b * fa) + fc[s] * (-p.lam * fr + b * p.mu * fa);
+            pd[s] = dfc[s] * (fr - b * fa) + fc[s] * (-pp.lam * fr + b * pp.mu * fa);
             zp[s] = fc[s] * fa * db;
         }
     }
@@ -378,7 +526,7 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
                         g = g0[k];
                         dg = dg0[k];
                     } else {
-                        angular_g(p, cs, g, dg);
+                        angular_g(pc, cs, g, dg);
                     }
                     const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
                     const T bb = T(-0.5) * ep * dfc[s] * g;
@@ -403,51 +551,61 @@ k_tersoff_site_quad(TersoffK<T> p, double rc2, Segs S, int M, int64_t cap,
 
 // Atoms whose in-cutoff count exceeded the main tile; the tile here covers
 // the whole list capacity.
-template <class T>
+template <class T, bool MULTI>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_partials_ovf(TersoffK<T> p, Segs S, int64_t cap, const double4* __restrict__ xw,
+k_tersoff_partials_ovf(TersoffKM<T> K, Segs S, int64_t cap, const double4* __restrict__ xw,
                        const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
                        double* __restrict__ U, T* __restrict__ dpart,
                        const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
 {
+    __shared__ TersoffLds<T> L;
+    if (MULTI) fill_lds_table(K, L);
     const int total = *ovf_count;
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
         const int64_t i = ovf_list[k];
         const double4 xi = xw[i];
         const Box box = S.seg[seg_of_atom(S, i)].box;
         const unsigned long long msk = mask[i];
-        tersoff_site<T, kMaxSlots, false>(p, i, cap, xi, msk, __popcll(msk), nl, xw, box, U,
-                                          dpart);
+        tersoff_site<T, kMaxSlots, false, MULTI>(K, L, i, cap, xi, msk, __popcll(msk), nl, xw,
+                                                 box, U, dpart);
     }
 }
 
 constexpr int kOvfGrid = 64;
 
-template <class T>
-hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
-                                   const TersoffParams& p, bool overflow_pass, int max_nn,
-                                   hipStream_t s)
+template <class T, bool MULTI>
+hipError_t launch_tersoff_kernels(const Buffers& b, const Segs& S, int cur,
+                                  const TersoffKM<T>& k, bool overflow_pass, int max_nn,
+                                  hipStream_t s)
 {
-    if (S.nblk_quad <= 0) return hipSuccess;
-    if (!segs_ready(S, b)) return hipErrorInvalidValue;
-    const TersoffK<T> k = tersoff_constants<T>(p);
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_tersoff_site_quad<T, kTersoffSlots><<<S.nblk_quad, kBlock, 0, s>>>(k, p.S * p.S, S, b.M, b.cap,
-                                                              b.xw[cur], b.nn, b.nl, b.mask, b.U,
-                                                              dp, b.ovf_count, b.ovf_list);
+        k_tersoff_site_quad<T, kTersoffSlots, MULTI><<<S.nblk_quad, kBlock, 0, s>>>(
+            k, S, b.M, b.cap, b.xw[cur], b.nn, b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
     if (b.M > kQuad * kTersoffSlots && max_nn > kQuad * kTersoffSlots)
-        k_tersoff_partials_ovf<T><<<kOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl,
-                                                              b.mask, b.U, dp, b.ovf_count,
-                                                              b.ovf_list);
+        k_tersoff_partials_ovf<T, MULTI><<<kOvfGrid, kBlock, 0, s>>>(
+            k, S, b.cap, b.xw[cur], b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
+                                   const TersoffTable& tab, bool overflow_pass, int max_nn,
+                                   hipStream_t s)
+{
+    if (S.nblk_quad <= 0) return hipSuccess;
+    if (!segs_ready(S, b) || tab.nt < 1 || tab.nt > kMaxTypes) return hipErrorInvalidValue;
+    const TersoffKM<T> k = tersoff_table<T>(tab);
+    if (tab.nt > 1)
+        return launch_tersoff_kernels<T, true>(b, S, cur, k, overflow_pass, max_nn, s);
+    return launch_tersoff_kernels<T, false>(b, S, cur, k, overflow_pass, max_nn, s);
+}
+
 template hipError_t launch_tersoff_partials<double>(const Buffers&, const Segs&, int,
-                                                    const TersoffParams&, bool, int, hipStream_t);
+                                                    const TersoffTable&, bool, int, hipStream_t);
 template hipError_t launch_tersoff_partials<float>(const Buffers&, const Segs&, int,
-                                                   const TersoffParams&, bool, int, hipStream_t);
+                                                   const TersoffTable&, bool, int, hipStream_t);
 
 }  // namespace mbmd
