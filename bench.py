@@ -404,6 +404,59 @@ def bench_green_kubo(mb, wl, torch, args):
                            "peak_fp64_TFLOPs": FP64_VECTOR_PEAK_TFLOPS}}
 
 
+def bench_sic(mb, wl, torch, args, si_ms_per_step):
+    """Tersoff's multicomponent form: zincblende SiC, 40^3 cells = 512,000
+    atoms at a = 4.32 A (the potential's own lattice constant), per-type
+    masses, NVE, both precisions."""
+    import numpy as np
+    log("SiC: generating the 512,000-atom zincblende input (seed 1006)")
+    s = wl.binary_crystal(40, seed=1006, a=4.32, sigma=0.05, masses=(wl.M_SI, wl.M_C))
+    dev = torch.device("cuda", 0)
+    ctx = mb.Context(0)
+    chi = [[1.0, wl.CHI_SI_C_1989], [wl.CHI_SI_C_1989, 1.0]]
+    ctx.set_tersoff_multi([wl.TERSOFF_SI_1989, wl.TERSOFF_C_1989], chi)
+    ctx.set_neighbor(0.5, 32)
+    ctx.set_rebuild_policy("fixed")
+    ctx.set_type_masses([wl.M_SI, wl.M_C])
+    pos0 = torch.tensor(wl.soa(s.pos), device=dev)
+    vel0 = torch.tensor(wl.soa(s.vel), device=dev)
+    types = torch.tensor(s.types, dtype=torch.int32, device=dev)
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=dev)
+    out = dict(U=z(s.n), F=z(3, s.n), W=z(9, s.n), J=z(3, s.n))
+    steps = args.sic_steps
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ctx.nve_run(pos0.clone(), vel0.clone(), s.box, 0.0, 1.0, args.warmup, 20, types=types,
+                    precision=prec, out=out)
+        pos, vel = pos0.clone(), vel0.clone()
+        th = z(steps + 1, mb.THERMO_COLS)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.nve_run(pos, vel, s.box, 0.0, 1.0, steps, 20, types=types, precision=prec,
+                    thermo=th, out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        thh = th.cpu().numpy()
+        log(f"SiC {prec}: {t:.3f} s, {s.n * steps / t:.4e} atom-steps/s")
+        res[prec] = {"value": s.n * steps / t, "unit": "atom-steps/s", "steps": steps,
+                     "ms_per_step": 1e3 * t / steps,
+                     "energy_change_eV_per_atom": float((thh[-1, 14] - thh[0, 14]) / s.n),
+                     "E_pot_eV_per_atom_step0": float(thh[0, 0] / s.n)}
+    ctx.set_profiling(True)
+    ctx.reset_profile()
+    ctx.nve_run(pos0.clone(), vel0.clone(), s.box, 0.0, 1.0, min(args.profile_steps, steps), 20,
+                types=types, out=out)
+    prof = ctx.profile()
+    ctx.close()
+    res["kernels"] = {k: {"launches": c, "avg_us": round(1e3 * ms / c, 3)}
+                      for k, (c, ms) in prof.items() if c}
+    res["fp64_vs_si_time"] = round(res["fp64"]["ms_per_step"] / si_ms_per_step, 4)
+    res["config"] = {"workload": "tersoff_sic_zincblende_40x40x40_512000_atoms_nve",
+                     "atoms": s.n, "a_A": 4.32, "chi_SiC": wl.CHI_SI_C_1989, "seed": 1006,
+                     "rebuild_every": 20, "skin_A": 0.5, "masses": [wl.M_SI, wl.M_C]}
+    return res
+
+
 def bench_sw(mb, wl, torch, args):
     log("generating the 1,000,000-atom SW Si input (seed 1003)")
     s = wl.sw_1m()
@@ -538,6 +591,7 @@ def main():
     ap.add_argument("--sw-steps", type=int, default=1000)
     ap.add_argument("--npt-steps", type=int, default=1000)
     ap.add_argument("--gk-steps", type=int, default=100000)
+    ap.add_argument("--sic-steps", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -552,6 +606,7 @@ def main():
     ap.add_argument("--no-sw", action="store_true")
     ap.add_argument("--no-npt", action="store_true")
     ap.add_argument("--no-gk", action="store_true")
+    ap.add_argument("--no-sic", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=200,
                     help="steps of the HIP-event profiled pass used for the roofline")
@@ -659,6 +714,7 @@ def main():
     mixed = None if args.no_mixed else bench_mixed(W, args)
     npt = None if args.no_npt else bench_npt(W, args, 1e3 * t64 / args.steps)
     W.close()
+    sic = None if args.no_sic else bench_sic(mb, wl, torch, args, 1e3 * t64 / args.steps)
     sw = None if args.no_sw else bench_sw(mb, wl, torch, args)
     serve = None if args.no_serving else bench_serving(mb, wl, torch, args)
     gkr = None if args.no_gk else bench_green_kubo(mb, wl, torch, args)
@@ -695,6 +751,7 @@ def main():
         "mixed": mixed,
         "npt": npt,
         "green_kubo": gkr,
+        "sic_512k": sic,
         "sw_1m": sw,
         "serving": serve,
         "speed_vs_n": sweep,

@@ -422,7 +422,8 @@ hipError_t partials(mbmd_ctx* c, int cur)
     hipError_t e;
     for (int pass = 0; pass < 2; ++pass) {
         // the overflow pass only exists when a site can exceed the fast path
-        const int fast = kQuad * (c->potential == 1 ? kSWSlots : kTersoffSlots);
+        const int fast = kQuad * (c->potential == 1 ? kSWSlots
+                                  : (c->ttab.nt > 1 ? kTersoffMultiSlots : kTersoffSlots));
         if (pass == 1 && !(c->buf.M > fast && c->max_nn > fast)) break;
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)

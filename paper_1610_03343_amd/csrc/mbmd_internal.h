@@ -42,6 +42,8 @@ constexpr int kQuadAtoms = 64;       // atoms per block of the four-lanes-per-at
 constexpr int kMaxSlots = 64;        // list capacity limit (cutoff mask is 64-bit)
 constexpr int kQuad = 4;             // lanes per atom in the site passes
 constexpr int kTersoffSlots = 2;     // bonds per lane: Tersoff site pass (8 bonds per atom)
+constexpr int kTersoffMultiSlots = 3;    // several types (12 bonds: the Si-Si second
+                                         // neighbours of SiC sit at the Si-Si cutoff)
 constexpr int kSWSlots = 3;          // bonds per lane: SW site pass (12 bonds per atom)
 constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)

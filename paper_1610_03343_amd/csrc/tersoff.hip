@@ -372,7 +372,7 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
     return quad_or(msk);
 }
 
-// Quad site pass: four lanes per atom, lane q owning bonds q and q + 4.  The
+// Quad site pass: four lanes per atom, lane q owning bonds q, q + 4, ....  The
 // arithmetic is the one of tersoff_site, distributed over the quad: each lane
 // forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
 // bonds' unit vectors, f_C and P from the other lanes.  Atoms with more than
@@ -578,13 +578,14 @@ hipError_t launch_tersoff_kernels(const Buffers& b, const Segs& S, int cur,
                                   const TersoffKM<T>& k, bool overflow_pass, int max_nn,
                                   hipStream_t s)
 {
+    constexpr int kSlots = MULTI ? kTersoffMultiSlots : kTersoffSlots;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
-        k_tersoff_site_quad<T, kTersoffSlots, MULTI><<<S.nblk_quad, kBlock, 0, s>>>(
+        k_tersoff_site_quad<T, kSlots, MULTI><<<S.nblk_quad, kBlock, 0, s>>>(
             k, S, b.M, b.cap, b.xw[cur], b.nn, b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
         return hipGetLastError();
     }
-    if (b.M > kQuad * kTersoffSlots && max_nn > kQuad * kTersoffSlots)
+    if (b.M > kQuad * kSlots && max_nn > kQuad * kSlots)
         k_tersoff_partials_ovf<T, MULTI><<<kOvfGrid, kBlock, 0, s>>>(
             k, S, b.cap, b.xw[cur], b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
     return hipGetLastError();
