@@ -48,11 +48,21 @@ template <class T>
 struct TPair {
     T A, B, lam, mu, R, S, pi_sr, chi;
 };
-// Kernel-argument table: entry [0] alone for one type; [ti] and
-// [ti * kMaxTypes + tj] otherwise.  S2 is the FP64 cutoff squared per pair
-// (the in-cutoff test on r^2, the same for (i, j) and (j, i)).
+// Kernel arguments: one element (MULTI = false), or the table indexed
+// [ti] and [ti * kMaxTypes + tj].  S2 is the FP64 cutoff squared of a pair
+// (the in-cutoff test on r^2, the same for (i, j) and (j, i)).  The
+// single-type argument stays small: the table would be fetched with every
+// launch.
+template <class T, bool MULTI>
+struct TersoffArg;
 template <class T>
-struct TersoffKM {
+struct TersoffArg<T, false> {   // the centre and pair constants of one element, flat
+    T A, B, lam, mu, beta, n, inv2n, c2, c2_d2, d2, h, R, pi_sr;
+    T u_series, a1, a2, a3, a4, a5;
+    T S;
+};
+template <class T>
+struct TersoffArg<T, true> {
     TCenter<T> c[kMaxTypes];
     TPair<T> p[kMaxTypes * kMaxTypes];
     double S2[kMaxTypes * kMaxTypes];
@@ -106,9 +116,9 @@ TPair<T> pair_constants(const TersoffTable& tab, int a, int b, double* S_out)
 }
 
 template <class T>
-TersoffKM<T> tersoff_table(const TersoffTable& tab)
+TersoffArg<T, true> tersoff_table(const TersoffTable& tab)
 {
-    TersoffKM<T> k{};
+    TersoffArg<T, true> k{};
     for (int a = 0; a < tab.nt; ++a) {
         k.c[a] = center_constants<T>(tab.elem[a]);
         for (int b = 0; b < tab.nt; ++b) {
@@ -117,6 +127,37 @@ TersoffKM<T> tersoff_table(const TersoffTable& tab)
             k.S2[a * kMaxTypes + b] = S * S;
         }
     }
+    return k;
+}
+
+template <class T>
+TersoffArg<T, false> tersoff_single(const TersoffTable& tab, double* S2)
+{
+    double S;
+    const TCenter<T> c = center_constants<T>(tab.elem[0]);
+    const TPair<T> p = pair_constants<T>(tab, 0, 0, &S);
+    TersoffArg<T, false> k;
+    k.A = p.A;
+    k.B = p.B;
+    k.lam = p.lam;
+    k.mu = p.mu;
+    k.beta = c.beta;
+    k.n = c.n;
+    k.inv2n = c.inv2n;
+    k.c2 = c.c2;
+    k.c2_d2 = c.c2_d2;
+    k.d2 = c.d2;
+    k.h = c.h;
+    k.R = p.R;
+    k.pi_sr = p.pi_sr;
+    k.u_series = c.u_series;
+    k.a1 = c.a1;
+    k.a2 = c.a2;
+    k.a3 = c.a3;
+    k.a4 = c.a4;
+    k.a5 = c.a5;
+    k.S = p.S;
+    *S2 = S * S;
     return k;
 }
 
@@ -129,7 +170,7 @@ struct TersoffLds {
 };
 
 template <class T>
-__device__ __forceinline__ void fill_lds_table(const TersoffKM<T>& K, TersoffLds<T>& L)
+__device__ __forceinline__ void fill_lds_table(const TersoffArg<T, true>& K, TersoffLds<T>& L)
 {
     if (threadIdx.x < kMaxTypes) L.c[threadIdx.x] = K.c[threadIdx.x];
     if (threadIdx.x < kMaxTypes * kMaxTypes) {
@@ -183,8 +224,8 @@ __device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(
 // f_C and f_C' (the caller only passes bonds inside the cutoff by the FP64
 // test on r^2; r formed in the working precision that rounds to S or above
 // takes the limit 0).
-template <class T>
-__device__ __forceinline__ void cutoff_fc(const TPair<T>& p, T r, T& fc, T& dfc)
+template <class P, class T>
+__device__ __forceinline__ void cutoff_fc(const P& p, T r, T& fc, T& dfc)
 {
     if (r < p.R) {
         fc = T(1);
@@ -200,8 +241,8 @@ __device__ __forceinline__ void cutoff_fc(const TPair<T>& p, T r, T& fc, T& dfc)
     }
 }
 
-template <class T>
-__device__ __forceinline__ void angular_g(const TCenter<T>& p, T cs, T& g, T& dg)
+template <class P, class T>
+__device__ __forceinline__ void angular_g(const P& p, T cs, T& g, T& dg)
 {
     const T t = p.h - cs;
     const T iq = nr_rcp(p.d2 + t * t);
@@ -212,8 +253,8 @@ __device__ __forceinline__ void angular_g(const TCenter<T>& p, T cs, T& g, T& dg
 // b(zeta) and db/dzeta; b(0) = 1, db/dzeta(0) = 0.  With u = (beta zeta)^n,
 // b = (1 + u)^(-1/(2n)) is summed as its binomial series when u is small
 // (the usual case: u ~ 1e-4 in the crystal) and through exp/log1p otherwise.
-template <class T>
-__device__ __forceinline__ void bond_order(const TCenter<T>& p, T zeta, T& b, T& db)
+template <class P, class T>
+__device__ __forceinline__ void bond_order(const P& p, T zeta, T& b, T& db)
 {
     b = T(1);
     db = T(0);
@@ -240,26 +281,28 @@ __device__ __forceinline__ void bond_geometry(const Disp& d, T& ux, T& uy, T& uz
     uz = dz * ir;
 }
 
-// Per-bond constants: the table entry of type pair (ti, tj), or entry 0.
+// Per-bond and per-centre constants: the LDS table entries of type pair tp
+// and of type ti, or the single element's flat argument (which carries both
+// sets of fields).
 template <class T, bool MULTI>
-__device__ __forceinline__ const TPair<T>& pair_of(const TersoffKM<T>& K, const TersoffLds<T>& L,
-                                                   int tp)
+__device__ __forceinline__ const auto& pair_of(const TersoffArg<T, MULTI>& K,
+                                               const TersoffLds<T>& L, int tp)
 {
     if constexpr (MULTI) return L.p[tp];
-    else return K.p[0];
+    else return K;
 }
 template <class T, bool MULTI>
-__device__ __forceinline__ const TCenter<T>& center_of(const TersoffKM<T>& K,
-                                                       const TersoffLds<T>& L, int ti)
+__device__ __forceinline__ const auto& center_of(const TersoffArg<T, MULTI>& K,
+                                                 const TersoffLds<T>& L, int ti)
 {
     if constexpr (MULTI) return L.c[ti];
-    else return K.c[0];
+    else return K;
 }
 
 // One thread, any number of bonds (the overflow pass).  tp of bond c is the
 // table index ti * kMaxTypes + tj.
 template <class T, int MAXC, bool FIXED, bool MULTI>
-__device__ __forceinline__ void tersoff_site(const TersoffKM<T>& K, const TersoffLds<T>& L,
+__device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, const TersoffLds<T>& L,
                                              int64_t i, int64_t cap, const double4& xi,
                                              unsigned long long msk, int cnt,
                                              const int* __restrict__ nl,
@@ -269,7 +312,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffKM<T>& K, const Tersof
     T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], fc[MAXC], dfc[MAXC], zp[MAXC], pd[MAXC];
     int slot[MAXC], tp[MAXC];
     const int ti = MULTI ? (int)xi.w : 0;
-    const TCenter<T>& pc = center_of<T, MULTI>(K, L, ti);
+    const auto& pc = center_of<T, MULTI>(K, L, ti);
     unsigned long long rem = msk;
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
@@ -307,10 +350,10 @@ __device__ __forceinline__ void tersoff_site(const TersoffKM<T>& K, const Tersof
 #pragma unroll
     for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
         if (c < cnt) {
-            const TPair<T>& pp = pair_of<T, MULTI>(K, L, tp[c]);
+            const auto& pp = pair_of<T, MULTI>(K, L, tp[c]);
             T b, db;
             bond_order(pc, zp[c], b, db);
-            if (MULTI) {
+            if constexpr (MULTI) {
                 b *= pp.chi;
                 db *= pp.chi;
             }
@@ -379,7 +422,7 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
 // kQuad * SLOTS in-cutoff bonds go to the overflow list.
 template <class T, int SLOTS, bool MULTI>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
+k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t cap,
                     const double4* __restrict__ xw, const int* __restrict__ nn,
                     const int* __restrict__ nl, unsigned long long* __restrict__ mask,
                     double* __restrict__ U, T* __restrict__ dpart, int* __restrict__ ovf_count,
@@ -391,7 +434,7 @@ k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
     if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
-    if (MULTI) fill_lds_table(K, L);
+    if constexpr (MULTI) fill_lds_table(K, L);
     const Box box = g.box;
     const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
     const int64_t i = g.atom_off + local;
@@ -401,9 +444,11 @@ k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
     const int nnb = valid ? min(nn[i], M) : 0;
     Disp d_first;
     int t_first = 0;
-    const unsigned long long msk =
-        MULTI ? quad_cutoff_mask_typed(xi, ti, i, cap, nnb, q, nl, xw, box, L.S2, d_first, t_first)
-              : quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, K.S2[0], d_first);
+    unsigned long long msk;
+    if constexpr (MULTI)
+        msk = quad_cutoff_mask_typed(xi, ti, i, cap, nnb, q, nl, xw, box, L.S2, d_first, t_first);
+    else
+        msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
@@ -411,7 +456,7 @@ k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
         if (ovf) ovf_list[atomicAdd(ovf_count, 1)] = (int)i;
     }
     const int kc = (valid && !ovf) ? cnt : 0;   // bonds handled by this quad
-    const TCenter<T>& pc = center_of<T, MULTI>(K, L, ti);
+    const auto& pc = center_of<T, MULTI>(K, L, ti);
 
     T ux[SLOTS], uy[SLOTS], uz[SLOTS], rr[SLOTS], ir[SLOTS],
         fc[SLOTS], dfc[SLOTS], zp[SLOTS], pd[SLOTS];
@@ -479,10 +524,10 @@ k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
     for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         if (c < kc) {
-            const TPair<T>& pp = pair_of<T, MULTI>(K, L, tp[s]);
+            const auto& pp = pair_of<T, MULTI>(K, L, tp[s]);
             T b, db;
             bond_order(pc, zp[s], b, db);
-            if (MULTI) {
+            if constexpr (MULTI) {
                 b *= pp.chi;
                 db *= pp.chi;
             }
@@ -553,13 +598,13 @@ k_tersoff_site_quad(TersoffKM<T> K, Segs S, int M, int64_t cap,
 // the whole list capacity.
 template <class T, bool MULTI>
 __global__ void __launch_bounds__(kBlock)
-k_tersoff_partials_ovf(TersoffKM<T> K, Segs S, int64_t cap, const double4* __restrict__ xw,
+k_tersoff_partials_ovf(TersoffArg<T, MULTI> K, Segs S, int64_t cap, const double4* __restrict__ xw,
                        const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
                        double* __restrict__ U, T* __restrict__ dpart,
                        const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
 {
     __shared__ TersoffLds<T> L;
-    if (MULTI) fill_lds_table(K, L);
+    if constexpr (MULTI) fill_lds_table(K, L);
     const int total = *ovf_count;
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
         const int64_t i = ovf_list[k];
@@ -573,16 +618,18 @@ k_tersoff_partials_ovf(TersoffKM<T> K, Segs S, int64_t cap, const double4* __res
 
 constexpr int kOvfGrid = 64;
 
+// rc2: the single element's cutoff squared (the multi-type table holds its own).
 template <class T, bool MULTI>
 hipError_t launch_tersoff_kernels(const Buffers& b, const Segs& S, int cur,
-                                  const TersoffKM<T>& k, bool overflow_pass, int max_nn,
-                                  hipStream_t s)
+                                  const TersoffArg<T, MULTI>& k, double rc2, bool overflow_pass,
+                                  int max_nn, hipStream_t s)
 {
     constexpr int kSlots = MULTI ? kTersoffMultiSlots : kTersoffSlots;
     T* dp = static_cast<T*>(b.dpart);
     if (!overflow_pass) {
         k_tersoff_site_quad<T, kSlots, MULTI><<<S.nblk_quad, kBlock, 0, s>>>(
-            k, S, b.M, b.cap, b.xw[cur], b.nn, b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
+            k, rc2, S, b.M, b.cap, b.xw[cur], b.nn, b.nl, b.mask, b.U, dp, b.ovf_count,
+            b.ovf_list);
         return hipGetLastError();
     }
     if (b.M > kQuad * kSlots && max_nn > kQuad * kSlots)
@@ -598,10 +645,12 @@ hipError_t launch_tersoff_partials(const Buffers& b, const Segs& S, int cur,
 {
     if (S.nblk_quad <= 0) return hipSuccess;
     if (!segs_ready(S, b) || tab.nt < 1 || tab.nt > kMaxTypes) return hipErrorInvalidValue;
-    const TersoffKM<T> k = tersoff_table<T>(tab);
     if (tab.nt > 1)
-        return launch_tersoff_kernels<T, true>(b, S, cur, k, overflow_pass, max_nn, s);
-    return launch_tersoff_kernels<T, false>(b, S, cur, k, overflow_pass, max_nn, s);
+        return launch_tersoff_kernels<T, true>(b, S, cur, tersoff_table<T>(tab), 0.0,
+                                               overflow_pass, max_nn, s);
+    double rc2;
+    const TersoffArg<T, false> k = tersoff_single<T>(tab, &rc2);
+    return launch_tersoff_kernels<T, false>(b, S, cur, k, rc2, overflow_pass, max_nn, s);
 }
 
 template hipError_t launch_tersoff_partials<double>(const Buffers&, const Segs&, int,
