@@ -103,10 +103,12 @@ def tersoff_site_flops(mean_L, mean_K, mean_KK):
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the HIP sources and headers the library is built from."""
+    """SHA-256 over the sources that define the kernels and their launch
+    shapes (every csrc file but the host-side C ABI, capi.hip, which only
+    sequences launches)."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1610_03343_amd", "csrc", "*")))
-    files.append(os.path.join(ROOT, "include", "mbmd.h"))
+    files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_1610_03343_amd", "csrc", "*"))
+                   if os.path.basename(f) != "capi.hip")
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())

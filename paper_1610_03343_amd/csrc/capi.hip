@@ -85,7 +85,10 @@ struct mbmd_ctx {
     int laid_M = 0, laid_segs = 0;
     bool laid_state = false;
     int max_nn = kMaxSlots;      // largest list count over the segments of the next launch
-    std::vector<int> seg_max_nn; // per segment, from the last build launch
+    int* nn_host = nullptr;      // pinned: per-segment largest list count of the last build
+    int nn_host_cap = 0;
+    hipEvent_t nn_ev = nullptr;  // marks when nn_host is complete
+    bool nn_pending = false;     // max_nn still to be formed from nn_host
     int pp = 0;                  // phase buffer read by the next pairwise launch
     int fold_from = 0;           // single-structure thermo rows pending a fold
     int fold_to = 0;
@@ -387,10 +390,12 @@ mbmd_status finish(mbmd_ctx* c)
 }
 
 // Builds the lists of every segment flagged in the table.  With `readback`
-// the largest count per segment is read back (one stream sync per build) and
-// c->max_nn, the largest over the built segments, decides whether the
-// partials overflow pass is needed; without it the overflow pass is always
-// enqueued (it exits at once when no atom overflowed).
+// the largest count per segment is copied to pinned host memory behind an
+// event, and c->max_nn, the largest over the built segments, is formed from
+// it when the partials pass has to decide on its overflow pass: by then the
+// fast site pass is already queued, so the GPU computes while the host waits
+// for the copy.  Without `readback` the overflow pass is always enqueued (it
+// exits at once when no atom overflowed).
 hipError_t build(mbmd_ctx* c, int total_cells, int cur, bool readback = true)
 {
     hipError_t e;
@@ -399,21 +404,48 @@ hipError_t build(mbmd_ctx* c, int total_cells, int cur, bool readback = true)
         e = launch_build_neighbors(c->buf, c->segs, total_cells, cur, cutoff_of(c) + c->skin,
                                    cutoff_of(c), c->stream);
     }
-    if (!readback) {
-        c->max_nn = kMaxSlots;
-        return e;
-    }
+    c->max_nn = kMaxSlots;
+    c->nn_pending = false;
     const int ns = c->segs.nseg;
-    c->seg_max_nn.assign(ns > 0 ? ns : 1, kMaxSlots);
-    if (e == hipSuccess && ns > 0)
-        e = hipMemcpyAsync(c->seg_max_nn.data(), c->buf.maxnn, sizeof(int) * ns,
-                           hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    int mx = 0;
-    for (int k = 0; k < ns; ++k)
-        if (c->segs_host[k].build) mx = std::max(mx, c->seg_max_nn[k]);
-    c->max_nn = e == hipSuccess ? mx : kMaxSlots;
+    if (!readback || e != hipSuccess || ns <= 0) return e;
+    if (c->nn_host_cap < ns) {
+        if (c->nn_host) (void)hipHostFree(c->nn_host);
+        c->nn_host = nullptr;
+        c->nn_host_cap = 0;
+        e = hipHostMalloc((void**)&c->nn_host, sizeof(int) * ns, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            c->nn_host = nullptr;
+            return e;
+        }
+        c->nn_host_cap = ns;
+    }
+    if (!c->nn_ev) {
+        e = hipEventCreateWithFlags(&c->nn_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            c->nn_ev = nullptr;
+            return e;
+        }
+    }
+    e = hipMemcpyAsync(c->nn_host, c->buf.maxnn, sizeof(int) * ns, hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->nn_ev, c->stream);
+    c->nn_pending = e == hipSuccess;
     return e;
+}
+
+// Forms c->max_nn from the read-back counts of the last build (waits for
+// the copy if it is still in flight).
+hipError_t resolve_max_nn(mbmd_ctx* c)
+{
+    if (!c->nn_pending) return hipSuccess;
+    c->nn_pending = false;
+    hipError_t e = hipEventSynchronize(c->nn_ev);
+    if (e != hipSuccess) return e;
+    int mx = 0;
+    for (int k = 0; k < c->segs.nseg; ++k)
+        if (c->segs_host[k].build) mx = std::max(mx, c->nn_host[k]);
+    c->max_nn = mx;
+    return hipSuccess;
 }
 
 template <class T>
@@ -424,7 +456,12 @@ hipError_t partials(mbmd_ctx* c, int cur)
         // the overflow pass only exists when a site can exceed the fast path
         const int fast = kQuad * (c->potential == 1 ? kSWSlots
                                   : (c->ttab.nt > 1 ? kTersoffMultiSlots : kTersoffSlots));
-        if (pass == 1 && !(c->buf.M > fast && c->max_nn > fast)) break;
+        if (pass == 1) {
+            if (!(c->buf.M > fast)) break;
+            e = resolve_max_nn(c);
+            if (e != hipSuccess) return e;
+            if (!(c->max_nn > fast)) break;
+        }
         ProfScope ps(c, pass ? P_PARTIALS_OVF : P_PARTIALS);
         if (c->potential == 1)
             e = launch_sw_partials<T>(c->buf, c->segs, cur, c->sp, pass == 1, c->max_nn,
@@ -903,6 +940,8 @@ void mbmd_destroy(mbmd_ctx* c)
         (void)hipSetDevice(c->device);
         (void)hipFree(c->gk_ws);
     }
+    if (c->nn_host) (void)hipHostFree(c->nn_host);
+    if (c->nn_ev) (void)hipEventDestroy(c->nn_ev);
     free_batch(c);
     delete c;
 }

@@ -34,7 +34,9 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Fixed-order block sum of kPartialCols values per thread into lds_out.
+// Fixed-order sum over a block of NT threads of kPartialCols values per
+// thread into lds_out (lds: one row per wave).
+template <int NT>
 __device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
                                                double (*lds)[kPartialCols],
                                                double* lds_out)
@@ -49,11 +51,15 @@ __device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
     if (threadIdx.x < kPartialCols) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < kBlock / 64; ++k) s += lds[k][threadIdx.x];
+        for (int k = 0; k < NT / 64; ++k) s += lds[k][threadIdx.x];
         lds_out[threadIdx.x] = s;
     }
     __syncthreads();
 }
+
+// Threads of the fold kernels (1024 threads, four times fewer rounds of
+// loads, measured slower: the fold is bound by launch latency).
+constexpr int kFoldThreads = kBlock;
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
@@ -204,14 +210,15 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     for (int c = 0; c < 9; ++c) vals[2 + c] = w[c];
 #pragma unroll
     for (int c = 0; c < 3; ++c) vals[11 + c] = jj[c];
-    block_sum_cols(vals, lds, lds_tot);
+    block_sum_cols<kBlock>(vals, lds, lds_tot);
     if (threadIdx.x < kPartialCols) a.part_row[(int64_t)lb * kPartialCols + threadIdx.x] = lds_tot[threadIdx.x];
 }
 
-// Sums one segment's block partials of one step (ring row rowp), in block
+// Sums one segment's block partials of one step (ring row rowp), in a fixed
 // order, into its thermo row: 0 E_pot, 1 E_kin, 2..10 W, 11..13 J,
 // 14 E_pot + E_kin, 15 kinetic temperature (k_B in eV/K, 3N - 3 degrees of
-// freedom).  Called by every thread of the block; thread 0 writes the row.
+// freedom).  Called by every thread of a kFoldThreads block; thread 0 writes
+// the row.
 __device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp, const Seg& g,
                                                  double (*lds)[kPartialCols], double* lds_tot,
                                                  double* __restrict__ row)
@@ -220,12 +227,12 @@ __device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp
     double vals[kPartialCols];
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
+    for (int b = b0 + threadIdx.x; b < b1; b += kFoldThreads) {
         const double* p = rowp + (int64_t)b * kPartialCols;
 #pragma unroll
         for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
     }
-    block_sum_cols(vals, lds, lds_tot);
+    block_sum_cols<kFoldThreads>(vals, lds, lds_tot);
     if (threadIdx.x == 0) {
         const double n = (double)g.n;
 #pragma unroll
@@ -236,11 +243,11 @@ __device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp
 }
 
 // One block per step of one segment: row k = first + blockIdx.x.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFoldThreads)
 k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int sid, int first,
               int ring0, double* __restrict__ thermo)
 {
-    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     const int k = first + blockIdx.x;
     const double* rowp = part_b + (int64_t)((ring0 + k) % kThermoRing) * blk_cap * kPartialCols;
@@ -252,16 +259,16 @@ hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int firs
 {
     if (count <= 0) return hipSuccess;
     if (!S.seg || sid < 0 || sid >= S.nseg || !thermo) return hipErrorInvalidValue;
-    k_thermo_fold<<<count, kBlock, 0, s>>>(b.part_b, b.blk_cap, S, sid, first, ring0, thermo);
+    k_thermo_fold<<<count, kFoldThreads, 0, s>>>(b.part_b, b.blk_cap, S, sid, first, ring0, thermo);
     return hipGetLastError();
 }
 
 // One block per segment: its row of the step just taken (phase_in) from ring
 // row `ring_row`, for segments that took part and have a thermo pointer.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFoldThreads)
 k_thermo_fold_segments(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int ring_row)
 {
-    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     const int sid = blockIdx.x;
     const Seg& g = S.seg[sid];
@@ -276,7 +283,7 @@ hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring
 {
     if (S.nseg <= 0) return hipSuccess;
     if (!segs_ready(S, b)) return hipErrorInvalidValue;
-    k_thermo_fold_segments<<<S.nseg, kBlock, 0, s>>>(b.part_b, b.blk_cap, S,
+    k_thermo_fold_segments<<<S.nseg, kFoldThreads, 0, s>>>(b.part_b, b.blk_cap, S,
                                                       ring_row % kThermoRing);
     return hipGetLastError();
 }
@@ -292,13 +299,13 @@ hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring
 // scales the segment's box in device memory, so the step loop never waits
 // for the host.  The arithmetic is kept unfused, as a plain IEEE evaluation
 // of these expressions in this order.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kFoldThreads)
 k_npt_fold(const double* __restrict__ rowp, Segs S, Seg* __restrict__ seg_rw, NptArgs a,
            int step, int last, double* __restrict__ coupling, double* __restrict__ thermo,
            double* __restrict__ box_traj, unsigned* __restrict__ status)
 {
 #pragma clang fp contract(off)
-    __shared__ double lds[kBlock / 64][kPartialCols];
+    __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     double* row = thermo + (int64_t)step * kThermoCols;
     fold_segment_row(rowp, S.seg[0], lds, lds_tot, row);
@@ -335,7 +342,7 @@ hipError_t launch_npt_fold(const Buffers& b, const Segs& S, int ring_row, int st
 {
     if (!segs_ready(S, b) || S.nseg != 1 || !thermo || !b.coupling) return hipErrorInvalidValue;
     const double* rowp = b.part_b + (int64_t)(ring_row % kThermoRing) * b.blk_cap * kPartialCols;
-    k_npt_fold<<<1, kBlock, 0, s>>>(rowp, S, b.seg, a, step, last ? 1 : 0, b.coupling, thermo,
+    k_npt_fold<<<1, kFoldThreads, 0, s>>>(rowp, S, b.seg, a, step, last ? 1 : 0, b.coupling, thermo,
                                     box_traj, b.status);
     return hipGetLastError();
 }
