@@ -285,36 +285,62 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
         const double4 xi = xw[i];
         const int c = cell_of[i] - g.cell_off;
         const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
-        int lo[3], hi[3];
+        // The stencil cells to visit, as bits k = 9 (oz + 1) + 3 (oy + 1) +
+        // (ox + 1).  A cell at offset (ox, oy, oz) whose nearest point is
+        // farther from x_i than r_list (with a relative margin of 1e-5 on r^2,
+        // far above the float rounding of these sums) holds no list entry and
+        // is left out, so the lists are exactly those of the full stencil.
+        // Boxes with fewer than three cells along an axis visit each distinct
+        // cell once and prune nothing.
+        unsigned visit = 0;
+        {
+            float gap2[3][3];
+            const int ci[3] = {cx, cy, cz};
+            const double xa[3] = {xi.x, xi.y, xi.z};
+            int lo[3], hi[3];
+            bool prune = true;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = g.nc[a] >= 3 ? -1 : 0;
-            hi[a] = g.nc[a] >= 2 ? 1 : 0;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = g.nc[a] >= 3 ? -1 : 0;
+                hi[a] = g.nc[a] >= 2 ? 1 : 0;
+                prune = prune && g.nc[a] >= 3;
+                double f = xa[a] * g.inv_lc[a] - (double)ci[a];
+                f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+                const double side = g.box.L[a] / (double)g.nc[a];
+                gap2[a][0] = (float)(f * f * side * side);
+                gap2[a][1] = 0.0f;
+                gap2[a][2] = (float)((1.0 - f) * (1.0 - f) * side * side);
+            }
+            const float skip2 = prune ? (float)(rl2 * (1.0 + 1e-5)) : 3.0e38f;
+            for (int oz = lo[2]; oz <= hi[2]; ++oz)
+                for (int oy = lo[1]; oy <= hi[1]; ++oy)
+                    for (int ox = lo[0]; ox <= hi[0]; ++ox)
+                        if (gap2[2][oz + 1] + gap2[1][oy + 1] + gap2[0][ox + 1] <= skip2)
+                            visit |= 1u << (9 * (oz + 1) + 3 * (oy + 1) + (ox + 1));
         }
-        for (int oz = lo[2]; oz <= hi[2]; ++oz) {
+        while (visit) {
+            const int k = __builtin_ctz(visit);
+            visit &= visit - 1;
+            const int oz = k / 9 - 1, oy = (k / 3) % 3 - 1, ox = k % 3 - 1;
             const int zz = (cz + oz + g.nc[2]) % g.nc[2];
-            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-                const int yy = (cy + oy + g.nc[1]) % g.nc[1];
-                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                    const int xx = (cx + ox + g.nc[0]) % g.nc[0];
-                    const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
-                    const int e = start[cc + 1];
-                    for (int p = start[cc]; p < e; ++p) {
-                        const int j = cell_atoms[p];
-                        if (j == (int)i) continue;
-                        double r2;
-                        if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi, r2)) {
-                            // insertion into the LDS list (capacity M) ordered by key
-                            const unsigned key = (unsigned)j | (r2 < rc2 ? 0u : 0x80000000u);
-                            int q = cnt < M ? cnt : M;
-                            while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
-                                if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
-                                --q;
-                            }
-                            if (q < M) buf[q * kSearchBlock] = (int)key;
-                            ++cnt;
-                        }
+            const int yy = (cy + oy + g.nc[1]) % g.nc[1];
+            const int xx = (cx + ox + g.nc[0]) % g.nc[0];
+            const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
+            const int e = start[cc + 1];
+            for (int p = start[cc]; p < e; ++p) {
+                const int j = cell_atoms[p];
+                if (j == (int)i) continue;
+                double r2;
+                if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi, r2)) {
+                    // insertion into the LDS list (capacity M) ordered by key
+                    const unsigned key = (unsigned)j | (r2 < rc2 ? 0u : 0x80000000u);
+                    int q = cnt < M ? cnt : M;
+                    while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
+                        if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
+                        --q;
                     }
+                    if (q < M) buf[q * kSearchBlock] = (int)key;
+                    ++cnt;
                 }
             }
         }
