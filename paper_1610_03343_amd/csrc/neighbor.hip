@@ -269,7 +269,7 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
          double rc2, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
          const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
-         int* __restrict__ maxnn, unsigned* __restrict__ status)
+         int* __restrict__ rev, int* __restrict__ maxnn, unsigned* __restrict__ status)
 {
     extern __shared__ int lbuf[];
     __shared__ int lds_max[kSearchBlock / 64];
@@ -349,8 +349,10 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
         if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
         nn[i] = cnt;
         const int w = cnt < M ? cnt : M;
-        for (int m = 0; m < w; ++m)
+        for (int m = 0; m < w; ++m) {
             nl[(int64_t)m * cap + i] = buf[m * kSearchBlock] & 0x7fffffff;
+            rev[(int64_t)m * cap + i] = 0;   // an in-range slot until k_reverse sets it
+        }
     }
     // largest count of the block, one atomic per block
     int mx = cnt;
@@ -376,12 +378,32 @@ k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M,
     const int cnt = min(nn[i], M);
     for (int m = 0; m < cnt; ++m) {
         const int j = nl[(int64_t)m * cap + i];
+        // Complete lists are symmetric (the inclusion test gives the same
+        // bits for (i, j) and (j, i)), so such a pair is settled once, by
+        // its smaller index, which writes both reverse slots.  When either
+        // list overflowed (the call then fails) each thread writes its own
+        // entry.  Either way every entry below the count is written exactly
+        // once, so the pairwise pass never reads a stale slot.
+        const bool both_complete = nn[i] <= M && nn[j] <= M;
+        if (both_complete && j < (int)i) continue;
         const int cj = min(nn[j], M);
         int s = -1;
-        for (int q = 0; q < cj; ++q)
-            if (nl[(int64_t)q * cap + j] == (int)i) { s = q; break; }
-        if (s < 0) atomicOr(status, ST_ASYMMETRIC);
-        rev[(int64_t)m * cap + i] = s < 0 ? 0 : s;
+        // find i in j's list, eight independent loads at a time
+        for (int q0 = 0; q0 < cj && s < 0; q0 += 8) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = q0 + u < cj ? nl[(int64_t)(q0 + u) * cap + j] : -1;
+#pragma unroll
+            for (int u = 7; u >= 0; --u)
+                if (v[u] == (int)i) s = q0 + u;
+        }
+        if (s < 0) {
+            atomicOr(status, ST_ASYMMETRIC);
+            rev[(int64_t)m * cap + i] = 0;
+            continue;
+        }
+        rev[(int64_t)m * cap + i] = s;
+        if (both_complete) rev[(int64_t)s * cap + j] = m;
     }
 }
 
@@ -409,7 +431,7 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
                                                    rl2 * (1.0 + 1e-10), rcut * rcut, b.M, b.cap,
                                                    b.cell_of,
                                                    b.cell_start, b.cell_atoms, b.nn, b.nl,
-                                                   b.maxnn, b.status);
+                                                   b.rev, b.maxnn, b.status);
     k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
 }
