@@ -298,8 +298,11 @@ mbmd_status mbmd_sync(mbmd_ctx *ctx);
  * per-atom sum runs over its own sorted list, and every per-structure sum
  * over its own blocks in a fixed order, so they equal, bit for bit, those of
  * the same structure alone.  While a batch is open the context accepts only
- * batch calls.  The lists of a structure are rebuilt at its admission and
- * every rebuild_every of its steps. */
+ * batch calls.  Lists are rebuilt for all running structures together,
+ * every rebuild_every batch steps; an admitted structure starts at the next
+ * such step (at once if no structure is running, else at most rebuild_every
+ * - 1 batch steps later), so its lists are rebuilt at its own steps 0,
+ * rebuild_every, 2 rebuild_every, ... as in a run alone. */
 
 /* Open a batch of at most max_atoms atoms in at most max_structures
  * structures (the workspace is sized for that; see
@@ -332,10 +335,11 @@ mbmd_status mbmd_batch_add(mbmd_ctx *ctx, int64_t n, const double box[3], const 
                            const double *vel, double mass_amu, double dt_fs, int n_steps,
                            double *thermo, int *handle);
 
-/* One step of every unfinished structure (its force evaluation, and the
- * integration unless it is at its last step).  *n_active receives the
- * number of structures that took part.  Asynchronous: returns once the work
- * is enqueued. */
+/* One step of every started, unfinished structure (its force evaluation,
+ * and the integration unless it is at its last step).  *n_active receives
+ * the number of structures that took part (admitted structures waiting for
+ * the next rebuild step do not).  Asynchronous: returns once the work is
+ * enqueued. */
 mbmd_status mbmd_batch_step(mbmd_ctx *ctx, mbmd_precision prec, int *n_active);
 
 /* Handles of finished, not yet retired structures (up to capacity; *count

@@ -6,10 +6,13 @@
 
 namespace mbmd {
 
+// Positions go to both position buffers: a structure waits for the batch's
+// next list-rebuild step before it starts, and until then no step carries
+// its positions from one buffer to the other.
 __global__ void __launch_bounds__(kBlock)
 k_batch_admit(const double* __restrict__ pos, const double* __restrict__ vel, int64_t n, Box box,
-              int atom_off, double4* __restrict__ xw, double* __restrict__ vel_dst,
-              int64_t stride, unsigned* __restrict__ status)
+              int atom_off, double4* __restrict__ xw0, double4* __restrict__ xw1,
+              double* __restrict__ vel_dst, int64_t stride, unsigned* __restrict__ status)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -18,19 +21,21 @@ k_batch_admit(const double* __restrict__ pos, const double* __restrict__ vel, in
         atomicOr(status, ST_NONFINITE);
         x = y = z = 0.0;
     }
-    xw[atom_off + i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
-                                    wrap_coord(z, box.L[2]), 0.0);
+    const double4 p = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
+                                   wrap_coord(z, box.L[2]), 0.0);
+    xw0[atom_off + i] = p;
+    xw1[atom_off + i] = p;
 #pragma unroll
     for (int r = 0; r < 3; ++r) vel_dst[r * stride + atom_off + i] = vel[r * n + i];
 }
 
 hipError_t launch_batch_admit(const double* pos, const double* vel, int64_t n, Box box,
-                              int atom_off, double4* xw, double* vel_dst, int64_t stride,
-                              unsigned* status, hipStream_t s)
+                              int atom_off, double4* xw0, double4* xw1, double* vel_dst,
+                              int64_t stride, unsigned* status, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    k_batch_admit<<<blocks_for(n), kBlock, 0, s>>>(pos, vel, n, box, atom_off, xw, vel_dst, stride,
-                                                   status);
+    k_batch_admit<<<blocks_for(n), kBlock, 0, s>>>(pos, vel, n, box, atom_off, xw0, xw1, vel_dst,
+                                                   stride, status);
     return hipGetLastError();
 }
 

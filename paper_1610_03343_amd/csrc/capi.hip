@@ -42,7 +42,7 @@ struct Slot {
     int step = 0;            // index of its next step
     double mass = 0, dt = 0;
     double* thermo = nullptr;
-    int last_build = -1;     // its step at the last list build (-1: none yet)
+    bool started = false;    // stepping (admitted structures wait for a rebuild step)
     int final_buf = 0;       // position buffer holding its final positions
     bool done = false;
 };
@@ -53,9 +53,11 @@ struct Batch {
     int rebuild_every = 10;
     int next_handle = 1;
     int batch_step = 0;
+    int phase0 = 0;          // batch step of a list rebuild; they recur every rebuild_every
     int cur = 0;             // position buffer the next launch reads
     bool changed = true;     // segment table must be rebuilt
     std::vector<Slot> slots; // ordered by atom offset
+    std::vector<int> table;  // slots (indices) of the segment table, in order
     // Pinned staging for table uploads, used alternately; an event marks when
     // the stream has consumed each, so uploads never stall the host on the
     // kernels queued ahead of them.
@@ -801,20 +803,24 @@ Slot* find_slot(Batch& B, int handle)
 // phase of each segment (its slot's step counter, nsteps + 1 once finished)
 // goes into the phase buffer the next launch reads.  Both are staged in
 // pinned memory and copied asynchronously.
-hipError_t batch_table(mbmd_ctx* c, int* total_cells, bool* any_build)
+// Segment table of the started structures (build flag on every unfinished
+// one when `rebuild`), uploaded through the pinned staging buffers.
+hipError_t batch_table(mbmd_ctx* c, int* total_cells, bool rebuild)
 {
     Batch& B = *c->batch;
     c->segs_host.clear();
+    B.table.clear();
     const double rl = cutoff_of(c) + c->skin;
-    *any_build = false;
-    for (const Slot& s : B.slots) {
+    for (size_t q = 0; q < B.slots.size(); ++q) {
+        const Slot& s = B.slots[q];
+        if (!s.started) continue;
         Seg g = make_seg(s.box, rl, s.atom_off, s.n, s.nsteps, s.mass, s.dt, s.thermo);
-        g.build = !s.done && (s.last_build < 0 || s.step - s.last_build >= B.rebuild_every);
-        *any_build = *any_build || g.build;
+        g.build = rebuild && !s.done;
         c->segs_host.push_back(g);
+        B.table.push_back((int)q);
     }
     assign_offsets(c, total_cells);
-    const size_t ns = B.slots.size();
+    const size_t ns = B.table.size();
     if (ns == 0) return hipSuccess;
     const int k = B.stage_k;
     B.stage_k ^= 1;
@@ -825,7 +831,8 @@ hipError_t batch_table(mbmd_ctx* c, int* total_cells, bool* any_build)
     int* hp = reinterpret_cast<int*>(hs + B.max_structs);
     for (size_t q = 0; q < ns; ++q) {
         hs[q] = c->segs_host[q];
-        hp[q] = B.slots[q].done ? B.slots[q].nsteps + 1 : B.slots[q].step;
+        const Slot& s = B.slots[B.table[q]];
+        hp[q] = s.done ? s.nsteps + 1 : s.step;
     }
     e = hipMemcpyAsync(c->buf.seg, hs, sizeof(Seg) * ns, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
@@ -854,29 +861,37 @@ template <class T>
 mbmd_status batch_step_impl(mbmd_ctx* c, int* n_active)
 {
     Batch& B = *c->batch;
-    int active = 0;
-    bool due = false;
+    int running = 0, waiting = 0;
     for (const Slot& s : B.slots) {
         if (s.done) continue;
-        ++active;
-        if (s.last_build < 0 || s.step - s.last_build >= B.rebuild_every) due = true;
+        if (s.started) ++running;
+        else ++waiting;
     }
-    if (n_active) *n_active = active;
-    if (active == 0) return MBMD_OK;
+    // Lists are rebuilt for every running structure at the batch steps
+    // phase0 + k rebuild_every; an admitted structure starts at the next of
+    // them, so its own rebuild steps are 0, rebuild_every, ... as when it
+    // runs alone, and one build launch serves the whole batch.  An idle
+    // batch starts a new phase at once.
+    if (running == 0) B.phase0 = B.batch_step;
+    const bool due = (B.batch_step - B.phase0) % B.rebuild_every == 0;
+    if (due && waiting > 0) {
+        for (Slot& s : B.slots)
+            if (!s.done) s.started = true;
+        running += waiting;
+        B.changed = true;
+    }
+    if (n_active) *n_active = running;
+    if (running == 0) return MBMD_OK;
     hipError_t e = hipSuccess;
     int cells = 0;
-    bool any_build = false;
     if (B.changed || due) {
-        e = batch_table(c, &cells, &any_build);
+        e = batch_table(c, &cells, due);
         B.changed = false;
     }
-    if (e == hipSuccess && any_build) {
-        // the table was rebuilt just above, so it lists the slots in order
+    if (e == hipSuccess && due) {
         e = build(c, cells, B.cur, false);
-        for (size_t k = 0; k < B.slots.size(); ++k)
-            if (c->segs_host[k].build) B.slots[k].last_build = B.slots[k].step;
-        // the table keeps its build flags until the next rebuild of it; make
-        // sure a later step does not rebuild anything unintended
+        // the uploaded table carries build flags: the next step uploads one
+        // without them
         B.changed = true;
     }
     // no list counts are read back in the batch: the overflow pass is always
@@ -895,7 +910,7 @@ mbmd_status batch_step_impl(mbmd_ctx* c, int* n_active)
     B.cur ^= 1;
     ++B.batch_step;
     for (Slot& s : B.slots) {
-        if (s.done) continue;
+        if (s.done || !s.started) continue;
         if (s.step == s.nsteps) {
             s.done = true;
             s.final_buf = B.cur;
@@ -1367,8 +1382,8 @@ mbmd_status mbmd_batch_add(mbmd_ctx* c, int64_t n, const double box[3], const do
     sl.thermo = thermo;
     // positions into the buffer the next launch reads, velocities into the
     // batch state
-    hipError_t e = launch_batch_admit(pos, vel, n, b, (int)at, c->buf.xw[B.cur], c->buf.vel,
-                                      c->buf.ostride, c->buf.status, c->stream);
+    hipError_t e = launch_batch_admit(pos, vel, n, b, (int)at, c->buf.xw[0], c->buf.xw[1],
+                                      c->buf.vel, c->buf.ostride, c->buf.status, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "batch add");
     auto it = std::lower_bound(B.slots.begin(), B.slots.end(), (int)at,
                                [](const Slot& x, int off) { return x.atom_off < off; });

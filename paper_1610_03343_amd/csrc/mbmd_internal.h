@@ -209,11 +209,11 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int ntypes,
                                  int64_t n, Box box, int atom_off, double4* xw,
                                  unsigned* status, hipStream_t s);
-// Serving batch: wraps positions pos[3][n] into xw[atom_off ..) and copies
-// velocities vel[3][n] into vel_dst (row stride `stride`) at atom_off.
+// Serving batch: wraps positions pos[3][n] into xw0 and xw1 at atom_off and
+// copies velocities vel[3][n] into vel_dst (row stride `stride`) at atom_off.
 hipError_t launch_batch_admit(const double* pos, const double* vel, int64_t n, Box box,
-                              int atom_off, double4* xw, double* vel_dst, int64_t stride,
-                              unsigned* status, hipStream_t s);
+                              int atom_off, double4* xw0, double4* xw1, double* vel_dst,
+                              int64_t stride, unsigned* status, hipStream_t s);
 // Serving batch: copies one structure's final positions (from xw), velocities
 // and U, F, W, J (row stride `stride`, from atom_off) into caller arrays of n
 // atoms; any output may be null.

@@ -9,6 +9,13 @@ retired at once, their results are copied to the host, and their latency
 (arrival to results on the host) is recorded.  The batch's atom capacity is
 set from an HBM budget, so admission is by free device memory.
 
+The loop never drains the stream while it runs: a retirement's copies to
+pinned host memory are followed by an event that later iterations poll, and
+the host stays at most MAX_STEPS_AHEAD batch steps ahead of the GPU (it waits
+on the event of an older step), so the GPU always has queued work while the
+host admits and retires.  A request's latency ends when the host sees its
+copy complete.  The batch's device status is checked once at the end.
+
 The one-structure-per-launch path serves the same trace in arrival order
 through mbmd_compute / mbmd_nve_run, one structure at a time.
 
@@ -27,6 +34,8 @@ from . import THERMO_COLS, Context, MbmdError, MBMD_EBUSY
 
 # rows of the stacked per-request result: U, F (3), W (9), J (3), pos (3), vel (3)
 RESULT_ROWS = 22
+# batch steps the host may enqueue ahead of the GPU
+MAX_STEPS_AHEAD = 3
 
 
 @dataclass
@@ -137,10 +146,31 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
     pending = collections.deque(order)
     waiting = collections.deque()
     in_flight = {}
+    copies = collections.deque()     # (event, [(job, host, thermo host)]) not yet seen complete
+    steps_ahead = collections.deque()
+    stream = ctx.stream
     free_atoms, free_slots, largest = ctx.batch_capacity()
     t0 = clock()
+
+    def collect(block):
+        """Record every retirement whose copies have completed (the oldest
+        first; with block, wait for all of them)."""
+        while copies and (block or copies[0][0].query()):
+            ev, done = copies.popleft()
+            ev.synchronize()
+            now = clock() - t0
+            for job, host, th_host in done:
+                stats.latencies_s[job.rid] = now - (0.0 if saturate else job.arrival_s)
+                stats.atom_steps += job.n * max(1, job.n_steps)
+                if keep_results:
+                    r = _unstack(host)
+                    if th_host is not None:
+                        r["thermo"] = th_host
+                    results[job.rid] = r
+
     try:
-        while pending or waiting or in_flight:
+        while pending or waiting or in_flight or copies:
+            collect(False)
             now = clock() - t0
             while pending and (saturate or pending[0].arrival_s <= now):
                 waiting.append(pending.popleft())
@@ -161,18 +191,25 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
                 free_atoms, free_slots, largest = ctx.batch_capacity()
             stats.max_in_flight = max(stats.max_in_flight, len(in_flight))
             if not in_flight:
-                if pending and not admitted:
+                if copies:
+                    collect(True)
+                elif pending and not admitted:
                     delay = pending[0].arrival_s - (clock() - t0)
                     if delay > 2e-3:
                         time.sleep(delay - 1e-3)
                 continue
             ctx.batch_step(precision)
             stats.loop_steps += 1
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            steps_ahead.append(ev)
+            if len(steps_ahead) > MAX_STEPS_AHEAD:
+                steps_ahead.popleft().synchronize()
             fin = ctx.batch_finished()
             if not fin:
                 continue
-            # retire every finished structure (asynchronous copies into
-            # pinned host buffers), then wait once for all of them
+            # retire every finished structure: asynchronous copies into pinned
+            # host buffers, marked by one event that later iterations poll
             done = []
             for h in fin:
                 job = in_flight.pop(h)
@@ -185,18 +222,13 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
                     th_host = torch.empty(th.shape, dtype=torch.float64, pin_memory=True)
                     th_host.copy_(th, non_blocking=True)
                 done.append((job, host, th_host))
-            ctx.batch_sync()
-            now = clock() - t0
-            for job, host, th_host in done:
-                stats.latencies_s[job.rid] = now - (0.0 if saturate else job.arrival_s)
-                stats.atom_steps += job.n * max(1, job.n_steps)
-                if keep_results:
-                    r = _unstack(host)
-                    if th_host is not None:
-                        r["thermo"] = th_host
-                    results[job.rid] = r
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            copies.append((ev, done))
             free_atoms, free_slots, largest = ctx.batch_capacity()
+        collect(True)
         stats.makespan_s = clock() - t0
+        ctx.batch_sync()
     finally:
         ctx.batch_close()
     return results, stats

@@ -229,3 +229,22 @@ def test_serving_loop_trace_and_identity():
             b = res_s[rid][k].cpu().numpy()
             assert np.array_equal(a, b), (rid, k)
     assert mb.MBMD_OK == 0
+
+
+def test_serving_loop_reports_device_errors():
+    """The request loop checks the batch status once, at the end: a request
+    with a non-finite position still surfaces as MBMD_ENONFINITE."""
+    import paper_1610_03343_amd as mb
+    from paper_1610_03343_amd import serving
+    reqs = wl.serving_trace(8, rate_hz=400.0, seed=2002, max_cells=4, nve_steps=10)
+    jobs = serving.jobs_from_requests(reqs)
+    bad = jobs[3]
+    pos = bad.pos.copy()
+    pos[0, 1] = np.nan
+    jobs[3] = serving.Job(bad.rid, bad.arrival_s, pos, bad.vel, bad.box, bad.n_steps)
+    with context("tersoff") as ctx:
+        with pytest.raises(mb.MbmdError) as e:
+            serving.serve_batched(ctx, jobs, hbm_budget_bytes=128 << 20, max_structures=8,
+                                  rebuild_every=5)
+        assert e.value.code == mb.MBMD_ENONFINITE
+        ctx.sync()
