@@ -415,6 +415,57 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
     return quad_or(msk);
 }
 
+// Partner terms of the partials of the quad site pass: for each own bond c
+// and partner bond e of the same atom (fetched from the other lanes),
+//   dU_i/dr_c += -1/2 (P_c f_C(r_e) + P_e f_C(r_c)) g'(cos_ce) (u_e - cos_ce u_c) / r_c
+//               [- 1/2 P_e f_C'(r_c) g(cos_ce) u_c   when TAPER].
+template <class T, int SLOTS, bool TAPER, class P>
+__device__ __forceinline__ void tersoff_partner_terms(
+    const P& pc, int q, int kc, int tmax, const T (&ux)[SLOTS], const T (&uy)[SLOTS],
+    const T (&uz)[SLOTS], const T (&ir)[SLOTS], const T (&fc)[SLOTS], const T (&dfc)[SLOTS],
+    const T (&zp)[SLOTS], const T (&g0)[kQuad], const T (&dg0)[kQuad], T (&gx)[SLOTS],
+    T (&gy)[SLOTS], T (&gz)[SLOTS])
+{
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+        if (t >= tmax) break;   // wave-uniform
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k) {
+            const T ex = k ? quad_xor(ux[t], k) : ux[t];
+            const T ey = k ? quad_xor(uy[t], k) : uy[t];
+            const T ez = k ? quad_xor(uz[t], k) : uz[t];
+            const T ef = k ? quad_xor(fc[t], k) : fc[t];
+            const T ep = k ? quad_xor(zp[t], k) : zp[t];
+            const int e = (q ^ k) + kQuad * t;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int c = q + kQuad * s;
+                if (c < kc && e < kc && e != c) {
+                    const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
+                    T g, dg;
+                    if (s == 0 && t == 0) {
+                        g = g0[k];
+                        dg = dg0[k];
+                    } else {
+                        angular_g(pc, cs, g, dg);
+                    }
+                    const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
+                    if constexpr (TAPER) {
+                        const T bb = T(-0.5) * ep * dfc[s] * g;
+                        gx[s] += a * (ex - cs * ux[s]) + bb * ux[s];
+                        gy[s] += a * (ey - cs * uy[s]) + bb * uy[s];
+                        gz[s] += a * (ez - cs * uz[s]) + bb * uz[s];
+                    } else {
+                        gx[s] += a * (ex - cs * ux[s]);
+                        gy[s] += a * (ey - cs * uy[s]);
+                        gz[s] += a * (ez - cs * uz[s]);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Quad site pass: four lanes per atom, lane q owning bonds q, q + 4, ....  The
 // arithmetic is the one of tersoff_site, distributed over the quad: each lane
 // forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
@@ -542,46 +593,24 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     if (q == 0 && kc > 0) U[i] = 0.5 * u_i;
     if (q == 0 && valid && !ovf && kc == 0) U[i] = 0.0;
 
-    // partials dU_i/dr_c
+    // partials dU_i/dr_c.  The term in f_C'(r_c) vanishes for bonds below
+    // R; a wave none of whose bonds is in the taper skips it (a uniform
+    // branch, so only one body is issued).
     T gx[SLOTS], gy[SLOTS], gz[SLOTS];
+    bool taper = false;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         gx[s] = T(0.5) * pd[s] * ux[s];
         gy[s] = T(0.5) * pd[s] * uy[s];
         gz[s] = T(0.5) * pd[s] * uz[s];
+        taper = taper || dfc[s] != T(0);
     }
-#pragma unroll
-    for (int t = 0; t < SLOTS; ++t) {
-        if (t >= tmax) break;   // wave-uniform
-#pragma unroll
-        for (int k = 0; k < kQuad; ++k) {
-            const T ex = k ? quad_xor(ux[t], k) : ux[t];
-            const T ey = k ? quad_xor(uy[t], k) : uy[t];
-            const T ez = k ? quad_xor(uz[t], k) : uz[t];
-            const T ef = k ? quad_xor(fc[t], k) : fc[t];
-            const T ep = k ? quad_xor(zp[t], k) : zp[t];
-            const int e = (q ^ k) + kQuad * t;
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const int c = q + kQuad * s;
-                if (c < kc && e < kc && e != c) {
-                    const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
-                    T g, dg;
-                    if (s == 0 && t == 0) {
-                        g = g0[k];
-                        dg = dg0[k];
-                    } else {
-                        angular_g(pc, cs, g, dg);
-                    }
-                    const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
-                    const T bb = T(-0.5) * ep * dfc[s] * g;
-                    gx[s] += a * (ex - cs * ux[s]) + bb * ux[s];
-                    gy[s] += a * (ey - cs * uy[s]) + bb * uy[s];
-                    gz[s] += a * (ez - cs * uz[s]) + bb * uz[s];
-                }
-            }
-        }
-    }
+    if (__any(taper))
+        tersoff_partner_terms<T, SLOTS, true>(pc, q, kc, tmax, ux, uy, uz, ir, fc, dfc, zp, g0, dg0,
+                                              gx, gy, gz);
+    else
+        tersoff_partner_terms<T, SLOTS, false>(pc, q, kc, tmax, ux, uy, uz, ir, fc, dfc, zp, g0,
+                                               dg0, gx, gy, gz);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
