@@ -17,9 +17,14 @@ bracketed by device synchronisation.
 Also measured, as extra fields of the same line:
   mixed    the same input with FP32 bond-order/force arithmetic, --mixed-steps
            steps: throughput, max |dF| and per-atom energy error against the
-           oracle at step 0 and against the FP64 path on the mixed
-           trajectory every --mixed-check steps, total-energy drift of both
-           paths (eV/atom/ps, linear fit)
+           FP64 path at step 0 and on the mixed trajectory every
+           --mixed-check steps, total-energy drift of both paths
+           (eV/atom/ps, linear fit)
+  npt      the same input under Berendsen weak coupling (300 K, 0 Pa), both
+           precisions
+  sic_512k Tersoff's multicomponent form on 512,000-atom zincblende SiC
+  green_kubo  heat-current autocorrelation and running conductivity of an
+           8,000-atom NVE run, and the correlation kernel at 10^6 samples
   repeats  further timed FP64 runs: median/min/max and whether the outputs
            (x, v, F, W, J, thermo) are the same bits every time
   sw_1m    Stillinger-Weber (1985) Si, 50x50x50 cells = 1,000,000 atoms, FP64
