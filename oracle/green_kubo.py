@@ -38,6 +38,20 @@ def hcacf(J, max_lag: int):
     return C
 
 
+def hcacf_lags(J, lags):
+    """C[k, a] for the listed lags only (the same per-lag dot products as
+    hcacf, for sampling long series)."""
+    J = np.asarray(J, dtype=np.float64)
+    S = J.shape[0]
+    out = np.zeros((len(lags), J.shape[1]))
+    for r, k in enumerate(lags):
+        if not 0 <= k < S:
+            raise ValueError("lag out of range")
+        for a in range(J.shape[1]):
+            out[r, a] = np.dot(J[:S - k, a], J[k:, a]) / (S - k)
+    return out
+
+
 def running_kappa(C, dtau_fs: float, volume_A3: float, T_K: float):
     """Trapezoid running integral of the HCACF scaled to W/(m K); row K is
     the integral up to lag K (row 0 is zero)."""

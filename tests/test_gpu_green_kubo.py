@@ -94,3 +94,22 @@ def test_green_kubo_errors():
         out = ctx.green_kubo(th, 3, 4, 1.0, 1.0, 300.0, kappa=False)
         torch.cuda.synchronize()
         assert "kappa" not in out and torch.equal(out["hac"], torch.zeros_like(out["hac"]))
+
+
+def test_green_kubo_full_size_sampled_lags():
+    """The correlator at the size the bench times (10^6 samples, 10^4 lags):
+    sampled lags against the oracle's per-lag dot products."""
+    import torch
+    from oracle import green_kubo as gk
+    S, K = 1_000_000, 10_000
+    rng = np.random.default_rng(1005)
+    th = rng.normal(size=(S, 16))
+    with context("tersoff") as ctx:
+        out = ctx.green_kubo(torch.tensor(th, device="cuda:0"), 1, K, 1.0, 1.0, 300.0,
+                             kappa=False)
+        torch.cuda.synchronize()
+        hac = out["hac"].cpu().numpy()
+    lags = [0, 1, 63, 64, 65, 1023, 1024, 5000, K - 1]
+    ref = gk.hcacf_lags(th[:, 11:14], lags)
+    scale = np.max(np.abs(ref), axis=0)
+    assert np.all(np.max(np.abs(hac[lags] - ref), axis=0) <= TOL * scale)

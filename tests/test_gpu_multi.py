@@ -231,3 +231,16 @@ def test_multi_errors():
         with pytest.raises(mb.MbmdError) as e:
             ctx.compute(to_dev(s.pos), s.box, types=_types(s))
         assert e.value.code == mb.MBMD_EINVAL
+
+
+def test_multi_full_size_sic_512k():
+    """Every atom of the 512,000-atom zincblende SiC input the bench times
+    (seed 1006, a = 4.32 A, list capacity 32) against the oracle, FP64."""
+    s = wl.binary_crystal(40, seed=1006, a=4.32, sigma=0.05, masses=(wl.M_SI, wl.M_C))
+    ref = _oracle(s, [SI, C], CHI_SIC, 32)
+    with multi_context([SI, C], CHI_SIC, 32) as ctx:
+        got = _gpu(ctx, s)
+    errs = {k: rel(got[k], ref[k]) for k in ("U", "F", "W", "J")}
+    print("sic 512k", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL_FP64, (k, v)

@@ -198,3 +198,20 @@ def test_npt_errors():
                           rebuild_every=2, **OFF)
         torch.cuda.synchronize()
         assert np.array_equal(out["box"], s2.box)
+
+
+def test_npt_without_coupling_equals_nve_full_size():
+    """The 512,000-atom input the bench times: with both couplings off, 25
+    NPT steps equal 25 NVE steps bit for bit (rebuild every 20)."""
+    import torch
+    s = wl.tersoff_512k()
+    with context("tersoff") as ctx:
+        ctx.set_rebuild_policy("fixed")
+        p1, v1 = to_dev(s.pos), to_dev(s.vel)
+        a = ctx.nve_run(p1, v1, s.box, wl.M_SI, 1.0, 25, rebuild_every=20)
+        p2, v2 = to_dev(s.pos), to_dev(s.vel)
+        b = ctx.npt_run(p2, v2, s.box, wl.M_SI, 1.0, 25, rebuild_every=20, **OFF)
+        torch.cuda.synchronize()
+        assert torch.equal(p1, p2) and torch.equal(v1, v2)
+        for key in ("U", "F", "W", "J", "thermo"):
+            assert torch.equal(a[key], b[key]), key

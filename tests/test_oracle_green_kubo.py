@@ -85,3 +85,13 @@ def test_samples_from_thermo_and_argument_checks():
         gk.hcacf(np.zeros((5, 3)), 0)
     with pytest.raises(ValueError):
         gk.running_kappa(np.zeros((5, 3)), 1.0, 1.0, 0.0)
+
+
+def test_hcacf_lags_equals_hcacf():
+    rng = np.random.default_rng(5)
+    J = rng.normal(size=(3000, 3))
+    full = gk.hcacf(J, 3000)
+    lags = [0, 1, 17, 1024, 2999]
+    assert np.array_equal(gk.hcacf_lags(J, lags), full[lags])
+    with pytest.raises(ValueError):
+        gk.hcacf_lags(J, [3000])
