@@ -162,7 +162,8 @@ class Context:
         self._ws = None
 
     def close(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.mbmd_destroy(self._h)
             self._h = None
 
