@@ -480,14 +480,38 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
                     int* __restrict__ ovf_list)
 {
     __shared__ TersoffLds<T> L;
+    __shared__ int order[MULTI ? kQuadAtoms : 1];
     const int q = threadIdx.x & (kQuad - 1);
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
     if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
-    if constexpr (MULTI) fill_lds_table(K, L);
+    const int first = (lb - g.blk_quad) * kQuadAtoms;
+    int a = threadIdx.x >> 2;
+    if constexpr (MULTI) {
+        // The block's atoms are taken in the order of a stable partition by
+        // type, so that the waves of an element with few bonds (C in SiC)
+        // do not run the partner-slot loops sized for one with many.  Wave
+        // 0 (threads 0-63, one per atom) ranks the keys; atoms past the
+        // segment's end sort last.
+        if (threadIdx.x < kQuadAtoms) {
+            const int loc = first + (int)threadIdx.x;
+            const int key =
+                loc < g.n ? min(max((int)xw[g.atom_off + loc].w, 0), kMaxTypes - 1) : kMaxTypes;
+            const unsigned long long below = (1ull << threadIdx.x) - 1ull;
+            int rank = 0;
+#pragma unroll
+            for (int t = 0; t <= kMaxTypes; ++t) {
+                const unsigned long long m = __ballot(key == t);
+                rank += t < key ? __popcll(m) : (t == key ? __popcll(m & below) : 0);
+            }
+            order[rank] = (int)threadIdx.x;
+        }
+        fill_lds_table(K, L);   // its barrier also publishes the order
+        a = order[a];
+    }
     const Box box = g.box;
-    const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
+    const int local = first + a;
     const int64_t i = g.atom_off + local;
     const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
