@@ -197,11 +197,15 @@ mbmd_status mbmd_bind_workspace(mbmd_ctx *ctx, void *dev_ptr, size_t bytes);
  * for atom i iff j != i and the minimum-image squared distance, evaluated in
  * FP64 as (dx*dx + dy*dy) + dz*dz with d <- d - L rint(d/L) and no fused
  * multiply-add, is below (cutoff + skin)^2 (the Verlet list over a cell list
- * of Section 2.1).  Each list holds the neighbours inside the potential
- * cutoff first, then the others, each group by ascending atom index: a
- * deterministic order, so every per-atom sum over the list is reproducible. */
+ * of Section 2.1).  The cutoff is the pair's: SW's a*sigma, Tersoff's S, and
+ * under a multi-element Tersoff potential S_ab = sqrt(S_a S_b) for types a
+ * and b (device types[n] as in mbmd_compute, or NULL for type 0 everywhere;
+ * one element ignores them); the run and compute calls build the same
+ * lists.  Each list holds the neighbours inside the pair's cutoff first,
+ * then the others, each group by ascending atom index: a deterministic
+ * order, so every per-atom sum over the list is reproducible. */
 mbmd_status mbmd_neighbors(mbmd_ctx *ctx, int64_t n, const double box[3], const double *pos,
-                           int32_t *nn, int32_t *nl);
+                           const int32_t *types, int32_t *nn, int32_t *nl);
 
 /* Single point (the force-evaluation kernel of Section 2.3 with the
  * bond-order precompute for Tersoff): per-atom energy U[n], force F[3][n],

@@ -49,6 +49,8 @@ def _load():
         P = C.c_void_p
         lib.ora_neighbors_brute.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_int, _ip, _ip]
         lib.ora_neighbors_cells.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_int, _ip, _ip]
+        lib.ora_neighbors_brute_typed.argtypes = [C.c_long, _dp, _dp, _ip, C.c_int, _dp, C.c_int,
+                                                  _ip, _ip]
         for name, st in (("ora_tersoff", _Tersoff), ("ora_sw", _SW)):
             fn = getattr(lib, name)
             fn.argtypes = [C.c_long, _dp, _dp, P, _ip, _ip, C.c_int, C.POINTER(st),
@@ -110,6 +112,29 @@ def neighbors(pos, box, rlist: float, maxnb: int, method: str = "cells", allow_o
     fn = lib.ora_neighbors_brute if method == "brute" else lib.ora_neighbors_cells
     st = fn(n, _f64(box), pos, float(rlist), int(maxnb), nn, nl)
     if st and not (allow_overflow and st == ENEIGH):
+        raise OracleError(st)
+    return nn, nl[:n]
+
+
+def neighbors_typed(pos, box, types, rpair, maxnb: int):
+    """Sorted neighbour lists with a radius per pair of types (rpair (nt, nt),
+    symmetric): j is listed for i iff r_ij < rpair[t_i, t_j].  Brute force.
+    Returns (nn (N,), nl (N, maxnb), padded with -1)."""
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    rp = np.ascontiguousarray(rpair, dtype=np.float64)
+    nt = rp.shape[0]
+    if rp.shape != (nt, nt) or not np.array_equal(rp, rp.T):
+        raise ValueError("rpair must be a symmetric (nt, nt) array")
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    if t.shape != (n,):
+        raise ValueError("one type per atom")
+    nn = np.zeros(n, dtype=np.int32)
+    nl = np.full((max(n, 1), maxnb), -1, dtype=np.int32)
+    st = lib.ora_neighbors_brute_typed(n, _f64(box), pos, t if n else np.zeros(1, np.int32), nt,
+                                       rp.reshape(-1), int(maxnb), nn, nl)
+    if st:
         raise OracleError(st)
     return nn, nl[:n]
 

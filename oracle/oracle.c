@@ -139,6 +139,43 @@ int ora_neighbors_brute(long n, const double *box, const double *pos, double rli
     return overflow ? ORA_ENEIGH : ORA_OK;
 }
 
+/* Neighbour list by definition with a radius per pair of atom types (the
+ * multi-element Tersoff form, whose cutoff depends on the pair): atom j is
+ * listed for atom i iff r_ij^2 < rpair[t_i * nt + t_j]^2.  All pairs,
+ * O(N^2); overflow as in ora_neighbors_brute. */
+int ora_neighbors_brute_typed(long n, const double *box, const double *pos, const int *types,
+                              int nt, const double *rpair, int maxnb, int *nn, int *nl)
+{
+    if (nt < 1) return ORA_EINVAL;
+    double rmax = 0.0;
+    for (int k = 0; k < nt * nt; ++k) {
+        if (!(rpair[k] > 0.0)) return ORA_EINVAL;
+        if (rpair[k] > rmax) rmax = rpair[k];
+    }
+    for (long i = 0; i < n; ++i)
+        if (types[i] < 0 || types[i] >= nt) return ORA_EINVAL;
+    int st = check_box(box, rmax);
+    if (st) return st;
+    int overflow = 0;
+    for (long i = 0; i < n; ++i) {
+        int cnt = 0;
+        for (long j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(box, &pos[i * 3], &pos[j * 3], d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double rl = rpair[types[i] * nt + types[j]];
+            if (r2 < rl * rl) {
+                if (cnt < maxnb) nl[i * maxnb + cnt] = (int)j;
+                ++cnt;
+            }
+        }
+        nn[i] = cnt;
+        if (cnt > maxnb) overflow = 1;
+    }
+    return overflow ? ORA_ENEIGH : ORA_OK;
+}
+
 /* Neighbour list through a linked cell list (cells of side >= r_list). */
 int ora_neighbors_cells(long n, const double *box, const double *pos, double rlist,
                         int maxnb, int *nn, int *nl)

@@ -83,7 +83,7 @@ def _load():
         "mbmd_get_profile": ([P, C.POINTER(mbmd_kernel_time), I, C.POINTER(I)], I),
         "mbmd_workspace_size": ([P, I64, C.POINTER(C.c_size_t)], I),
         "mbmd_bind_workspace": ([P, P, C.c_size_t], I),
-        "mbmd_neighbors": ([P, I64, P, P, P, P], I),
+        "mbmd_neighbors": ([P, I64, P, P, P, P, P], I),
         "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
         "mbmd_npt_run": ([P, I, I64, P, D, P, P, P, D, I, I, C.POINTER(mbmd_berendsen), P, P,
@@ -269,12 +269,13 @@ class Context:
         self._ws = buf
 
     # -- calls --------------------------------------------------------------
-    def neighbors(self, pos: torch.Tensor, box):
+    def neighbors(self, pos: torch.Tensor, box, types=None):
         n = pos.shape[1]
         M = self.max_neighbors
         nn = torch.zeros(n, dtype=torch.int32, device=self.device)
         nl = torch.full((M, n), -1, dtype=torch.int32, device=self.device)
         self._check(_lib.mbmd_neighbors(self._h, n, _box(box), _dptr(pos, (3, n), "pos"),
+                                        _dptr(types, (n,), "types", torch.int32),
                                         _dptr(nn, (n,), "nn", torch.int32),
                                         _dptr(nl, (M, n), "nl", torch.int32)),
                     "mbmd_neighbors")

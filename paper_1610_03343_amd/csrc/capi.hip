@@ -169,6 +169,25 @@ double cutoff_of(const mbmd_ctx* c)
 // Atom types the current potential knows (SW: one).
 int ntypes_of(const mbmd_ctx* c) { return c->potential == 0 ? c->ttab.nt : 1; }
 
+// Per-pair list radii of a multi-element Tersoff potential: pair (a, b)
+// lists atoms within S_ab + skin, S_ab = sqrt(S_a S_b) the pair's cutoff
+// (the mixing rule of the multicomponent form), and orders those within
+// S_ab first.  False (one radius for every pair) for one element and SW.
+bool list_radii(const mbmd_ctx* c, ListRadii& r)
+{
+    if (c->potential != 0 || c->ttab.nt < 2) return false;
+    r = ListRadii{};
+    r.nt = c->ttab.nt;
+    for (int a = 0; a < r.nt; ++a)
+        for (int b = 0; b < r.nt; ++b) {
+            const double S = std::sqrt(c->ttab.elem[a].S * c->ttab.elem[b].S);
+            const double rl = S + c->skin;
+            r.rl2[a * kMaxTypes + b] = rl * rl;
+            r.rc2[a * kMaxTypes + b] = S * S;
+        }
+    return true;
+}
+
 // Per-type integrator factors from the context's type masses.
 void apply_type_masses(const mbmd_ctx* c, double dt, Seg& g)
 {
@@ -403,8 +422,10 @@ hipError_t build(mbmd_ctx* c, int total_cells, int cur, bool readback = true)
     hipError_t e;
     {
         ProfScope ps(c, P_BUILD);
+        ListRadii r;
+        const bool typed = list_radii(c, r);
         e = launch_build_neighbors(c->buf, c->segs, total_cells, cur, cutoff_of(c) + c->skin,
-                                   cutoff_of(c), c->stream);
+                                   cutoff_of(c), typed ? &r : nullptr, c->stream);
     }
     c->max_nn = kMaxSlots;
     c->nn_pending = false;
@@ -1151,7 +1172,7 @@ mbmd_status mbmd_bind_workspace(mbmd_ctx* c, void* dev_ptr, size_t bytes)
 }
 
 mbmd_status mbmd_neighbors(mbmd_ctx* c, int64_t n, const double box[3], const double* pos,
-                           int32_t* nn, int32_t* nl)
+                           const int32_t* types, int32_t* nn, int32_t* nl)
 {
     if (!c) return MBMD_EINVAL;
     Box b{};
@@ -1160,7 +1181,7 @@ mbmd_status mbmd_neighbors(mbmd_ctx* c, int64_t n, const double box[3], const do
     if (n == 0) return MBMD_OK;
     if (!pos || !nn || !nl) return fail(c, MBMD_EINVAL, "null device pointer%s");
     int cells = 0;
-    s = begin_single(c, n, b, pos, nullptr, 0, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr,
+    s = begin_single(c, n, b, pos, types, 0, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr,
                      nullptr, &cells);
     if (s != MBMD_OK) return s;
     hipError_t e = build(c, cells, 0);

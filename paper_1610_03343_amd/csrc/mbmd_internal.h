@@ -228,8 +228,21 @@ hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, do
 // Builds the lists and reverse slots of every segment with build != 0 and
 // the largest count of each (maxnn).  Lists hold the neighbours inside rcut
 // at build time first, each group by ascending index.
+// Per-type-pair radii of a list build: pair (a, b) at index a * kMaxTypes + b
+// lists atoms closer than sqrt(rl2) and orders those closer than sqrt(rc2)
+// first.  The cell grid is sized for the largest radius.
+struct ListRadii {
+    int nt;
+    double rl2[kMaxTypes * kMaxTypes];
+    double rc2[kMaxTypes * kMaxTypes];
+};
+
+// rlist, rcut: the one radius and cutoff of every pair; `typed` (or null)
+// replaces them by per-pair values read with the types in the positions' w
+// lanes (rlist must then be the largest list radius).
 hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
-                                  double rlist, double rcut, hipStream_t s);
+                                  double rlist, double rcut, const ListRadii* typed,
+                                  hipStream_t s);
 
 // overflow_pass = false: the fast four-lanes-per-atom pass over every atom;
 // true: the pass over the atoms the first one left over.  max_nn bounds the

@@ -264,15 +264,28 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // the pairwise pass can stop at the last in-cutoff slot.  The grouping only
 // steers work (every step recomputes which slots are in the cutoff); the
 // order is a deterministic function of the positions.
+// TYPED: the radii of each pair come from R (copied to LDS), indexed by the
+// types in the w lanes, and the stencil is pruned with the largest radius of
+// atom i's type.
+template <bool TYPED>
 __global__ void __launch_bounds__(kSearchBlock)
 k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, double rl2_hi,
-         double rc2, int M,
+         double rc2, ListRadii R, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
          const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
          int* __restrict__ rev, int* __restrict__ maxnn, unsigned* __restrict__ status)
 {
     extern __shared__ int lbuf[];
     __shared__ int lds_max[kSearchBlock / 64];
+    __shared__ double t_rl2[TYPED ? kMaxTypes * kMaxTypes : 1];
+    __shared__ double t_rc2[TYPED ? kMaxTypes * kMaxTypes : 1];
+    if constexpr (TYPED) {
+        if (threadIdx.x < kMaxTypes * kMaxTypes) {
+            t_rl2[threadIdx.x] = R.rl2[threadIdx.x];
+            t_rc2[threadIdx.x] = R.rc2[threadIdx.x];
+        }
+        __syncthreads();
+    }
     const int lb2 = xcd_block(blockIdx.x, gridDim.x);
     const int lb = lb2 >> 1;
     const int sid = seg_of_block(S, lb, false);
@@ -283,6 +296,12 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
     if (local < g.n && g.build) {
         int* buf = lbuf + threadIdx.x;
         const double4 xi = xw[i];
+        const int ti = TYPED ? min(max((int)xi.w, 0), R.nt - 1) : 0;
+        double rl2_i = rl2;   // largest list radius squared of i's pairs
+        if constexpr (TYPED) {
+            rl2_i = t_rl2[ti * kMaxTypes];
+            for (int b = 1; b < R.nt; ++b) rl2_i = fmax(rl2_i, t_rl2[ti * kMaxTypes + b]);
+        }
         const int c = cell_of[i] - g.cell_off;
         const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
         // The stencil cells to visit, as bits k = 9 (oz + 1) + 3 (oy + 1) +
@@ -311,7 +330,7 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
                 gap2[a][1] = 0.0f;
                 gap2[a][2] = (float)((1.0 - f) * (1.0 - f) * side * side);
             }
-            const float skip2 = prune ? (float)(rl2 * (1.0 + 1e-5)) : 3.0e38f;
+            const float skip2 = prune ? (float)(rl2_i * (1.0 + 1e-5)) : 3.0e38f;
             for (int oz = lo[2]; oz <= hi[2]; ++oz)
                 for (int oy = lo[1]; oy <= hi[1]; ++oy)
                     for (int ox = lo[0]; ox <= hi[0]; ++ox)
@@ -331,9 +350,18 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
                 const int j = cell_atoms[p];
                 if (j == (int)i) continue;
                 double r2;
-                if (in_list(xi, xw[j], g.box, rl2, rl2_lo, rl2_hi, r2)) {
+                const double4 xj = xw[j];
+                double pl2 = rl2, pl2_lo = rl2_lo, pl2_hi = rl2_hi, pc2 = rc2;
+                if constexpr (TYPED) {
+                    const int p = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
+                    pl2 = t_rl2[p];
+                    pl2_lo = pl2 * (1.0 - 1e-10);
+                    pl2_hi = pl2 * (1.0 + 1e-10);
+                    pc2 = t_rc2[p];
+                }
+                if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
                     // insertion into the LDS list (capacity M) ordered by key
-                    const unsigned key = (unsigned)j | (r2 < rc2 ? 0u : 0x80000000u);
+                    const unsigned key = (unsigned)j | (r2 < pc2 ? 0u : 0x80000000u);
                     int q = cnt < M ? cnt : M;
                     while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
                         if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
@@ -408,7 +436,8 @@ k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M,
 }
 
 hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cells, int cur,
-                                  double rlist, double rcut, hipStream_t s)
+                                  double rlist, double rcut, const ListRadii* typed,
+                                  hipStream_t s)
 {
     if (S.nblk <= 0) return hipSuccess;
     if (!S.seg || S.nseg > b.seg_cap || total_cells > b.cell_cap) return hipErrorInvalidValue;
@@ -427,11 +456,17 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.cell_of, b.cell_start, b.cell_fill, b.cell_atoms);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
-    k_search<<<2 * S.nblk, kSearchBlock, lds, s>>>(S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10),
-                                                   rl2 * (1.0 + 1e-10), rcut * rcut, b.M, b.cap,
-                                                   b.cell_of,
-                                                   b.cell_start, b.cell_atoms, b.nn, b.nl,
-                                                   b.rev, b.maxnn, b.status);
+    if (typed && (typed->nt < 1 || typed->nt > kMaxTypes)) return hipErrorInvalidValue;
+    if (typed && typed->nt > 1)
+        k_search<true><<<2 * S.nblk, kSearchBlock, lds, s>>>(
+            S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut, *typed,
+            b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn,
+            b.status);
+    else
+        k_search<false><<<2 * S.nblk, kSearchBlock, lds, s>>>(
+            S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut,
+            ListRadii{}, b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev,
+            b.maxnn, b.status);
     k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
 }

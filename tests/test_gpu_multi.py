@@ -161,14 +161,20 @@ def test_multi_nve_trajectory_with_type_masses(name, steps):
     masses = np.array(tm)[s.types]
     par = dict(elems=elems, chi=np.array(chi), types=s.types)
     run = lambda p, v: oracle.nve("tersoff_multi", par, p, v, s.box, 0.0, steps, 1.0,
-                                  rlist(elems), 10, M, check_skin=False, masses=masses)
+                                  rlist(elems), 10, M, check_skin=True, masses=masses)
     ref, tol = _chaos(run, s)
+    # These disordered starts move atoms up to 0.85 A in ten steps, beyond
+    # any list's skin, so both sides rebuild early once an atom has moved
+    # more than skin/2 (the library's default policy, the oracle's
+    # check_skin); with every list complete the trajectory does not depend
+    # on when each side rebuilds.
     with multi_context(elems, chi, M) as ctx:
-        ctx.set_rebuild_policy("fixed")
         ctx.set_type_masses(tm)
         pos, vel = to_dev(s.pos), to_dev(s.vel)
         out = ctx.nve_run(pos, vel, s.box, 0.0, 1.0, steps, rebuild_every=10, types=_types(s))
         torch.cuda.synchronize()
+        st = ctx.run_stats()
+        assert 0.0 <= st["max_displacement"] <= SKIN / 2, st
         gp, gv, th = pos.cpu().numpy().T, vel.cpu().numpy().T, out["thermo"].cpu().numpy()
     print(f"{name}: tolerances x {tol['x']:.2e} A, v {tol['v']:.2e} A/fs")
     assert rel(th[0], ref["thermo"][0]) <= 1e-12
@@ -185,13 +191,15 @@ def test_multi_npt_trajectory_with_type_masses():
     par = dict(elems=elems, chi=np.array(chi), types=s.types)
     k = dict(T0=600.0, tau_T=20.0, P0_GPa=0.0, tau_P=50.0, beta_per_GPa=0.005)
     run = lambda p, v: oracle.npt("tersoff_multi", par, p, v, s.box, 0.0, 60, 1.0, rlist(elems),
-                                  10, M, k["T0"], k["tau_T"], k["P0_GPa"], k["tau_P"],
+                                  1, M, k["T0"], k["tau_T"], k["P0_GPa"], k["tau_P"],
                                   k["beta_per_GPa"], masses=masses)
     ref, tol = _chaos(run, s)
+    # NPT rebuilds on its schedule only: every step on both sides, since this
+    # disordered start moves atoms ~0.1 A per step
     with multi_context(elems, chi, M) as ctx:
         ctx.set_type_masses(tm)
         pos, vel = to_dev(s.pos), to_dev(s.vel)
-        out = ctx.npt_run(pos, vel, s.box, 0.0, 1.0, 60, rebuild_every=10, types=_types(s), **k)
+        out = ctx.npt_run(pos, vel, s.box, 0.0, 1.0, 60, rebuild_every=1, types=_types(s), **k)
         torch.cuda.synchronize()
         gp, gv = pos.cpu().numpy().T, vel.cpu().numpy().T
         bt = out["box_traj"].cpu().numpy()
@@ -199,6 +207,49 @@ def test_multi_npt_trajectory_with_type_masses():
                                                        10 * tol["x"])
     assert np.max(np.abs(min_image(gp - ref["pos"], ref["box"]))) <= tol["x"]
     assert np.max(np.abs(gv - ref["vel"])) <= tol["v"]
+
+
+def _pair_cutoffs(elems):
+    return np.array([[np.sqrt(a["S"] * b["S"]) for b in elems] for a in elems])
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_typed_neighbor_lists_bitexact(name):
+    """Per-pair list radii S_ab + skin: the GPU lists against the oracle's
+    brute-force typed lists as exact index sets, ordered as stated (pairs
+    inside their own cutoff S_ab first, then the others, each by index)."""
+    import oracle
+    s, elems, chi, M = SYSTEMS[name]
+    S = _pair_cutoffs(elems)
+    with multi_context(elems, chi, M) as ctx:
+        nn, nl = ctx.neighbors(to_dev(s.pos), s.box, types=_types(s))
+        torch.cuda.synchronize()
+        nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
+    onn, onl = oracle.neighbors_typed(s.pos, s.box, s.types, S + SKIN, M)
+    assert np.array_equal(nn, onn)
+    for i in range(s.n):
+        got = nl[:nn[i], i]
+        assert np.array_equal(np.sort(got), onl[i, :onn[i]]), i
+        d = min_image(s.pos[got] - s.pos[i], s.box)
+        inside = np.sum(d * d, axis=1) < S[s.types[i], s.types[got]] ** 2
+        k = int(inside.sum())
+        assert inside[:k].all() and not inside[k:].any(), i
+        assert np.all(np.diff(got[:k]) > 0) and np.all(np.diff(got[k:]) > 0), i
+
+
+def test_typed_lists_without_types_use_the_first_pair():
+    """types = NULL under a multi-element potential: every atom is type 0, so
+    every list has the radius S_00 + skin."""
+    import oracle
+    s, elems, chi, M = SYSTEMS["sic_alloy"]
+    with multi_context(elems, chi, M) as ctx:
+        nn, nl = ctx.neighbors(to_dev(s.pos), s.box)
+        torch.cuda.synchronize()
+        nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
+    onn, onl = oracle.neighbors(s.pos, s.box, elems[0]["S"] + SKIN, M, method="brute")
+    assert np.array_equal(nn, onn)
+    for i in range(s.n):
+        assert np.array_equal(np.sort(nl[:nn[i], i]), onl[i, :onn[i]]), i
 
 
 def test_multi_errors():
@@ -244,3 +295,30 @@ def test_multi_full_size_sic_512k():
     print("sic 512k", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= TOL_FP64, (k, v)
+
+
+def test_sic_512k_fixed_schedule_misses_no_pair():
+    """The benchmark's schedule on its 512,000-atom SiC input (lists rebuilt
+    every 20 steps, per-pair radii S_ab + 0.5 A, no displacement check):
+    60 NVE steps agree with the run that rebuilds before every step, whose
+    lists are complete at every step.  A pair missed for even one step
+    changes forces by far more than the rounding-level differences that
+    the two list orders leave."""
+    s = wl.binary_crystal(40, seed=1006, a=4.32, sigma=0.05, masses=(wl.M_SI, wl.M_C))
+    res = {}
+    for every in (20, 1):
+        with multi_context([SI, C], CHI_SIC, 32) as ctx:
+            ctx.set_rebuild_policy("fixed")
+            ctx.set_type_masses([wl.M_SI, wl.M_C])
+            pos, vel = to_dev(s.pos), to_dev(s.vel)
+            out = ctx.nve_run(pos, vel, s.box, 0.0, 1.0, 60, rebuild_every=every,
+                              types=_types(s))
+            torch.cuda.synchronize()
+            res[every] = (pos.cpu().numpy().T, vel.cpu().numpy().T,
+                          out["thermo"].cpu().numpy())
+    dx = np.max(np.abs(min_image(res[20][0] - res[1][0], s.box)))
+    dv = np.max(np.abs(res[20][1] - res[1][1]))
+    de = np.max(np.abs(res[20][2][:, 14] - res[1][2][:, 14])) / s.n
+    print(f"sic 512k, fixed 20 vs every step: dx {dx:.2e} A, dv {dv:.2e} A/fs, "
+          f"dE {de:.2e} eV/atom")
+    assert dx <= 1e-9 and dv <= 1e-10 and de <= 1e-12, (dx, dv, de)

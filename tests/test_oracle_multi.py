@@ -296,3 +296,45 @@ def test_trimer_closed_form_pair_selection(oracle_mod):
     ref = np.array([float(ui), float(uj), float(uk)])
     assert np.max(np.abs(o["U"] - ref)) < 1e-12 * np.max(np.abs(ref))
     assert float(zij) > 0 and float(fc(psc, rik)) == 0.0
+
+
+def pair_radii(elems, skin=0.5):
+    """List radius of each type pair: the pair's cutoff sqrt(S_a S_b) (the
+    mixing rule of the multicomponent form) plus the skin."""
+    return np.array([[math.sqrt(a["S"] * b["S"]) + skin for b in elems] for a in elems])
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_typed_lists_match_a_periodic_kd_tree(oracle_mod, name):
+    """The oracle's per-pair-radius lists against scipy's periodic k-d tree:
+    every pair within the largest radius, kept when closer than its own
+    pair's radius; and the same lists as the one-radius brute force when
+    every pair gets the largest radius."""
+    from scipy.spatial import cKDTree
+    s, elems, _chi, _rl = SYSTEMS[name]
+    rp = pair_radii(elems)
+    nn, nl = oracle_mod.neighbors_typed(s.pos, s.box, s.types, rp, 48)
+    pos = np.mod(s.pos, s.box)
+    tree = cKDTree(pos, boxsize=s.box)
+    dm = tree.sparse_distance_matrix(tree, rp.max(), output_type="ndarray")
+    i, j, r = dm["i"], dm["j"], dm["v"]
+    keep = (i != j) & (r < rp[s.types[i], s.types[j]])
+    want = [np.sort(j[keep & (i == a)]) for a in range(s.n)]
+    for a in range(s.n):
+        assert np.array_equal(nl[a, :nn[a]], want[a]), a
+    if name in ("zincblende", "sic_alloy"):
+        # the radii change these lists (C-C pairs between 2.6 and 3.5 A)
+        assert sum(len(w) for w in want) < int(np.sum((i != j) & (r < rp.max())))
+    full = np.full_like(rp, rp.max())
+    nn1, nl1 = oracle_mod.neighbors_typed(s.pos, s.box, s.types, full, 48)
+    nn2, nl2 = oracle_mod.neighbors(s.pos, s.box, rp.max(), 48, method="brute")
+    assert np.array_equal(nn1, nn2) and np.array_equal(nl1, nl2)
+
+
+def test_typed_lists_reject_bad_input(oracle_mod):
+    s, elems, _chi, _rl = SYSTEMS["zincblende"]
+    rp = pair_radii(elems)
+    with pytest.raises(ValueError):
+        oracle_mod.neighbors_typed(s.pos, s.box, s.types, np.array([[3.0, 2.0], [2.5, 3.0]]), 48)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.neighbors_typed(s.pos, s.box, s.types + 1, rp, 48)
