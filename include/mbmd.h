@@ -199,8 +199,8 @@ mbmd_status mbmd_bind_workspace(mbmd_ctx *ctx, void *dev_ptr, size_t bytes);
  * multiply-add, is below (cutoff + skin)^2 (the Verlet list over a cell list
  * of Section 2.1).  The cutoff is the pair's: SW's a*sigma, Tersoff's S, and
  * under a multi-element Tersoff potential S_ab = sqrt(S_a S_b) for types a
- * and b (device types[n] as in mbmd_compute, or NULL for type 0 everywhere;
- * one element ignores them); the run and compute calls build the same
+ * and b (types as in every call taking them: NULL for type 0 everywhere,
+ * else each in [0, ntypes)); the run and compute calls build the same
  * lists.  Each list holds the neighbours inside the pair's cutoff first,
  * then the others, each group by ascending atom index: a deterministic
  * order, so every per-atom sum over the list is reproducible. */
