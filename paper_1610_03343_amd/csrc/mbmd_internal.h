@@ -13,6 +13,10 @@
 //                    so a neighbour gather is one 32-byte access; two buffers
 //                    because the drift writes while neighbours are still read
 //   xbuild[N]        double4 positions at the last list build
+//   xcell[N]         double4 positions in cell order at the last build
+//                    (xcell[p] = xw[cell_atoms[p]]), so the search's lanes,
+//                    which also take atoms in cell order, read neighbouring
+//                    cells' atoms from neighbouring addresses
 //   nn[N]            int32 list count (true count, may exceed M on overflow)
 //   nl[M][N]         int32 neighbour index, slot-major (lane i reads nl[m*N+i]
 //                    coalesced); neighbours inside the potential cutoff at
@@ -149,6 +153,7 @@ struct Buffers {
     int* cell_start;
     int* cell_fill;
     int* cell_atoms;
+    double4* xcell;          // [N] positions in cell order (cell_atoms order)
     int64_t cell_cap;
     double* part_b;          // [kThermoRing][block capacity][kPartialCols]
     int64_t blk_cap;         // 256-atom block capacity

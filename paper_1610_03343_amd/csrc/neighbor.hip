@@ -220,15 +220,17 @@ k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ b
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_cell_fill(Segs S, const int* __restrict__ cell_of, const int* __restrict__ start,
-            int* __restrict__ fill, int* __restrict__ cell_atoms)
+k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell_of,
+            const int* __restrict__ start, int* __restrict__ fill, int* __restrict__ cell_atoms,
+            double4* __restrict__ xcell)
 {
     int sid;
     int64_t i;
     if (!block_atom(S, sid, i)) return;
     const int c = cell_of[i];
-    const int slot = atomicAdd(&fill[c], 1);
-    cell_atoms[start[c] + slot] = (int)i;
+    const int p = start[c] + atomicAdd(&fill[c], 1);
+    cell_atoms[p] = (int)i;
+    xcell[p] = xw[i];
 }
 
 // ---- neighbour search -----------------------------------------------------
@@ -269,7 +271,7 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // atom i's type.
 template <bool TYPED>
 __global__ void __launch_bounds__(kSearchBlock)
-k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, double rl2_hi,
+k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, double rl2_hi,
          double rc2, ListRadii R, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
          const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
@@ -290,12 +292,16 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
     const int lb = lb2 >> 1;
     const int sid = seg_of_block(S, lb, false);
     const Seg& g = S.seg[sid];
+    // Thread k of the segment takes the k-th atom in cell order, so the
+    // lanes of a wave sit in a run of neighbouring cells along x and, at
+    // each stencil offset, read candidates from one stretch of xcell.
     const int local = (lb - g.blk) * kBlock + (lb2 & 1) * kSearchBlock + threadIdx.x;
-    const int64_t i = g.atom_off + local;
     int cnt = 0;
     if (local < g.n && g.build) {
+        const int p0 = start[g.cell_off] + local;
+        const int64_t i = cell_atoms[p0];
         int* buf = lbuf + threadIdx.x;
-        const double4 xi = xw[i];
+        const double4 xi = xcell[p0];
         const int ti = TYPED ? min(max((int)xi.w, 0), R.nt - 1) : 0;
         double rl2_i = rl2;   // largest list radius squared of i's pairs
         if constexpr (TYPED) {
@@ -337,9 +343,10 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
                         if (gap2[2][oz + 1] + gap2[1][oy + 1] + gap2[0][ox + 1] <= skip2)
                             visit |= 1u << (9 * (oz + 1) + 3 * (oy + 1) + (ox + 1));
         }
-        while (visit) {
-            const int k = __builtin_ctz(visit);
-            visit &= visit - 1;
+        // every lane walks the offsets in the same order (a pruned cell is
+        // a skipped iteration), which keeps the wave's reads together
+        for (int k = 0; k < 27; ++k) {
+            if (!((visit >> k) & 1u)) continue;
             const int oz = k / 9 - 1, oy = (k / 3) % 3 - 1, ox = k % 3 - 1;
             const int zz = (cz + oz + g.nc[2]) % g.nc[2];
             const int yy = (cy + oy + g.nc[1]) % g.nc[1];
@@ -350,14 +357,14 @@ k_search(Segs S, const double4* __restrict__ xw, double rl2, double rl2_lo, doub
                 const int j = cell_atoms[p];
                 if (j == (int)i) continue;
                 double r2;
-                const double4 xj = xw[j];
+                const double4 xj = xcell[p];
                 double pl2 = rl2, pl2_lo = rl2_lo, pl2_hi = rl2_hi, pc2 = rc2;
                 if constexpr (TYPED) {
-                    const int p = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
-                    pl2 = t_rl2[p];
+                    const int t = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
+                    pl2 = t_rl2[t];
                     pl2_lo = pl2 * (1.0 - 1e-10);
                     pl2_hi = pl2 * (1.0 + 1e-10);
-                    pc2 = t_rc2[p];
+                    pc2 = t_rc2[t];
                 }
                 if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
                     // insertion into the LDS list (capacity M) ordered by key
@@ -453,18 +460,19 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
     k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
                                           b.cell_fill);
-    k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.cell_of, b.cell_start, b.cell_fill, b.cell_atoms);
+    k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_start, b.cell_fill,
+                                          b.cell_atoms, b.xcell);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
     if (typed && (typed->nt < 1 || typed->nt > kMaxTypes)) return hipErrorInvalidValue;
     if (typed && typed->nt > 1)
         k_search<true><<<2 * S.nblk, kSearchBlock, lds, s>>>(
-            S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut, *typed,
+            S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut, *typed,
             b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn,
             b.status);
     else
         k_search<false><<<2 * S.nblk, kSearchBlock, lds, s>>>(
-            S, b.xw[cur], rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut,
+            S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut,
             ListRadii{}, b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev,
             b.maxnn, b.status);
     k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
