@@ -343,41 +343,71 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                         if (gap2[2][oz + 1] + gap2[1][oy + 1] + gap2[0][ox + 1] <= skip2)
                             visit |= 1u << (9 * (oz + 1) + 3 * (oy + 1) + (ox + 1));
         }
-        // every lane walks the offsets in the same order (a pruned cell is
-        // a skipped iteration), which keeps the wave's reads together
-        for (int k = 0; k < 27; ++k) {
-            if (!((visit >> k) & 1u)) continue;
-            const int oz = k / 9 - 1, oy = (k / 3) % 3 - 1, ox = k % 3 - 1;
-            const int zz = (cz + oz + g.nc[2]) % g.nc[2];
-            const int yy = (cy + oy + g.nc[1]) % g.nc[1];
-            const int xx = (cx + ox + g.nc[0]) % g.nc[0];
-            const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
-            const int e = start[cc + 1];
-            for (int p = start[cc]; p < e; ++p) {
-                const int j = cell_atoms[p];
-                if (j == (int)i) continue;
-                double r2;
-                const double4 xj = xcell[p];
-                double pl2 = rl2, pl2_lo = rl2_lo, pl2_hi = rl2_hi, pc2 = rc2;
-                if constexpr (TYPED) {
-                    const int t = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
-                    pl2 = t_rl2[t];
-                    pl2_lo = pl2 * (1.0 - 1e-10);
-                    pl2_hi = pl2 * (1.0 + 1e-10);
-                    pc2 = t_rc2[t];
-                }
-                if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
-                    // insertion into the LDS list (capacity M) ordered by key
-                    const unsigned key = (unsigned)j | (r2 < pc2 ? 0u : 0x80000000u);
-                    int q = cnt < M ? cnt : M;
-                    while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
-                        if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
-                        --q;
-                    }
-                    if (q < M) buf[q * kSearchBlock] = (int)key;
-                    ++cnt;
-                }
+        // Candidate j (cell-order slot p) against the list radius of the pair,
+        // inserted into the LDS list (capacity M) ordered by key.
+        auto consider = [&](int j, const double4& xj) {
+            if (j == (int)i) return;
+            double r2;
+            double pl2 = rl2, pl2_lo = rl2_lo, pl2_hi = rl2_hi, pc2 = rc2;
+            if constexpr (TYPED) {
+                const int t = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
+                pl2 = t_rl2[t];
+                pl2_lo = pl2 * (1.0 - 1e-10);
+                pl2_hi = pl2 * (1.0 + 1e-10);
+                pc2 = t_rc2[t];
             }
+            if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
+                const unsigned key = (unsigned)j | (r2 < pc2 ? 0u : 0x80000000u);
+                int q = cnt < M ? cnt : M;
+                while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
+                    if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
+                    --q;
+                }
+                if (q < M) buf[q * kSearchBlock] = (int)key;
+                ++cnt;
+            }
+        };
+        // First cell-order slot and end of the cell at stencil offset k
+        // (an empty range for a cell left out).
+        auto cell_range = [&](int k, int& b, int& e) {
+            b = e = 0;
+            if (k < 27 && ((visit >> k) & 1u)) {
+                const int oz = k / 9 - 1, oy = (k / 3) % 3 - 1, ox = k % 3 - 1;
+                // periodic wrap by one cell (no integer division per offset)
+                auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+                const int zz = wrap(cz + oz, g.nc[2]);
+                const int yy = wrap(cy + oy, g.nc[1]);
+                const int xx = wrap(cx + ox, g.nc[0]);
+                const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
+                b = start[cc];
+                e = start[cc + 1];
+            }
+        };
+        // Every lane walks the offsets in the same order (a pruned cell is an
+        // empty iteration), which keeps the wave's reads together; the next
+        // cell's range is fetched before the current cell is scanned, and the
+        // scan takes two candidates per iteration, so more loads are in
+        // flight per lane.
+        int b, e;
+        cell_range(0, b, e);
+        for (int k = 0; k < 27; ++k) {
+            int nb, ne;
+            cell_range(k + 1, nb, ne);
+            for (int p = b; p < e; p += 2) {
+                const bool two = p + 1 < e;
+                const int j0 = cell_atoms[p];
+                const double4 x0 = xcell[p];
+                int j1 = -1;
+                double4 x1 = x0;
+                if (two) {
+                    j1 = cell_atoms[p + 1];
+                    x1 = xcell[p + 1];
+                }
+                consider(j0, x0);
+                if (two) consider(j1, x1);
+            }
+            b = nb;
+            e = ne;
         }
         // On overflow the stored entries are the M smallest keys; the status
         // bit turns the call into an error.
