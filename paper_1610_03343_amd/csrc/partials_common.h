@@ -157,6 +157,10 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long msk, int c)
 // Cutoff mask of atom i computed by its quad: lane q tests slots q, q+4, ...
 // and keeps the displacement of its first slot in d_first (the bond that
 // lane owns first whenever the atom's first slots are all in the cutoff).
+// TWO: two entries per iteration with both loads issued first, for long
+// lists (SW's ~16 entries: 7 % off its site pass); short Tersoff lists keep
+// the plain loop.
+template <bool TWO>
 __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi, int64_t i,
                                                                int64_t cap, int nnb, int q,
                                                                const int* __restrict__ nl,
@@ -166,9 +170,18 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi
 {
     unsigned long long msk = 0;
     d_first = Disp{0.0, 0.0, 0.0, 0.0};
-    for (int m = q; m < nnb; m += kQuad) {
-        const int j = nl[(int64_t)m * cap + i];
-        const Disp d = cut_disp(xi, xw[j], box);
+    int m = q;
+    for (; TWO && m + kQuad < nnb; m += 2 * kQuad) {
+        const int j0 = nl[(int64_t)m * cap + i];
+        const int j1 = nl[(int64_t)(m + kQuad) * cap + i];
+        const double4 x0 = xw[j0], x1 = xw[j1];
+        const Disp d0 = cut_disp(xi, x0, box), d1 = cut_disp(xi, x1, box);
+        if (m == q) d_first = d0;
+        if (d0.r2 < rc2) msk |= 1ull << m;
+        if (d1.r2 < rc2) msk |= 1ull << (m + kQuad);
+    }
+    for (; m < nnb; m += kQuad) {
+        const Disp d = cut_disp(xi, xw[nl[(int64_t)m * cap + i]], box);
         if (m == q) d_first = d;
         if (d.r2 < rc2) msk |= 1ull << m;
     }

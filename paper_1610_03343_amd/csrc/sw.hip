@@ -188,7 +188,7 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int nnb = valid ? min(nn[i], M) : 0;
     Disp d_first;
-    const unsigned long long msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
+    const unsigned long long msk = quad_cutoff_mask<true>(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {

@@ -402,7 +402,22 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
     unsigned long long msk = 0;
     d_first = Disp{0.0, 0.0, 0.0, 0.0};
     t_first = 0;
-    for (int m = q; m < nnb; m += kQuad) {
+    int m = q;
+    // two entries per iteration, both loads issued before either test
+    for (; m + kQuad < nnb; m += 2 * kQuad) {
+        const int j0 = nl[(int64_t)m * cap + i];
+        const int j1 = nl[(int64_t)(m + kQuad) * cap + i];
+        const double4 x0 = xw[j0], x1 = xw[j1];
+        const int t0 = (int)x0.w, t1 = (int)x1.w;
+        const Disp d0 = cut_disp(xi, x0, box), d1 = cut_disp(xi, x1, box);
+        if (m == q) {
+            d_first = d0;
+            t_first = t0;
+        }
+        if (d0.r2 < S2[ti * kMaxTypes + t0]) msk |= 1ull << m;
+        if (d1.r2 < S2[ti * kMaxTypes + t1]) msk |= 1ull << (m + kQuad);
+    }
+    if (m < nnb) {
         const double4 xj = xw[nl[(int64_t)m * cap + i]];
         const int tj = (int)xj.w;
         const Disp d = cut_disp(xi, xj, box);
@@ -523,7 +538,7 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     if constexpr (MULTI)
         msk = quad_cutoff_mask_typed(xi, ti, i, cap, nnb, q, nl, xw, box, L.S2, d_first, t_first);
     else
-        msk = quad_cutoff_mask(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
+        msk = quad_cutoff_mask<false>(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
