@@ -92,19 +92,12 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     if (local < g.n) {
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
-        // the in-cutoff slots lead the list: stop after the last one
-        const int mend = msk ? 64 - __clzll((long long)msk) : 0;
-        for (int m = 0; m < mend; ++m) {
-            if (!((msk >> m) & 1ull)) continue;
-            const int j = nl[(int64_t)m * cap + i];
-            const int rs = rev[(int64_t)m * cap + i];
-            const T* pij = dpart + ((int64_t)m * cap + i) * 3;
-            const T* pji = dpart + ((int64_t)rs * cap + j) * 3;
+        // One bond (list slot m, neighbour j): F_ij, W_i and M_i terms.
+        auto bond = [&](const T* pij, const T* pji, const double4& xj) {
             const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
             const double fij0 = (double)pij[0] - dji0;
             const double fij1 = (double)pij[1] - dji1;
             const double fij2 = (double)pij[2] - dji2;
-            const double4 xj = xw[j];
             double r[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
 #pragma unroll
             for (int c = 0; c < 3; ++c) r[c] -= box.L[c] * rint(r[c] * box.inv[c]);
@@ -120,6 +113,26 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
                 mm[3 * c + 1] += r[c] * dji1;
                 mm[3 * c + 2] += r[c] * dji2;
             }
+        };
+        // The in-cutoff slots in ascending order, two per iteration with
+        // every load of both issued first; the sums take the bonds in the
+        // same order as one at a time.
+        unsigned long long rem = msk;
+        while (rem) {
+            const int m0 = __builtin_ctzll(rem);
+            rem &= rem - 1;
+            const bool two = rem != 0;
+            const int m1 = two ? __builtin_ctzll(rem) : m0;
+            if (two) rem &= rem - 1;
+            const int64_t e0 = (int64_t)m0 * cap + i, e1 = (int64_t)m1 * cap + i;
+            const int j0 = nl[e0], rs0 = rev[e0];
+            const int j1 = nl[e1], rs1 = rev[e1];
+            const T* pji0 = dpart + ((int64_t)rs0 * cap + j0) * 3;
+            const T* pji1 = dpart + ((int64_t)rs1 * cap + j1) * 3;
+            const double4 xj0 = xw[j0];
+            const double4 xj1 = xw[j1];
+            bond(dpart + e0 * 3, pji0, xj0);
+            if (two) bond(dpart + e1 * 3, pji1, xj1);
         }
         ui = U[i];
         double hdt, kin;
