@@ -114,25 +114,34 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
                 mm[3 * c + 2] += r[c] * dji2;
             }
         };
-        // The in-cutoff slots in ascending order, two per iteration with
-        // every load of both issued first; the sums take the bonds in the
+        // The in-cutoff slots in ascending order, four per iteration with
+        // every load of them issued first; the sums take the bonds in the
         // same order as one at a time.
         unsigned long long rem = msk;
         while (rem) {
-            const int m0 = __builtin_ctzll(rem);
-            rem &= rem - 1;
-            const bool two = rem != 0;
-            const int m1 = two ? __builtin_ctzll(rem) : m0;
-            if (two) rem &= rem - 1;
-            const int64_t e0 = (int64_t)m0 * cap + i, e1 = (int64_t)m1 * cap + i;
-            const int j0 = nl[e0], rs0 = rev[e0];
-            const int j1 = nl[e1], rs1 = rev[e1];
-            const T* pji0 = dpart + ((int64_t)rs0 * cap + j0) * 3;
-            const T* pji1 = dpart + ((int64_t)rs1 * cap + j1) * 3;
-            const double4 xj0 = xw[j0];
-            const double4 xj1 = xw[j1];
-            bond(dpart + e0 * 3, pji0, xj0);
-            if (two) bond(dpart + e1 * 3, pji1, xj1);
+            int mk[4], nk = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                mk[u] = rem ? __builtin_ctzll(rem) : mk[0];
+                if (rem) {
+                    rem &= rem - 1;
+                    ++nk;
+                }
+            }
+            int64_t e[4];
+            int jk[4], rk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                e[u] = (int64_t)mk[u] * cap + i;
+                jk[u] = nl[e[u]];
+                rk[u] = rev[e[u]];
+            }
+            double4 xk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xk[u] = xw[jk[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < nk) bond(dpart + e[u] * 3, dpart + ((int64_t)rk[u] * cap + jk[u]) * 3, xk[u]);
         }
         ui = U[i];
         double hdt, kin;
