@@ -8,20 +8,31 @@
 // over S samples taken every `every` steps (every time origin is used, each
 // lag averaged over its own origin count), in W/(m K).
 //
-// The correlation is a lag x origin product: a block owns 64 consecutive
-// lags and walks a strided set of 1024-origin tiles, staging the two sample
-// windows it needs (J(t) and J(t + k0 ..)) in LDS, zero-padded past the end
-// so no product needs a bounds test.  Each lag's sum is split over a fixed
-// number of origin groups and over the four waves of the block in a fixed
-// pattern, and the finishing pass adds the group partials in group order:
-// the result is the same bits on every run, without atomics.
+// The correlation is a lag x origin product: a block owns 512 consecutive
+// lags, eight per lane (k0 + 8 l + r), and walks a strided set of
+// 1024-origin tiles, staging per component the two sample windows it needs
+// (J(t) and J(t + k0 ..)) in LDS, zero-padded past the end so no product
+// needs a bounds test.  A lane keeps the 16 samples J(t + k0 + 8 l + u),
+// u < 16, in registers and slides them eight origins at a time, so each
+// staged value it reads feeds eight multiply-adds.  Each lag's sum is split
+// over a fixed number of origin groups and over the four waves of the block
+// (each wave a contiguous quarter of every tile) in a fixed pattern, and
+// the finishing pass adds the partials in order: the result is the same
+// bits on every run, without atomics.
 #include "mbmd_internal.h"
 
 namespace mbmd {
 
-constexpr int kGkLags = 64;          // lags per block (one per lane of a wave)
-constexpr int kGkOrigins = 1024;     // origins per staged tile
+constexpr int kGkR = 8;                  // consecutive lags per lane
+constexpr int kGkLags = 64 * kGkR;       // lags per block
+constexpr int kGkOrigins = 1024;         // origins per staged tile
 constexpr int kGkWaves = kBlock / 64;
+constexpr int kGkWaveOrigins = kGkOrigins / kGkWaves;
+// b window index x lives at x + x / 8: a lane's reads (x = 8 l + const)
+// then fall 9 doubles apart, which spreads a wave over every LDS bank
+__device__ __forceinline__ int gk_pad(int x) { return x + (x >> 3); }
+constexpr int kGkBWin = kGkOrigins + kGkLags;
+constexpr int kGkBWinPadded = kGkBWin + kGkBWin / 8 + 1;
 
 __global__ void __launch_bounds__(kBlock)
 k_gk_compact(const double* __restrict__ thermo, int64_t S, int every, double* __restrict__ jc)
@@ -34,77 +45,103 @@ k_gk_compact(const double* __restrict__ thermo, int64_t S, int every, double* __
     jc[2 * S + s] = row[13];
 }
 
+// part[(g * kGkWaves + wave) * max_lag + k][3]
 __global__ void __launch_bounds__(kBlock)
 k_gk_corr(const double* __restrict__ jc, int64_t S, int max_lag, double* __restrict__ part)
 {
-    __shared__ double a_win[3][kGkOrigins];
-    __shared__ double b_win[3][kGkOrigins + kGkLags];
-    __shared__ double red[kGkWaves][kGkLags][3];
+    __shared__ double a_win[kGkOrigins];
+    __shared__ double b_win[kGkBWinPadded];
     const int g = blockIdx.x, G = gridDim.x;
     const int k0 = blockIdx.y * kGkLags;
     const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
-    double acc[3] = {0.0, 0.0, 0.0};
+    const int lb = kGkR * l;                  // this lane's first lag, less k0
+    double acc[3][kGkR];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < kGkR; ++r) acc[c][r] = 0.0;
     // origins t with t + k0 < S can pair with a lag of this block
     const int64_t tend = S - k0;
     for (int64_t t0 = (int64_t)g * kGkOrigins; t0 < tend; t0 += (int64_t)G * kGkOrigins) {
-        __syncthreads();   // the previous tile is consumed
-        for (int x = threadIdx.x; x < kGkOrigins + kGkLags; x += kBlock) {
-            const int64_t tb = t0 + k0 + x;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 3; ++c) {
+            __syncthreads();   // the previous window is consumed
+            const double* jcc = jc + c * S;
+            for (int x = threadIdx.x; x < kGkBWin; x += kBlock) {
                 if (x < kGkOrigins) {
                     const int64_t ta = t0 + x;
-                    a_win[c][x] = ta < S ? jc[c * S + ta] : 0.0;
+                    a_win[x] = ta < S ? jcc[ta] : 0.0;
                 }
-                b_win[c][x] = tb < S ? jc[c * S + tb] : 0.0;
+                const int64_t tb = t0 + k0 + x;
+                b_win[gk_pad(x)] = tb < S ? jcc[tb] : 0.0;
             }
-        }
-        __syncthreads();
-        // lag k0 + l, origins t0 + i for i = q, q + 4, ...: J(t + k) sits at
-        // b_win[i + l]; past the end of the series the window holds zeros
-        for (int i = q; i < kGkOrigins; i += kGkWaves) {
+            __syncthreads();
+            // wave q: origins i0 .. i0 + kGkWaveOrigins - 1 of the tile; lag
+            // k0 + lb + r pairs J(t0 + i) with b_win[i + lb + r]
+            const int i0 = q * kGkWaveOrigins;
+            double w0[kGkR], w1[kGkR];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] = fma(a_win[c][i], b_win[c][i + l], acc[c]);
+            for (int u = 0; u < kGkR; ++u) w0[u] = b_win[gk_pad(i0 + lb + u)];
+            for (int i = i0; i < i0 + kGkWaveOrigins; i += 2 * kGkR) {
+                // w0 = b[i + lb ..], w1 = b[i + lb + 8 ..]; then w1, w0 for i + 8
+#pragma unroll
+                for (int u = 0; u < kGkR; ++u) w1[u] = b_win[gk_pad(i + lb + kGkR + u)];
+#pragma unroll
+                for (int u = 0; u < kGkR; ++u) {
+                    const double av = a_win[i + u];
+#pragma unroll
+                    for (int r = 0; r < kGkR; ++r)
+                        acc[c][r] = fma(av, u + r < kGkR ? w0[u + r] : w1[u + r - kGkR],
+                                        acc[c][r]);
+                }
+#pragma unroll
+                for (int u = 0; u < kGkR; ++u)
+                    w0[u] = b_win[gk_pad(i + lb + 2 * kGkR + u)];
+#pragma unroll
+                for (int u = 0; u < kGkR; ++u) {
+                    const double av = a_win[i + kGkR + u];
+#pragma unroll
+                    for (int r = 0; r < kGkR; ++r)
+                        acc[c][r] = fma(av, u + r < kGkR ? w1[u + r] : w0[u + r - kGkR],
+                                        acc[c][r]);
+                }
+            }
         }
     }
+    double* out = part + ((int64_t)(g * kGkWaves + q) * max_lag) * 3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) red[q][l][c] = acc[c];
-    __syncthreads();
-    if (threadIdx.x < kGkLags) {
-        const int k = k0 + threadIdx.x;
+    for (int r = 0; r < kGkR; ++r) {
+        const int k = k0 + lb + r;
         if (k < max_lag) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double s = red[0][threadIdx.x][c];
-#pragma unroll
-                for (int w = 1; w < kGkWaves; ++w) s += red[w][threadIdx.x][c];
-                part[((int64_t)g * max_lag + k) * 3 + c] = s;
-            }
+            for (int c = 0; c < 3; ++c) out[(int64_t)k * 3 + c] = acc[c][r];
         }
     }
 }
 
-// One block: C(k) from the group partials (in group order), then the
-// trapezoid running integral as a chunked scan (each thread a contiguous
-// run of lags; the chunk totals are scanned in order by one thread).
+// C(k) from the P = groups x waves partials, added in partial order: one
+// thread per (lag, component), reading part with the same index stride.
 __global__ void __launch_bounds__(kBlock)
-k_gk_finish(const double* __restrict__ part, int G, int64_t S, int max_lag, double scale,
-            double* __restrict__ hac, double* __restrict__ kappa)
+k_gk_sum(const double* __restrict__ part, int P, int64_t S, int max_lag, double* __restrict__ hac)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // k * 3 + c
+    const int64_t n = (int64_t)max_lag * 3;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += part[(int64_t)p * n + e];
+    hac[e] = s / (double)(S - e / 3);
+}
+
+// One block: the trapezoid running integral of C as a chunked scan (each
+// thread a contiguous run of lags; the chunk totals are scanned in order by
+// one thread).
+__global__ void __launch_bounds__(kBlock)
+k_gk_kappa(const double* __restrict__ hac, int max_lag, double scale, double* __restrict__ kappa)
 {
     __shared__ double chunk_sum[kBlock][3];
     const int per = (max_lag + kBlock - 1) / kBlock;
     const int lo = threadIdx.x * per;
     const int hi = lo + per < max_lag ? lo + per : max_lag;
-    for (int k = lo; k < hi; ++k) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double s = 0.0;
-            for (int g = 0; g < G; ++g) s += part[((int64_t)g * max_lag + k) * 3 + c];
-            hac[(int64_t)k * 3 + c] = s / (double)(S - k);
-        }
-    }
-    __syncthreads();
-    if (!kappa) return;
     double run[3] = {0.0, 0.0, 0.0};
     for (int k = lo > 0 ? lo : 1; k < hi; ++k)
 #pragma unroll
@@ -143,7 +180,7 @@ int gk_groups(int64_t S)
 
 size_t gk_scratch_bytes(int64_t S, int max_lag)
 {
-    return sizeof(double) * (3 * (size_t)S + (size_t)gk_groups(S) * max_lag * 3);
+    return sizeof(double) * (3 * (size_t)S + (size_t)gk_groups(S) * kGkWaves * max_lag * 3);
 }
 
 hipError_t launch_green_kubo(const double* thermo, int64_t S, int every, int max_lag,
@@ -162,7 +199,12 @@ hipError_t launch_green_kubo(const double* thermo, int64_t S, int every, int max
     k_gk_corr<<<grid, kBlock, 0, s>>>(jc, S, max_lag, part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_gk_finish<<<1, kBlock, 0, s>>>(part, G, S, max_lag, scale, hac, kappa);
+    const int64_t n = (int64_t)max_lag * 3;
+    k_gk_sum<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(part, G * kGkWaves, S, max_lag,
+                                                               hac);
+    e = hipGetLastError();
+    if (e != hipSuccess || !kappa) return e;
+    k_gk_kappa<<<1, kBlock, 0, s>>>(hac, max_lag, scale, kappa);
     return hipGetLastError();
 }
 
