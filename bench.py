@@ -84,8 +84,8 @@ def algorithmic_bytes(kernel: str, k_cut: float, l_list: float, dsize: int) -> f
     return 0.0
 
 
-# FP64 operations (FMA = 2) of the special functions as this build compiles
-# them for gfx950 (read from the kernels' assembly), used as their weights
+# FP64 operations (FMA = 2) of the special functions as hipcc compiles them
+# for gfx950 (read from the kernels' assembly), used as their weights
 EXP_FLOPS, LOG_FLOPS, RCP_FLOPS, RSQRT_FLOPS = 30, 80, 9, 13
 
 
@@ -620,7 +620,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
