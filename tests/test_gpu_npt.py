@@ -215,3 +215,39 @@ def test_npt_without_coupling_equals_nve_full_size():
         assert torch.equal(p1, p2) and torch.equal(v1, v2)
         for key in ("U", "F", "W", "J", "thermo"):
             assert torch.equal(a[key], b[key]), key
+
+
+def test_npt_full_size_box_follows_its_thermo_rows():
+    """The 512,000-atom input with the bench's coupling (300 K, 0 GPa,
+    tau_T 100 fs, tau_P 1 ps, beta 1/98 GPa^-1), 40 steps: each step's box is
+    the previous one times mu = (1 - beta dt / tau_P (P0 - P))^(1/3), with P
+    = (2 E_kin + tr W) / (3 V) taken from the previous step's thermo row and
+    box (the Berendsen barostat as the oracle's ora_npt applies it), to a
+    few ulp (the host's cube root need not round like the device's); and
+    the thermo rows are those of the pressure and temperature they report
+    (E_pot + E_kin in column 14, T from E_kin)."""
+    import torch
+    s = wl.tersoff_512k()
+    k = dict(T0=300.0, tau_T=100.0, P0_GPa=0.0, tau_P=1000.0, beta_per_GPa=0.0102)
+    steps = 40
+    with context("tersoff") as ctx:
+        out = ctx.npt_run(to_dev(s.pos), to_dev(s.vel), s.box, wl.M_SI, 1.0, steps,
+                          rebuild_every=20, **k)
+        torch.cuda.synchronize()
+        th = out["thermo"].cpu().numpy()
+        bt = out["box_traj"].cpu().numpy()
+    gpa = 160.21766208                     # GPa per eV/A^3
+    P0, beta = k["P0_GPa"] / gpa, k["beta_per_GPa"] * gpa
+    assert np.array_equal(bt[0], s.box)
+    moved = 0.0
+    for st in range(steps):
+        V = bt[st, 0] * bt[st, 1] * bt[st, 2]
+        P = (2.0 * th[st, 1] + th[st, 2] + th[st, 6] + th[st, 10]) / (3.0 * V)
+        mu = float(np.cbrt(1.0 - beta * 1.0 / k["tau_P"] * (P0 - P)))
+        assert np.all(np.abs(bt[st + 1] - bt[st] * mu) <= 4e-16 * bt[st]), st
+        moved = max(moved, abs(mu - 1.0))
+    assert moved > 1e-9                    # the barostat does act here
+    n = s.n
+    assert np.allclose(th[:, 14], th[:, 0] + th[:, 1], rtol=0, atol=1e-9 * n)
+    T = 2.0 * th[:, 1] / ((3.0 * n - 3.0) * 8.617333262e-5)
+    assert np.allclose(th[:, 15], T, rtol=1e-14, atol=0)
