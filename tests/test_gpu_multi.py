@@ -47,6 +47,9 @@ SYSTEMS = _systems()
 
 
 def rlist(elems):
+    """The oracle's one list radius: the largest pair cutoff plus the skin.
+    Its lists contain the library's per-pair lists, and the oracle's sums
+    run over in-cutoff pairs only, so its results do not depend on it."""
     return max(e["S"] for e in elems) + SKIN
 
 
