@@ -35,7 +35,7 @@
  *     (Section 3; the paper names it without formulas: the scaling factors
  *     are Berendsen's, applied after each step's second half-kick).
  *
- * Readings where the paper is silent (all also recorded in the design doc):
+ * Readings where the paper is silent:
  *   - f_C, f_R, f_A are Tersoff's 1989 forms: f_R = A exp(-lambda r),
  *     f_A = B exp(-mu r), f_C = 1 (r < R), 1/2 + 1/2 cos(pi (r-R)/(S-R))
  *     (R <= r < S), 0 (r >= S);
