@@ -157,9 +157,9 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long msk, int c)
 // Cutoff mask of atom i computed by its quad: lane q tests slots q, q+4, ...
 // and keeps the displacement of its first slot in d_first (the bond that
 // lane owns first whenever the atom's first slots are all in the cutoff).
-// TWO: two entries per iteration with both loads issued first, for long
-// lists (SW's ~16 entries: 7 % off its site pass); short Tersoff lists keep
-// the plain loop.
+// TWO: four, then two, entries per iteration with their loads issued first,
+// for long lists (SW's ~16 entries: 11 % off its site pass); short Tersoff
+// lists keep the plain loop.
 template <bool TWO>
 __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi, int64_t i,
                                                                int64_t cap, int nnb, int q,
@@ -171,6 +171,20 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask(const double4& xi
     unsigned long long msk = 0;
     d_first = Disp{0.0, 0.0, 0.0, 0.0};
     int m = q;
+    for (; TWO && m + 3 * kQuad < nnb; m += 4 * kQuad) {
+        int jv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) jv[u] = nl[(int64_t)(m + u * kQuad) * cap + i];
+        double4 xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = xw[jv[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const Disp d = cut_disp(xi, xv[u], box);
+            if (u == 0 && m == q) d_first = d;
+            if (d.r2 < rc2) msk |= 1ull << (m + u * kQuad);
+        }
+    }
     for (; TWO && m + kQuad < nnb; m += 2 * kQuad) {
         const int j0 = nl[(int64_t)m * cap + i];
         const int j1 = nl[(int64_t)(m + kQuad) * cap + i];
