@@ -242,9 +242,12 @@ def test_typed_neighbor_lists_bitexact(name):
 
 def test_typed_lists_without_types_use_the_first_pair():
     """types = NULL under a multi-element potential: every atom is type 0, so
-    every list has the radius S_00 + skin."""
+    every list has the radius S_00 + skin.  Element 0 is carbon here, whose
+    cutoff (2.1 A) is below silicon's, so the lists differ from those of the
+    largest radius."""
     import oracle
-    s, elems, chi, M = SYSTEMS["sic_alloy"]
+    s, _elems, _chi, M = SYSTEMS["sic_alloy"]
+    elems, chi = [C, SI], CHI_SIC
     with multi_context(elems, chi, M) as ctx:
         nn, nl = ctx.neighbors(to_dev(s.pos), s.box)
         torch.cuda.synchronize()
@@ -253,6 +256,8 @@ def test_typed_lists_without_types_use_the_first_pair():
     assert np.array_equal(nn, onn)
     for i in range(s.n):
         assert np.array_equal(np.sort(nl[:nn[i], i]), onl[i, :onn[i]]), i
+    wide, _ = oracle.neighbors(s.pos, s.box, rlist(elems), M, method="brute")
+    assert np.sum(wide) > np.sum(onn)
 
 
 def test_multi_errors():
