@@ -129,6 +129,29 @@ __device__ __forceinline__ T quad_xor(T v, int k)
     return k == 0 ? v : (k == 1 ? quad_xor_k<1>(v) : (k == 2 ? quad_xor_k<2>(v) : quad_xor_k<3>(v)));
 }
 
+// Value of lane (q + D) mod 4 of the same quad, D = +1 or -1 (a DPP quad
+// rotation).  Every lane of the wave is active at each call site.
+template <int D>
+__device__ __forceinline__ int quad_rot_i32(int v)
+{
+    static_assert(D == 1 || D == -1, "quad rotation");
+    // quad_perm selectors: lane l reads lane (l + 1) & 3 (0x39) or (l + 3) & 3 (0x93)
+    constexpr int ctrl = D == 1 ? 0x39 : 0x93;
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
+}
+template <int D>
+__device__ __forceinline__ double quad_rot(double v)
+{
+    const int lo = quad_rot_i32<D>(__double2loint(v));
+    const int hi = quad_rot_i32<D>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int D>
+__device__ __forceinline__ float quad_rot(float v)
+{
+    return __int_as_float(quad_rot_i32<D>(__float_as_int(v)));
+}
+
 __device__ __forceinline__ unsigned long long quad_or(unsigned long long v)
 {
     int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);

@@ -582,9 +582,43 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     T g0[kQuad], dg0[kQuad];
 #pragma unroll
     for (int k = 0; k < kQuad; ++k) g0[k] = dg0[k] = T(0);
+    if (tmax == 1) {   // wave-uniform: every bond is its lane's first slot
+        // The angle of bonds c and e is the same value for both lanes, so
+        // the lanes evaluate different angles in one instruction: lane q
+        // takes (q, q+1 mod 4) and (q, q xor 2), and receives (q-1 mod 4, q)
+        // from lane q-1; the three give bond q's partners q xor 1, 2, 3.
+        // Products and fused adds are symmetric in their factors, so every
+        // value has the bits lane q would compute itself.
+        const int qa = (q + 1) & 3, qb = q ^ 2;
+        const T ax = quad_rot<1>(ux[0]), ay = quad_rot<1>(uy[0]), az = quad_rot<1>(uz[0]);
+        const T bx = quad_xor_k<2>(ux[0]), by = quad_xor_k<2>(uy[0]), bz = quad_xor_k<2>(uz[0]);
+        T gA = T(0), dgA = T(0), gB = T(0), dgB = T(0);
+        if (q < kc && qa < kc) {
+            const T cs = ux[0] * ax + uy[0] * ay + uz[0] * az;
+            angular_g(pc, cs, gA, dgA);
+        }
+        if (q < kc && qb < kc) {
+            const T cs = ux[0] * bx + uy[0] * by + uz[0] * bz;
+            angular_g(pc, cs, gB, dgB);
+        }
+        const T gP = quad_rot<-1>(gA), dgP = quad_rot<-1>(dgA);
+        const bool even = (q & 1) == 0;
+        g0[1] = even ? gA : gP;
+        dg0[1] = even ? dgA : dgP;
+        g0[2] = gB;
+        dg0[2] = dgB;
+        g0[3] = even ? gP : gA;
+        dg0[3] = even ? dgP : dgA;
+        const T ef1 = quad_xor_k<1>(fc[0]), ef2 = quad_xor_k<2>(fc[0]), ef3 = quad_xor_k<3>(fc[0]);
+        if (q < kc) {
+            if ((q ^ 1) < kc) zp[0] += ef1 * g0[1];
+            if ((q ^ 2) < kc) zp[0] += ef2 * g0[2];
+            if ((q ^ 3) < kc) zp[0] += ef3 * g0[3];
+        }
+    }
 #pragma unroll
     for (int t = 0; t < SLOTS; ++t) {
-        if (t >= tmax) break;   // wave-uniform
+        if (tmax == 1 || t >= tmax) break;   // wave-uniform
 #pragma unroll
         for (int k = 0; k < kQuad; ++k) {
             const T ex = k ? quad_xor(ux[t], k) : ux[t];
