@@ -87,7 +87,9 @@ typedef struct {
  * fixed schedule; Section 3). */
 typedef enum {
     MBMD_REBUILD_FIXED = 0,    /* every rebuild_every steps, nothing else; no
-                                  displacement is tracked */
+                                  displacement is tracked, so the caller picks
+                                  rebuild_every short enough that no pair
+                                  closes in by more than skin between builds */
     MBMD_REBUILD_ON_SKIN = 1   /* also before any step whose positions moved
                                   more than skin/2 from the last build
                                   (default) */
@@ -153,7 +155,9 @@ mbmd_status mbmd_set_type_masses(mbmd_ctx *ctx, int ntypes, const double *mass_a
 mbmd_status mbmd_set_sw(mbmd_ctx *ctx, const mbmd_sw_params *p);
 
 /* Neighbour-list settings (Section 2.1: Verlet list built with a cell list).
- * The list radius is the potential cutoff plus `skin` (>= 0).
+ * The list radius is the potential cutoff plus `skin` (>= 0); under a
+ * multi-element Tersoff potential each pair of types has its own cutoff
+ * S_ab = sqrt(S_a S_b), so its own radius S_ab + skin.
  * `max_neighbors` is the list capacity per atom, 1..64, or 0 for the default
  * (16 for Tersoff, 32 for Stillinger-Weber). */
 mbmd_status mbmd_set_neighbor(mbmd_ctx *ctx, double skin, int max_neighbors);
