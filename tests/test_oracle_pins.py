@@ -614,3 +614,67 @@ def test_npt_barostat_moves_toward_target_pressure(oracle_mod, a):
     assert abs(p_end) < 0.5 * abs(p0), (p0, p_end)
     # isotropic: the three edges keep their ratios
     assert np.allclose(r["box_traj"][-1] / r["box_traj"][0], r["box"][0] / s.box[0], rtol=1e-12)
+
+
+# Berendsen's coupling law, pinned on atoms that never interact: with every
+# force zero the velocity-Verlet kicks add nothing, so the kinetic
+# temperature and the volume follow the weak-coupling relations exactly,
+#   T_{s+1} - T_s = (dt / tau_T) (T0 - T_s),
+#   V_{s+1} / V_s - 1 = -(beta dt / tau_P) (P0 - P_s),  P_s = 2 E_kin,s / (3 V_s),
+# which the recursions below integrate with no square or cube root: a
+# velocity factor without its square root, or a box factor without its cube
+# root, misses them at the first step.
+
+def ideal_gas(seed, temperature=300.0, spacing=4.5, cells=4):
+    """A simple-cubic arrangement 4.5 A apart: beyond the Tersoff list radius
+    (3.5 A), so every list is empty and every force zero."""
+    g = np.stack(np.meshgrid(*[np.arange(cells)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = (g + 0.5) * spacing
+    box = np.full(3, cells * spacing)
+    rng = np.random.default_rng(seed)
+    vel = wl.maxwell_boltzmann(pos.shape[0], temperature, rng)
+    return pos, vel, box
+
+
+def berendsen_law(T_init, ekin_init, V_init, steps, dt, T0, tau_T, P0, tau_P, beta):
+    """(T_s, V_s) of the weak-coupling relations for non-interacting atoms
+    (P0 in eV/A^3, beta in A^3/eV)."""
+    T, E, V = [T_init], [ekin_init], [V_init]
+    for _ in range(steps):
+        t, e, v = T[-1], E[-1], V[-1]
+        t_next = t + dt / tau_T * (T0 - t) if tau_T > 0 else t
+        v_next = v * (1.0 - beta * dt / tau_P * (P0 - 2.0 * e / (3.0 * v))) if tau_P > 0 else v
+        E.append(e * t_next / t)
+        T.append(t_next)
+        V.append(v_next)
+    return np.array(T), np.array(V)
+
+
+@pytest.mark.parametrize("T0,tau_T,P0_GPa,tau_P,beta_GPa", [
+    (150.0, 10.0, 0.0, 0.0, 0.0),      # thermostat only, cooling
+    (900.0, 7.0, 0.0, 0.0, 0.0),       # thermostat only, heating
+    (0.0, 0.0, 0.0, 20.0, 1.0),        # barostat only, ideal-gas pressure: expands
+    (0.0, 0.0, 0.2, 100.0, 1.0),       # barostat only, target above: compresses
+    (500.0, 15.0, 0.1, 50.0, 2.0),     # both
+])
+def test_npt_follows_berendsen_law_on_free_atoms(oracle_mod, T0, tau_T, P0_GPa, tau_P,
+                                                 beta_GPa):
+    pos, vel, box = ideal_gas(seed=41)
+    steps = 60
+    r = oracle_mod.npt("tersoff", TP, pos, vel, box, wl.M_SI, steps, 1.0, RL_T, 10, 16,
+                       T0, tau_T, P0_GPa, tau_P, beta_GPa)
+    th = r["thermo"]
+    # the premise: nothing interacted
+    assert np.all(th[:, 0] == 0.0) and np.all(th[:, 2:11] == 0.0)
+    ev = oracle_mod.EV_PER_A3_IN_GPA
+    T, V = berendsen_law(th[0, 15], th[0, 1], float(np.prod(box)), steps, 1.0, T0, tau_T,
+                         P0_GPa / ev, tau_P, beta_GPa * ev)
+    assert rel_err(th[:, 15], T) <= 1e-12
+    vol = np.prod(r["box_traj"], axis=1)
+    assert rel_err(vol, V) <= 1e-12
+    # isotropic: the edges keep their ratios
+    assert np.allclose(r["box_traj"] / r["box_traj"][0], (vol / vol[0])[:, None] ** (1 / 3),
+                       rtol=1e-12, atol=0)
+    # the coupling actually moved something
+    moved = max(np.abs(T - T[0]).max() / T[0], np.abs(V - V[0]).max() / V[0])
+    assert moved > 1e-2
