@@ -69,6 +69,10 @@ def _load():
         lib.ora_npt.restype = C.c_int
         lib.ora_wrap.argtypes = [C.c_long, _dp, _dp]
         lib.ora_wrap.restype = None
+        lib.ora_set_threads.argtypes = [C.c_int]
+        lib.ora_set_threads.restype = None
+        lib.ora_threads.argtypes = []
+        lib.ora_threads.restype = C.c_int
         for name in ("ora_tersoff_g", "ora_tersoff_g_literal", "ora_tersoff_b", "ora_tersoff_db"):
             getattr(lib, name).argtypes = [C.POINTER(_Tersoff), C.c_double]
             getattr(lib, name).restype = C.c_double
@@ -93,6 +97,17 @@ def tersoff_params(p: dict) -> _Tersoff:
 
 def sw_params(p: dict) -> _SW:
     return _SW(**{k: float(p[k]) for k in ("epsilon", "sigma", "a", "lam", "gamma", "A", "B", "p", "q")})
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the loops over atoms (OpenMP; 1 = serial, the
+    default).  Forces (scattered to neighbours) are summed over per-thread
+    buffers in thread order, so they round differently with more than one
+    thread; every other output is the same bit for bit.  Returns the count
+    in effect."""
+    lib = _load()
+    lib.ora_set_threads(int(n))
+    return lib.ora_threads()
 
 
 def wrap(pos, box):

@@ -1,7 +1,9 @@
 """Build the CPU oracle shared library (test infrastructure only).
 
 gcc -O2 -ffp-contract=off: no fused multiply-add and no fast-math, so the
-oracle's rounding is plain IEEE round-to-nearest per operation.
+oracle's rounding is plain IEEE round-to-nearest per operation.  -fopenmp
+lets the timing baseline spread the loops over atoms across host threads
+(ora_set_threads; one thread by default).
 
 build_sanitized() builds the same source with AddressSanitizer and
 UndefinedBehaviorSanitizer (host code only; the oracle has no GPU code) into
@@ -20,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 FLAGS = ["-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall", "-Wextra", "-fPIC",
-         "-shared"]
+         "-shared", "-fopenmp"]
 SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
             "-fno-omit-frame-pointer", "-g"]
 

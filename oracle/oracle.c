@@ -51,6 +51,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_EINVAL 1
@@ -62,6 +65,49 @@ typedef struct { double A, B, lam, mu, beta, n, c, d, h, R, S; } ora_tersoff_t;
 typedef struct { double epsilon, sigma, a, lam, gamma, A, B, p, q; } ora_sw_t;
 
 static const double ORA_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------- threads
+ * The timing baseline on all host cores runs the loops over atoms i with
+ * OpenMP.  The conventional scatter writes forces (and the LAMMPS-form
+ * virial) of neighbours, so each thread scatters into its own buffer and
+ * the buffers are summed in thread order afterwards: a fixed order for a
+ * given thread count.  Per-atom energies, captured partials and everything
+ * formed from them are written by atom i's own iteration only and do not
+ * depend on the thread count.  With one thread (the default) every loop
+ * runs serially on the output arrays, operation for operation as written. */
+static int g_threads = 1;
+
+void ora_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return g_threads;
+#else
+    return 1;
+#endif
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* dst[x] = sum over threads t = 0..T-1 of buf[t][x], in that order (the
+ * entries x are independent, so they are split over the threads too). */
+static void reduce_threads(double *dst, const double *buf, int T, size_t len)
+{
+#pragma omp parallel for num_threads(T) schedule(static)
+    for (size_t x = 0; x < len; ++x) {
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) acc += buf[(size_t)t * len + x];
+        dst[x] = acc;
+    }
+}
 
 /* ---------------------------------------------------------------- geometry */
 
@@ -211,7 +257,12 @@ int ora_neighbors_cells(long n, const double *box, const double *pos, double rli
     }
     double rl2 = rlist * rlist;
     int overflow = 0;
+    const int T = ora_threads();
+    int *cand_all = T > 1 ? (int *)malloc(sizeof(int) * (size_t)T * (size_t)(n > 0 ? n : 1)) : cand;
+    if (!cand_all) { free(head); free(next); free(cand); free(cell_of); return ORA_ENOMEM; }
+#pragma omp parallel for num_threads(T) schedule(static) reduction(| : overflow) if (T > 1)
     for (long i = 0; i < n; ++i) {
+        int *cand = cand_all + (size_t)thread_id() * (size_t)(n > 0 ? n : 1);
         int lo[3], hi[3];
         for (int a = 0; a < 3; ++a) {
             if (nc[a] >= 3) { lo[a] = -1; hi[a] = 1; }
@@ -239,6 +290,7 @@ int ora_neighbors_cells(long n, const double *box, const double *pos, double rli
         nn[i] = ncand;
         if (ncand > maxnb) overflow = 1;
     }
+    if (cand_all != cand) free(cand_all);
     free(head); free(next); free(cand); free(cell_of);
     return overflow ? ORA_ENEIGH : ORA_OK;
 }
@@ -341,13 +393,16 @@ static int pairwise_post(long n, const double *box, const double *pos, const dou
                          const int *nn, const int *nl, int maxnb, const double *G,
                          double *W, double *J, double *Fpair)
 {
+    int bad = 0;
+    const int T = ora_threads();
+#pragma omp parallel for num_threads(T) schedule(static) reduction(| : bad) if (T > 1)
     for (long i = 0; i < n; ++i) {
         double w[9] = {0}, jj[3] = {0}, fp[3] = {0};
         int cnt = nn[i];
         for (int m = 0; m < cnt; ++m) {
             long j = nl[i * maxnb + m];
             int s = find_slot(nn, nl, maxnb, j, i);
-            if (s < 0) return ORA_EINVAL;          /* lists must be symmetric */
+            if (s < 0) { bad = 1; break; }         /* lists must be symmetric */
             const double *dij = &G[((size_t)i * maxnb + m) * 3];
             const double *dji = &G[((size_t)j * maxnb + s) * 3];
             double rij[3];
@@ -366,7 +421,7 @@ static int pairwise_post(long n, const double *box, const double *pos, const dou
         if (J) memcpy(&J[i * 3], jj, sizeof jj);
         if (Fpair) memcpy(&Fpair[i * 3], fp, sizeof fp);
     }
-    return ORA_OK;
+    return bad ? ORA_EINVAL : ORA_OK;
 }
 
 static void stress_current(long n, const double *WL, const double *vel, double *JL)
@@ -406,6 +461,26 @@ static int tersoff_core(long n, const double *box, const double *pos, const doub
         U[i] = 0.0;
         F[i * 3 + 0] = F[i * 3 + 1] = F[i * 3 + 2] = 0.0;
     }
+    const int T = ora_threads();
+    const size_t nf = (size_t)(n > 0 ? n : 1) * 3, nw = (size_t)(n > 0 ? n : 1) * 9;
+    double *Fbuf = T > 1 ? (double *)malloc(sizeof(double) * (size_t)T * nf) : NULL;
+    double *wbuf = T > 1 ? (double *)malloc(sizeof(double) * (size_t)T * nw) : NULL;
+    if (T > 1 && (!Fbuf || !wbuf)) {
+        free(Fbuf); free(wbuf);
+        if (!Gout) free(G);
+        free(wl);
+        return ORA_ENOMEM;
+    }
+#pragma omp parallel num_threads(T) if (T > 1)
+    {
+    double *const F_out = F, *const wl_out = wl;
+    double *F = T > 1 ? Fbuf + (size_t)thread_id() * nf : F_out;     /* this thread's scatter */
+    double *wl = T > 1 ? wbuf + (size_t)thread_id() * nw : wl_out;
+    if (T > 1) {                       /* each thread clears its own buffers */
+        memset(F, 0, sizeof(double) * nf);
+        memset(wl, 0, sizeof(double) * nw);
+    }
+#pragma omp for schedule(static)
     for (long i = 0; i < n; ++i) {
         int cnt = nn[i];
         const int ti = types ? types[i] : 0;
@@ -494,6 +569,14 @@ static int tersoff_core(long n, const double *box, const double *pos, const doub
                     }
             }
         }
+    }
+    (void)F_out; (void)wl_out;
+    }
+    if (T > 1) {
+        reduce_threads(F, Fbuf, T, nf);
+        reduce_threads(wl, wbuf, T, nw);
+        free(Fbuf);
+        free(wbuf);
     }
     int st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, W, J, Fpair);
     if (WL) memcpy(WL, wl, sizeof(double) * 9 * (size_t)n);
@@ -597,6 +680,26 @@ int ora_sw(long n, const double *box, const double *pos, const double *vel,
         U[i] = 0.0;
         F[i * 3 + 0] = F[i * 3 + 1] = F[i * 3 + 2] = 0.0;
     }
+    const int T = ora_threads();
+    const size_t nf = (size_t)(n > 0 ? n : 1) * 3, nw = (size_t)(n > 0 ? n : 1) * 9;
+    double *Fbuf = T > 1 ? (double *)malloc(sizeof(double) * (size_t)T * nf) : NULL;
+    double *wbuf = T > 1 ? (double *)malloc(sizeof(double) * (size_t)T * nw) : NULL;
+    if (T > 1 && (!Fbuf || !wbuf)) {
+        free(Fbuf); free(wbuf);
+        if (!Gout) free(G);
+        free(wl);
+        return ORA_ENOMEM;
+    }
+#pragma omp parallel num_threads(T) if (T > 1)
+    {
+    double *const F_out = F, *const wl_out = wl;
+    double *F = T > 1 ? Fbuf + (size_t)thread_id() * nf : F_out;     /* this thread's scatter */
+    double *wl = T > 1 ? wbuf + (size_t)thread_id() * nw : wl_out;
+    if (T > 1) {                       /* each thread clears its own buffers */
+        memset(F, 0, sizeof(double) * nf);
+        memset(wl, 0, sizeof(double) * nw);
+    }
+#pragma omp for schedule(static)
     for (long i = 0; i < n; ++i) {
         int cnt = nn[i];
         for (int m = 0; m < cnt; ++m) {
@@ -667,6 +770,14 @@ int ora_sw(long n, const double *box, const double *pos, const double *vel,
                     }
             }
         }
+    }
+    (void)F_out; (void)wl_out;
+    }
+    if (T > 1) {
+        reduce_threads(F, Fbuf, T, nf);
+        reduce_threads(wl, wbuf, T, nw);
+        free(Fbuf);
+        free(wbuf);
     }
     int st = pairwise_post(n, box, pos, vel, nn, nl, maxnb, G, W, J, Fpair);
     if (WL) memcpy(WL, wl, sizeof(double) * 9 * (size_t)n);

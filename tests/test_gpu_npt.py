@@ -251,3 +251,33 @@ def test_npt_full_size_box_follows_its_thermo_rows():
     assert np.allclose(th[:, 14], th[:, 0] + th[:, 1], rtol=0, atol=1e-9 * n)
     T = 2.0 * th[:, 1] / ((3.0 * n - 3.0) * 8.617333262e-5)
     assert np.allclose(th[:, 15], T, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("T0,tau_T,P0_GPa,tau_P,beta_GPa", [
+    (150.0, 10.0, 0.0, 0.0, 0.0),
+    (0.0, 0.0, 0.2, 100.0, 1.0),
+    (500.0, 15.0, 0.1, 50.0, 2.0),
+])
+def test_npt_follows_berendsen_law_on_free_atoms(T0, tau_T, P0_GPa, tau_P, beta_GPa):
+    """The coupling of the HIP path against Berendsen's relations directly
+    (not through the oracle): on atoms that never interact the temperature
+    and volume of every step follow the weak-coupling recursions within
+    rounding (tests/coupling_law.py)."""
+    import torch
+    from conftest import rel_err
+    from coupling_law import berendsen_law, ideal_gas
+    pos, vel, box = ideal_gas(seed=41)
+    steps = 60
+    with context("tersoff") as ctx:
+        out = ctx.npt_run(to_dev(pos), to_dev(vel), box.copy(), wl.M_SI, 1.0, steps,
+                          rebuild_every=10, T0=T0, tau_T=tau_T, P0_GPa=P0_GPa, tau_P=tau_P,
+                          beta_per_GPa=beta_GPa)
+        torch.cuda.synchronize()
+        th = out["thermo"].cpu().numpy()
+        bt = out["box_traj"].cpu().numpy()
+    assert np.all(th[:, 0] == 0.0) and np.all(th[:, 2:11] == 0.0)
+    ev = 160.21766208
+    T, V = berendsen_law(th[0, 15], th[0, 1], float(np.prod(box)), steps, 1.0, T0, tau_T,
+                         P0_GPa / ev, tau_P, beta_GPa * ev)
+    assert rel_err(th[:, 15], T) <= 1e-12
+    assert rel_err(np.prod(bt, axis=1), V) <= 1e-12

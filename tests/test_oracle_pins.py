@@ -15,6 +15,7 @@ import pytest
 
 import workload as wl
 from conftest import rel_err
+from coupling_law import berendsen_law, ideal_gas
 
 TP = wl.TERSOFF_SI_1989
 SP = wl.SW_SI_1985
@@ -625,31 +626,6 @@ def test_npt_barostat_moves_toward_target_pressure(oracle_mod, a):
 # velocity factor without its square root, or a box factor without its cube
 # root, misses them at the first step.
 
-def ideal_gas(seed, temperature=300.0, spacing=4.5, cells=4):
-    """A simple-cubic arrangement 4.5 A apart: beyond the Tersoff list radius
-    (3.5 A), so every list is empty and every force zero."""
-    g = np.stack(np.meshgrid(*[np.arange(cells)] * 3, indexing="ij"), -1).reshape(-1, 3)
-    pos = (g + 0.5) * spacing
-    box = np.full(3, cells * spacing)
-    rng = np.random.default_rng(seed)
-    vel = wl.maxwell_boltzmann(pos.shape[0], temperature, rng)
-    return pos, vel, box
-
-
-def berendsen_law(T_init, ekin_init, V_init, steps, dt, T0, tau_T, P0, tau_P, beta):
-    """(T_s, V_s) of the weak-coupling relations for non-interacting atoms
-    (P0 in eV/A^3, beta in A^3/eV)."""
-    T, E, V = [T_init], [ekin_init], [V_init]
-    for _ in range(steps):
-        t, e, v = T[-1], E[-1], V[-1]
-        t_next = t + dt / tau_T * (T0 - t) if tau_T > 0 else t
-        v_next = v * (1.0 - beta * dt / tau_P * (P0 - 2.0 * e / (3.0 * v))) if tau_P > 0 else v
-        E.append(e * t_next / t)
-        T.append(t_next)
-        V.append(v_next)
-    return np.array(T), np.array(V)
-
-
 @pytest.mark.parametrize("T0,tau_T,P0_GPa,tau_P,beta_GPa", [
     (150.0, 10.0, 0.0, 0.0, 0.0),      # thermostat only, cooling
     (900.0, 7.0, 0.0, 0.0, 0.0),       # thermostat only, heating
@@ -678,3 +654,29 @@ def test_npt_follows_berendsen_law_on_free_atoms(oracle_mod, T0, tau_T, P0_GPa, 
     # the coupling actually moved something
     moved = max(np.abs(T - T[0]).max() / T[0], np.abs(V - V[0]).max() / V[0])
     assert moved > 1e-2
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_threaded_oracle_matches_serial(oracle_mod, pot):
+    """The all-cores timing baseline: with several threads the per-atom
+    energies, lists and pairwise W, J are the same bits (each written by its
+    own atom's iteration) and the scattered forces differ only by the order
+    of the per-thread sums."""
+    s = wl.silicon_crystal(4, seed=51, sigma=0.1, vacancy_fraction=0.02)
+    p, rl = (TP, RL_T) if pot == "tersoff" else (SP, RL_S)
+    outs = []
+    try:
+        for t in (1, 4):
+            assert oracle_mod.set_threads(t) == t
+            nn, nl = oracle_mod.neighbors(s.pos, s.box, rl, 48)
+            o = evaluate(oracle_mod, pot, s.pos, s.box, nn, nl, vel=s.vel)
+            r = oracle_mod.nve(pot, p, s.pos, s.vel, s.box, wl.M_SI, 5, 1.0, rl, 3, 48)
+            outs.append((nn, nl, o, r))
+    finally:
+        oracle_mod.set_threads(1)
+    (nn1, nl1, o1, r1), (nn4, nl4, o4, r4) = outs
+    assert np.array_equal(nn1, nn4) and np.array_equal(nl1, nl4)
+    for k in ("U", "W", "J", "Fpair"):
+        assert np.array_equal(o1[k], o4[k]), k
+    assert rel_err(o4["F"], o1["F"]) <= 1e-14
+    assert rel_err(r4["pos"], r1["pos"]) <= 1e-13
