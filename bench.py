@@ -10,9 +10,13 @@ stored every step; a thermo row per step.  FP64.
 
 One "step" is one MD step of the whole path (list build when due, site-local
 partials, pairwise forces with the fused integrator, thermo reduction).
-Inputs are resident in HBM before the timed region; the timed region is one
-mbmd_nve_run of --steps steps (plus the force evaluation at its start),
-bracketed by device synchronisation.
+Inputs are resident in HBM before the timed region.  --warmup steps run
+first (an mbmd_nve_run from the input); the timed region is the
+mbmd_nve_continue of that run by --steps steps, bracketed by device
+synchronisation: each timed step has its one force evaluation, and the list
+builds are those the 20-step schedule puts among the timed steps (with
+--warmup 0 the timed run starts from the input instead, and its initial
+list build and step-0 force evaluation fall inside the time).
 
 Also measured, as extra fields of the same line:
   mixed    the same input with FP32 bond-order/force arithmetic, --mixed-steps
@@ -207,25 +211,31 @@ class Workload:
         z = lambda *sh: torch.empty(*sh, dtype=torch.float64, device=self.dev)
         self.out = dict(U=z(self.n), F=z(3, self.n), W=z(9, self.n), J=z(3, self.n))
 
-    def run(self, precision, steps, pos=None, vel=None, thermo=None):
+    def run(self, precision, steps, pos=None, vel=None, thermo=None, cont=False):
         torch, mb = self.torch, self.mb
         if pos is None:
             pos, vel = self.pos0.clone(), self.vel0.clone()
         if thermo is None:
             thermo = torch.empty(steps + 1, mb.THERMO_COLS, dtype=torch.float64, device=self.dev)
         self.ctx.nve_run(pos, vel, self.s.box, self.wl.M_SI, 1.0, steps, self.every,
-                         precision=precision, thermo=thermo, out=self.out)
+                         precision=precision, thermo=thermo, out=self.out, cont=cont)
         return pos, vel, thermo
 
     def timed(self, precision, steps, warmup):
+        """Times `steps` MD steps that continue a `warmup`-step run from the
+        input (mbmd_nve_continue): steps warmup + 1 ... warmup + steps of one
+        trajectory, each with its force evaluation, per-atom outputs and
+        thermo row, and the list builds the 20-step schedule puts among them.
+        With warmup 0 the timed run starts from the input, so its step-0
+        force evaluation and list build fall inside the time."""
         torch = self.torch
-        if warmup > 0:
-            self.run(precision, warmup)
         pos, vel = self.pos0.clone(), self.vel0.clone()
+        if warmup > 0:
+            self.run(precision, warmup, pos, vel)
         thermo = torch.empty(steps + 1, self.mb.THERMO_COLS, dtype=torch.float64, device=self.dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        self.run(precision, steps, pos, vel, thermo)
+        self.run(precision, steps, pos, vel, thermo, cont=warmup > 0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return dt, self.ctx.run_stats(), thermo.cpu().numpy(), pos, vel
@@ -246,31 +256,37 @@ def bench_mixed(W, args):
     tmx, stmx, th_mx, pos_mx, vel_mx = W.timed("mixed", steps, args.warmup)
     log(f"mixed: {tmx:.3f} s, {n * steps / tmx:.4e} atom-steps/s")
     log(f"fp64 reference run: {steps} steps")
-    t64, _, th_64, _, _ = W.timed("fp64", steps, 0)
+    t64, _, th_64, _, _ = W.timed("fp64", steps, args.warmup)
 
-    # step 0: both paths on the input positions
-    o64 = W.ctx.compute(W.pos0, W.s.box, vel=W.vel0, precision="fp64")
-    omx = W.ctx.compute(W.pos0, W.s.box, vel=W.vel0, precision="mixed")
-    err0 = {"step": 0, "against": "fp64 path",
-            "max_abs_dF_eV_per_A": float((omx["F"] - o64["F"]).abs().max()),
-            "max_abs_dU_i_eV": float((omx["U"] - o64["U"]).abs().max())}
+    # error checks on a second context, so that the trajectory's context
+    # keeps its run continuable
+    chk = W.mb.Context(0)
+    chk.set_tersoff(wl.TERSOFF_SI_1989)
+    chk.set_neighbor(0.5, 16)
 
-    # the mixed trajectory in chunks (the chunked run reproduces the continuous
-    # one bit for bit); FP64 and mixed evaluated on its positions
-    checks = [err0]
+    def errors(step, pos, vel):
+        o64 = chk.compute(pos, W.s.box, vel=vel, precision="fp64")
+        omx = chk.compute(pos, W.s.box, vel=vel, precision="mixed")
+        return {"step": step, "against": "fp64 path",
+                "max_abs_dF_eV_per_A": float((omx["F"] - o64["F"]).abs().max()),
+                "max_abs_dU_i_eV": float((omx["U"] - o64["U"]).abs().max())}
+
+    # step 0: both paths on the input positions; then the mixed trajectory of
+    # the timed run again, its warm-up continued in chunks (the chunks
+    # reproduce the one continuation bit for bit), FP64 and mixed evaluated
+    # on its positions after each
+    checks = [errors(0, W.pos0, W.vel0)]
     pos, vel = W.pos0.clone(), W.vel0.clone()
     done = 0
+    if args.warmup > 0:
+        W.run("mixed", args.warmup, pos, vel)
     chunk = args.mixed_check
     while done < steps:
         k = min(chunk, steps - done)
-        W.run("mixed", k, pos, vel)
+        W.run("mixed", k, pos, vel, cont=args.warmup > 0 or done > 0)
         done += k
-        o64 = W.ctx.compute(pos, W.s.box, vel=vel, precision="fp64")
-        omx = W.ctx.compute(pos, W.s.box, vel=vel, precision="mixed")
-        checks.append({
-            "step": done, "against": "fp64 path",
-            "max_abs_dF_eV_per_A": float((omx["F"] - o64["F"]).abs().max()),
-            "max_abs_dU_i_eV": float((omx["U"] - o64["U"]).abs().max())})
+        checks.append(errors(args.warmup + done, pos, vel))
+    chk.close()
     same = bool(torch.equal(pos, pos_mx) and torch.equal(vel, vel_mx))
     # per-kernel durations of the mixed path (HIP events, separate pass)
     W.ctx.set_profiling(True)
@@ -430,14 +446,16 @@ def bench_sic(mb, wl, torch, args, si_ms_per_step):
     steps = args.sic_steps
     res = {}
     for prec in ("fp64", "mixed"):
-        ctx.nve_run(pos0.clone(), vel0.clone(), s.box, 0.0, 1.0, args.warmup, 20, types=types,
-                    precision=prec, out=out)
+        # the timed steps continue a warm-up run (as Workload.timed)
         pos, vel = pos0.clone(), vel0.clone()
+        if args.warmup > 0:
+            ctx.nve_run(pos, vel, s.box, 0.0, 1.0, args.warmup, 20, types=types,
+                        precision=prec, out=out)
         th = z(steps + 1, mb.THERMO_COLS)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.nve_run(pos, vel, s.box, 0.0, 1.0, steps, 20, types=types, precision=prec,
-                    thermo=th, out=out)
+                    thermo=th, out=out, cont=args.warmup > 0)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         thh = th.cpu().numpy()
@@ -504,10 +522,11 @@ def bench_serving(mb, wl, torch, args):
         return c
 
     c = ctx()
+    rc = ctx()     # structures reported with MBMD_ESKIN are served again here, alone
     # warm-up and capacity: the first requests all present at time 0
     sub = base[: args.serve_calib]
-    serving.serve_batched(c, sub[:32], saturate=True, rebuild_every=every)
-    _, st = serving.serve_batched(c, sub, saturate=True, rebuild_every=every)
+    serving.serve_batched(c, sub[:32], saturate=True, rebuild_every=every, rerun_ctx=rc)
+    _, st = serving.serve_batched(c, sub, saturate=True, rebuild_every=every, rerun_ctx=rc)
     cap_rps = len(sub) / st.makespan_s
     rate = args.serve_load * cap_rps
     log(f"serving: batched capacity {cap_rps:.1f} requests/s; arrival rate {rate:.1f}/s")
@@ -520,7 +539,8 @@ def bench_serving(mb, wl, torch, args):
            "rebuild_every": every, "latency": "arrival to results (U, F, W, J, x, v) on the host"}
     for prec in ("fp64", "mixed"):
         log(f"serving: batched {prec}")
-        _, sb = serving.serve_batched(c, jobs, precision=prec, rebuild_every=every)
+        _, sb = serving.serve_batched(c, jobs, precision=prec, rebuild_every=every,
+                                      rerun_ctx=rc)
         log(f"serving: one structure per launch {prec}")
         _, ss = serving.serve_sequential(c, jobs, precision=prec, rebuild_every=every)
         res[prec] = {"batched": sb.summary(), "one_per_launch": ss.summary()}
@@ -529,9 +549,10 @@ def bench_serving(mb, wl, torch, args):
             f"{ss.summary()['p50_ms']:.2f}/{ss.summary()['p99_ms']:.2f} ms")
     log(f"serving: batched fp64 with a {args.serve_cap_mib} MiB HBM budget")
     _, sc = serving.serve_batched(c, jobs, precision="fp64", rebuild_every=every,
-                                  hbm_budget_bytes=args.serve_cap_mib << 20)
+                                  hbm_budget_bytes=args.serve_cap_mib << 20, rerun_ctx=rc)
     res["fp64_hbm_capped"] = dict(sc.summary(), hbm_budget_mib=args.serve_cap_mib)
     c.close()
+    rc.close()
     return res
 
 
@@ -643,7 +664,7 @@ def main():
     # repetitions: spread of the timing, and the same bits every time
     rep_ms, digests = [1e3 * t64 / args.steps], []
     for _ in range(args.repeats):
-        tr, _, thr, pr, vr = W.timed("fp64", args.steps, 0)
+        tr, _, thr, pr, vr = W.timed("fp64", args.steps, args.warmup)
         rep_ms.append(1e3 * tr / args.steps)
         h = hashlib.sha256()
         for a in (pr, vr, W.out["F"], W.out["W"], W.out["J"]):

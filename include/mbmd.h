@@ -52,7 +52,10 @@ typedef enum {
     MBMD_EDEVICE = 3,     /* HIP runtime error or internal consistency failure */
     MBMD_EBOX = 4,        /* a box edge is shorter than 2 (cutoff + skin) or not finite */
     MBMD_ENEIGH = 5,      /* a neighbour list needed more than max_neighbors slots */
-    MBMD_ESKIN = 6,       /* reserved (skin violations are handled by the rebuild policy) */
+    MBMD_ESKIN = 6,       /* serving batch: an atom of the structure moved more than
+                             skin/2 from its position at a list build before the
+                             next scheduled build (reported by mbmd_batch_retire;
+                             single runs handle this through the rebuild policy) */
     MBMD_ENONFINITE = 7,  /* a non-finite position */
     MBMD_ENOPOT = 8,      /* no potential set on the context */
     MBMD_EBUSY = 9        /* serving batch: no room now, or structure not finished */
@@ -235,6 +238,31 @@ mbmd_status mbmd_nve_run(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
                          double dt_fs, int n_steps, int rebuild_every, double *U, double *F,
                          double *W, double *J, double *thermo);
 
+/* n_steps more steps of the run that the last call on this context (an
+ * mbmd_nve_run or mbmd_nve_continue that completed) took, from the state it
+ * left: the positions and velocities in pos and vel, the forces of its last
+ * step in F, and, in the context's workspace, its neighbour list, the
+ * positions of its last list build and its place in the rebuild schedule.
+ * The steps are those the original run would have taken next, bit for bit:
+ * the first half-kick and drift that its last step left out, then
+ * n_steps - 1 ordinary steps and a last one, with list builds where its
+ * schedule (or policy) puts them.  So a run of s1 + s2 steps equals a run
+ * of s1 steps continued by s2, and an MD program continues a run without
+ * the force evaluation and list build a new run starts with (velocity-Verlet
+ * of Section 3).  Arguments as for mbmd_nve_run: n, box, mass, dt,
+ * rebuild_every, precision, the rebuild policy and the pos, vel, types and F
+ * buffers must be those of the run continued, whose contents the caller has
+ * left unchanged (MBMD_EINVAL otherwise, or if no such run precedes: any
+ * other call that uses the workspace, or changes the potential, the list
+ * settings or the policy, ends the chance to continue).  thermo (device
+ * [n_steps + 1][16] or NULL) receives the continued run's rows, row 0 being
+ * the state it starts from (the previous run's last row; that run must have
+ * had a thermo array).  U, F, W, J receive the last step's values. */
+mbmd_status mbmd_nve_continue(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const double box[3],
+                              double mass_amu, double *pos, double *vel, const int32_t *types,
+                              double dt_fs, int n_steps, int rebuild_every, double *U,
+                              double *F, double *W, double *J, double *thermo);
+
 /* Berendsen weak coupling (Berendsen et al. 1984): the NPT ensemble, at
  * 300 K and 0 Pa, in which the paper times its runs (Section 3).  The paper
  * prints no coupling formula or constants; the isotropic form below is
@@ -359,18 +387,27 @@ mbmd_status mbmd_batch_finished(const mbmd_ctx *ctx, int *handles, int capacity,
  * velocities and per-atom U, F, W, J into caller device buffers of its n
  * atoms (layouts of mbmd_nve_run; any may be NULL) and free its slot and
  * atom range at once (a later admission is ordered after the copy on the
- * stream).  Asynchronous: the buffers hold the results once the stream has
- * reached this point (mbmd_batch_sync).  MBMD_EBUSY if it has not finished,
- * MBMD_EINVAL for an unknown handle.  Its thermo array is complete at the
- * same point. */
+ * stream).  status (device int32, or NULL) receives the structure's own
+ * status as an mbmd_status value: MBMD_OK; MBMD_ENONFINITE for a non-finite
+ * admitted position; MBMD_ENEIGH if one of its list builds overflowed the
+ * list capacity; MBMD_ESKIN if, between two of the batch's scheduled list
+ * builds, one of its atoms moved more than skin/2 from its position at the
+ * last build, so that its lists (of radius cutoff + skin) may have missed a
+ * pair (the results are then not those of a complete list; rerun it with
+ * rebuilds on the skin, or with a shorter rebuild_every).  The first of
+ * these in that order is reported.  Asynchronous: the buffers hold the
+ * results once the stream has reached this point (mbmd_batch_sync).
+ * MBMD_EBUSY if it has not finished, MBMD_EINVAL for an unknown handle.
+ * Its thermo array is complete at the same point. */
 mbmd_status mbmd_batch_retire(mbmd_ctx *ctx, int handle, double *pos, double *vel, double *U,
-                              double *F, double *W, double *J);
+                              double *F, double *W, double *J, int32_t *status);
 
 /* Wait for everything enqueued on the context's stream and report the
  * batch's status: MBMD_ENONFINITE if an admitted structure had a non-finite
  * position, MBMD_ENEIGH if a list build overflowed the list capacity (the
  * results of that build's structures are then wrong).  The status covers
- * the whole batch since the previous sync and is cleared by the call. */
+ * the whole batch since the previous sync and is cleared by the call.  Skin
+ * violations are reported per structure only (mbmd_batch_retire). */
 mbmd_status mbmd_batch_sync(mbmd_ctx *ctx);
 
 /* Close the batch (device memory stays with the context). */

@@ -86,6 +86,7 @@ def _load():
         "mbmd_neighbors": ([P, I64, P, P, P, P, P], I),
         "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
+        "mbmd_nve_continue": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
         "mbmd_npt_run": ([P, I, I64, P, D, P, P, P, D, I, I, C.POINTER(mbmd_berendsen), P, P,
                           P, P, P, P], I),
         "mbmd_green_kubo": ([P, P, I64, I, I, D, D, D, P, P], I),
@@ -95,7 +96,7 @@ def _load():
         "mbmd_batch_add": ([P, I64, P, P, P, D, D, I, P, C.POINTER(I)], I),
         "mbmd_batch_step": ([P, I, C.POINTER(I)], I),
         "mbmd_batch_finished": ([P, C.POINTER(I), I, C.POINTER(I)], I),
-        "mbmd_batch_retire": ([P, I, P, P, P, P, P, P], I),
+        "mbmd_batch_retire": ([P, I, P, P, P, P, P, P, P], I),
         "mbmd_batch_sync": ([P], I),
         "mbmd_sync": ([P], I),
         "mbmd_batch_close": ([P], I),
@@ -298,8 +299,11 @@ class Context:
         return out
 
     def nve_run(self, pos, vel, box, mass, dt, n_steps, rebuild_every=20, types=None,
-                precision="fp64", thermo=True, out=None):
-        """Advances pos/vel in place; returns dict(U, F, W, J[, thermo])."""
+                precision="fp64", thermo=True, out=None, cont=False):
+        """Advances pos/vel in place; returns dict(U, F, W, J[, thermo]).
+        cont=True continues the previous run on this context
+        (mbmd_nve_continue): the same pos, vel, types and out["F"] tensors,
+        box, mass, dt, rebuild_every and precision."""
         n = pos.shape[1]
         out = self._outputs(n, out)
         th = None
@@ -307,14 +311,15 @@ class Context:
             th = torch.empty(n_steps + 1, THERMO_COLS, dtype=torch.float64, device=self.device)
         elif isinstance(thermo, torch.Tensor):
             th = thermo
-        self._check(_lib.mbmd_nve_run(
+        fn = _lib.mbmd_nve_continue if cont else _lib.mbmd_nve_run
+        self._check(fn(
             self._h, _prec(precision), n, _box(box), float(mass), _dptr(pos, (3, n), "pos"),
             _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32), float(dt),
             int(n_steps), int(rebuild_every), _dptr(out["U"], (n,), "U"),
             _dptr(out["F"], (3, n), "F"), _dptr(out["W"], (9, n), "W"),
             _dptr(out["J"], (3, n), "J"),
             _dptr(th, (n_steps + 1, THERMO_COLS), "thermo") if th is not None else None),
-            "mbmd_nve_run")
+            "mbmd_nve_continue" if cont else "mbmd_nve_run")
         if th is not None:
             out["thermo"] = th
         return out
@@ -431,17 +436,24 @@ class Context:
         """Wait for the stream; raises MbmdError on a batch-wide error status."""
         self._check(_lib.mbmd_batch_sync(self._h), "mbmd_batch_sync")
 
-    def batch_retire(self, handle: int, n: int, out=None):
+    def batch_retire(self, handle: int, n: int, out=None, status=None):
         """Enqueue the copy of a finished structure's final pos, vel, U, F, W,
         J into `out` (allocated if None) and free its slot; the values are
-        there once the stream reaches this point (batch_sync)."""
+        there once the stream reaches this point (batch_sync).  `status` (an
+        int32 device tensor of one element, allocated if None, returned as
+        out["status"]) receives the structure's own status code at the same
+        point (MBMD_OK, MBMD_ENONFINITE, MBMD_ENEIGH or MBMD_ESKIN)."""
         if out is None:
             z = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
             out = dict(pos=z(3, n), vel=z(3, n), U=z(n), F=z(3, n), W=z(9, n), J=z(3, n))
+        if status is None:
+            status = torch.empty(1, dtype=torch.int32, device=self.device)
         self._check(_lib.mbmd_batch_retire(
             self._h, int(handle), _dptr(out["pos"], (3, n), "pos"), _dptr(out["vel"], (3, n), "vel"),
             _dptr(out["U"], (n,), "U"), _dptr(out["F"], (3, n), "F"), _dptr(out["W"], (9, n), "W"),
-            _dptr(out["J"], (3, n), "J")), "mbmd_batch_retire")
+            _dptr(out["J"], (3, n), "J"), _dptr(status, (1,), "status", torch.int32)),
+            "mbmd_batch_retire")
+        out["status"] = status
         th = self._batch_keep.pop(handle, None)
         if th is not None:
             out["thermo"] = th

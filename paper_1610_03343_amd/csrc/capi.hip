@@ -45,6 +45,22 @@ struct Slot {
     bool started = false;    // stepping (admitted structures wait for a rebuild step)
     int final_buf = 0;       // position buffer holding its final positions
     bool done = false;
+    int sidx = 0;            // its per-structure status word
+};
+
+// What the last completed mbmd_nve_run left for mbmd_nve_continue: the
+// call's arguments (the continuation must name the same state) and where
+// its list schedule and thermo ring stand.
+struct ResumeState {
+    bool valid = false;
+    int64_t n = 0;
+    double L[3] = {0, 0, 0};
+    double mass = 0, dt = 0;
+    int every = 0, prec = 0, policy = 0;
+    const void *pos = nullptr, *vel = nullptr, *types = nullptr, *F = nullptr;
+    int since_build = 0;     // steps taken since the last list build
+    int ring_row = 0;        // ring row holding the final state's block partials
+    bool ring_valid = false; // ... if the run formed them (it had a thermo array)
 };
 
 struct Batch {
@@ -58,6 +74,7 @@ struct Batch {
     bool changed = true;     // segment table must be rebuilt
     std::vector<Slot> slots; // ordered by atom offset
     std::vector<int> table;  // slots (indices) of the segment table, in order
+    std::vector<char> sidx_used;   // per-structure status words in use
     // Pinned staging for table uploads, used alternately; an event marks when
     // the stream has consumed each, so uploads never stall the host on the
     // kernels queued ahead of them.
@@ -97,6 +114,7 @@ struct mbmd_ctx {
     std::vector<Seg> segs_host;  // segment table of the current launch set
     Segs segs{};
     Batch* batch = nullptr;
+    ResumeState resume;          // the last completed NVE run, for a continuation
     void* gk_ws = nullptr;       // Green-Kubo scratch (own allocation)
     size_t gk_bytes = 0;
     std::string err;
@@ -236,6 +254,7 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     t.ovf_count = (int*)take(sizeof(int));
     t.ovf_list = (int*)take(sizeof(int) * nn);
     t.status = (unsigned*)take(sizeof(unsigned));
+    t.sstat = (unsigned*)take(sizeof(unsigned) * segs);
     t.xsnap = (double4*)take(sizeof(double4) * nn);
     t.vsnap = (double*)take(sizeof(double) * 3 * nn);
     t.step_disp2 = (unsigned long long*)take(sizeof(unsigned long long) * kMaxChunk);
@@ -502,7 +521,7 @@ hipError_t partials(mbmd_ctx* c, int cur)
 // (integrator per segment phase); flips the phase buffers.
 template <class T>
 hipError_t force_step(mbmd_ctx* c, int cur, bool check, unsigned long long* slot,
-                      double* part_row, bool hold = false)
+                      double* part_row, bool hold = false, unsigned* seg_status = nullptr)
 {
     // the site pass reads the phases too: point both passes at this step's
     set_phase_pointers(c);
@@ -514,6 +533,7 @@ hipError_t force_step(mbmd_ctx* c, int cur, bool check, unsigned long long* slot
     a.disp_slot = slot;
     a.part_row = part_row;
     a.hold = hold;
+    a.seg_status = seg_status;
     if (e == hipSuccess) {
         ProfScope ps(c, P_GATHER);
         e = launch_pair_gather<T>(c->buf, c->segs, a, c->stream);
@@ -537,6 +557,7 @@ mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* p
                          bool dt_run = false)
 {
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
+    c->resume.valid = false;     // this call reuses the workspace
     mbmd_status s = ensure_workspace(c, n, 1, false);
     if (s != MBMD_OK) return s;
     Buffers& b = c->buf;
@@ -608,11 +629,44 @@ hipError_t md_step(mbmd_ctx* c, int step, int cur, bool check, unsigned long lon
     return e;
 }
 
+// Records a completed NVE run for mbmd_nve_continue (prev: the state the
+// run itself continued, if it did).
+void keep_resume(mbmd_ctx* c, int prec, int64_t n, const Box& box, double mass, const double* pos,
+                 const double* vel, const int32_t* types, double dt, int n_steps, int every,
+                 const double* F, const double* thermo, int last_build, const ResumeState* prev)
+{
+    ResumeState r;
+    r.valid = true;
+    r.n = n;
+    for (int a = 0; a < 3; ++a) r.L[a] = box.L[a];
+    r.mass = mass;
+    r.dt = dt;
+    r.every = every;
+    r.prec = prec;
+    r.policy = c->policy;
+    r.pos = pos;
+    r.vel = vel;
+    r.types = types;
+    r.F = F;
+    r.since_build = n_steps - last_build;
+    if (n_steps > 0 || !prev) {
+        r.ring_row = n_steps % kThermoRing;
+        r.ring_valid = thermo != nullptr;
+    } else {
+        r.ring_row = prev->ring_row;
+        r.ring_valid = prev->ring_valid;
+    }
+    c->resume = r;
+}
+
 template <class T>
 mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double* pos,
                      double* vel, const int32_t* types, double dt, int n_steps, int every,
-                     double* U, double* F, double* W, double* J, double* thermo)
+                     double* U, double* F, double* W, double* J, double* thermo, bool resume)
 {
+    // a continuation keeps the lists, the build positions and the thermo
+    // ring the previous run left in the workspace
+    const ResumeState prev = c->resume;
     int cells = 0;
     mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
                                  &cells, true);
@@ -620,15 +674,56 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     const Buffers& b = c->buf;
     mbmd_run_stats st{};
     st.steps = n_steps;
-    c->fold_from = c->fold_to = 0;
-    int cur = 0, last_build = 0;
-    hipError_t e = build(c, cells, cur);
-    st.rebuilds = 1;
+    const double skin_half2 = 0.25 * c->skin * c->skin;
+    double committed_max2 = 0.0;
+    int cur = 0, last_build = 0, step0 = 0;
+    hipError_t e = hipSuccess;
+    if (!resume) {
+        c->fold_from = c->fold_to = 0;
+        e = build(c, cells, cur);
+        st.rebuilds = 1;
+    } else {
+        // Step 0 is the state the previous run ended in: its thermo row is
+        // that run's last one, folded again from the ring, and the first
+        // half-kick and drift its last step left out come first.
+        last_build = -prev.since_build;
+        c->fold_from = c->fold_to = 1;
+        if (thermo) e = launch_thermo_fold(b, c->segs, 0, 0, 1, prev.ring_row, thermo, c->stream);
+        if (e == hipSuccess && n_steps > 0) {
+            const bool chk = c->policy == MBMD_REBUILD_ON_SKIN && (1 - last_build) != every;
+            if (chk) e = launch_fill_int((int*)b.step_disp2, 2, 0, c->stream);
+            if (e == hipSuccess)
+                e = launch_kick_drift(b, c->segs, cur, chk ? b.step_disp2 : nullptr, c->stream);
+            cur = 1;
+            if (e == hipSuccess) e = launch_fill_int(b.phase[c->pp], 1, 1, c->stream);
+            if (e == hipSuccess && chk) {
+                unsigned long long bits = 0;
+                e = hipMemcpyAsync(&bits, b.step_disp2, sizeof bits, hipMemcpyDeviceToHost,
+                                   c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                double d2;
+                std::memcpy(&d2, &bits, sizeof d2);
+                if (e == hipSuccess && d2 > skin_half2) {
+                    e = build(c, cells, cur);
+                    last_build = 1;
+                    ++st.rebuilds;
+                } else if (d2 > committed_max2) {
+                    committed_max2 = d2;
+                }
+            }
+            if (e == hipSuccess && c->policy == MBMD_REBUILD_ON_SKIN && 1 - last_build == every) {
+                e = build(c, cells, cur);
+                last_build = 1;
+                ++st.rebuilds;
+            }
+        }
+        step0 = 1;
+    }
 
     if (c->policy == MBMD_REBUILD_FIXED) {
         // The list is rebuilt every `every` steps whatever the atoms do; no
         // displacement is tracked (the statistics report -1).
-        for (int step = 0; step <= n_steps && e == hipSuccess; ++step) {
+        for (int step = step0; step <= n_steps && e == hipSuccess; ++step) {
             if (step - last_build == every) {
                 e = build(c, cells, cur);
                 last_build = step;
@@ -643,6 +738,9 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         s = finish(c);
         st.max_displacement = -1.0;
         c->stats = st;
+        if (s == MBMD_OK)
+            keep_resume(c, sizeof(T) == 4 ? MBMD_MIXED : MBMD_FP64, n, box, mass, pos, vel, types,
+                        dt, n_steps, every, F, thermo, last_build, resume ? &prev : nullptr);
         return s;
     }
 
@@ -651,11 +749,9 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     // back.  If the positions of some step moved more than skin/2 from the
     // last build, the chunk is replayed from the snapshot (bit-identically)
     // up to that step and the list is rebuilt there.
-    const double skin_half2 = 0.25 * c->skin * c->skin;
-    int step = 0;
+    int step = step0;
     int chunk = every < kMaxChunk ? every : kMaxChunk;
     std::vector<unsigned long long> disp(kMaxChunk);
-    double committed_max2 = 0.0;
     while (step <= n_steps && e == hipSuccess) {
         const int cs = step;
         int cend = last_build + every;
@@ -725,6 +821,9 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     s = finish(c);
     st.max_displacement = std::sqrt(committed_max2);
     c->stats = st;
+    if (s == MBMD_OK)
+        keep_resume(c, sizeof(T) == 4 ? MBMD_MIXED : MBMD_FP64, n, box, mass, pos, vel, types, dt,
+                    n_steps, every, F, thermo, last_build, resume ? &prev : nullptr);
     return s;
 }
 
@@ -838,6 +937,7 @@ hipError_t batch_table(mbmd_ctx* c, int* total_cells, bool rebuild)
         if (!s.started) continue;
         Seg g = make_seg(s.box, rl, s.atom_off, s.n, s.nsteps, s.mass, s.dt, s.thermo);
         g.build = rebuild && !s.done;
+        g.sidx = s.sidx;
         c->segs_host.push_back(g);
         B.table.push_back((int)q);
     }
@@ -920,7 +1020,15 @@ mbmd_status batch_step_impl(mbmd_ctx* c, int* n_active)
     // enqueued
     c->max_nn = kMaxSlots;
     const int row = B.batch_step % kThermoRing;
-    if (e == hipSuccess) e = force_step<T>(c, B.cur, false, nullptr, ring_row(c, row));
+    // Unless the next batch step rebuilds the lists, every atom's drift is
+    // measured from its position at the last build: a structure whose atoms
+    // moved more than skin/2 gets its skin bit, reported when it is retired
+    // (its lists may then miss pairs; the step is not checked against the
+    // positions the next build sees).
+    const bool next_due = (B.batch_step + 1 - B.phase0) % B.rebuild_every == 0;
+    if (e == hipSuccess)
+        e = force_step<T>(c, B.cur, !next_due, nullptr, ring_row(c, row), false,
+                          c->buf.sstat);
     if (e == hipSuccess) {
         // the fold reads the phase buffer the pairwise launch read
         ProfScope ps(c, P_THERMO);
@@ -997,6 +1105,7 @@ mbmd_status mbmd_set_tersoff_multi(mbmd_ctx* c, int ntypes, const mbmd_tersoff_p
                                    const double* chi)
 {
     if (!c || !elem) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (ntypes < 1 || ntypes > kMaxTypes)
         return fail(c, MBMD_EINVAL, "ntypes must be in 1..4%s");
@@ -1028,6 +1137,7 @@ mbmd_status mbmd_set_tersoff_multi(mbmd_ctx* c, int ntypes, const mbmd_tersoff_p
 mbmd_status mbmd_set_type_masses(mbmd_ctx* c, int ntypes, const double* mass_amu)
 {
     if (!c) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (ntypes == 0) {
         c->n_tmass = 0;
         return MBMD_OK;
@@ -1045,6 +1155,7 @@ mbmd_status mbmd_set_type_masses(mbmd_ctx* c, int ntypes, const double* mass_amu
 mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
 {
     if (!c || !p) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (!tersoff_params_ok(p))
         return fail(c, MBMD_EINVAL,
@@ -1062,6 +1173,7 @@ mbmd_status mbmd_set_tersoff(mbmd_ctx* c, const mbmd_tersoff_params* p)
 mbmd_status mbmd_set_sw(mbmd_ctx* c, const mbmd_sw_params* p)
 {
     if (!c || !p) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     const double v[] = {p->epsilon, p->sigma, p->a, p->lambda, p->gamma, p->A, p->B, p->p, p->q};
     for (double x : v)
@@ -1077,6 +1189,7 @@ mbmd_status mbmd_set_sw(mbmd_ctx* c, const mbmd_sw_params* p)
 mbmd_status mbmd_set_neighbor(mbmd_ctx* c, double skin, int max_neighbors)
 {
     if (!c) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (!std::isfinite(skin) || skin < 0.0) return fail(c, MBMD_EINVAL, "skin must be >= 0%s");
     if (max_neighbors < 0 || max_neighbors > kMaxSlots)
@@ -1090,6 +1203,7 @@ mbmd_status mbmd_set_neighbor(mbmd_ctx* c, double skin, int max_neighbors)
 mbmd_status mbmd_set_rebuild_policy(mbmd_ctx* c, mbmd_rebuild_policy policy)
 {
     if (!c) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (policy != MBMD_REBUILD_FIXED && policy != MBMD_REBUILD_ON_SKIN)
         return fail(c, MBMD_EINVAL, "unknown rebuild policy%s");
     c->policy = policy;
@@ -1158,6 +1272,7 @@ mbmd_status mbmd_batch_workspace_size(const mbmd_ctx* c, int64_t max_atoms, int 
 mbmd_status mbmd_bind_workspace(mbmd_ctx* c, void* dev_ptr, size_t bytes)
 {
     if (!c) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     if (dev_ptr && ((uintptr_t)dev_ptr % kAlign) != 0)
         return fail(c, MBMD_EINVAL, "workspace must be 256-byte aligned%s");
@@ -1230,9 +1345,46 @@ mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const doub
     if (!pos || !vel || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
     if (prec == MBMD_MIXED)
         return nve_impl<float>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
-                               U, F, W, J, thermo);
+                               U, F, W, J, thermo, false);
     return nve_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every, U,
-                            F, W, J, thermo);
+                            F, W, J, thermo, false);
+}
+
+mbmd_status mbmd_nve_continue(mbmd_ctx* c, mbmd_precision prec, int64_t n, const double box[3],
+                              double mass_amu, double* pos, double* vel, const int32_t* types,
+                              double dt_fs, int n_steps, int rebuild_every, double* U, double* F,
+                              double* W, double* J, double* thermo)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (n_steps < 0) return fail(c, MBMD_EINVAL, "need n_steps >= 0%s");
+    if (!pos || !vel || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    const ResumeState& r = c->resume;
+    if (!r.valid)
+        return fail(c, MBMD_EINVAL,
+                    "nothing to continue: the last call on this context was not a completed "
+                    "mbmd_nve_run or mbmd_nve_continue%s");
+    const bool same = r.n == n && r.L[0] == b.L[0] && r.L[1] == b.L[1] && r.L[2] == b.L[2] &&
+                      r.mass == mass_amu && r.dt == dt_fs && r.every == rebuild_every &&
+                      r.prec == (int)prec && r.policy == c->policy && r.pos == pos &&
+                      r.vel == vel && r.types == types && r.F == F;
+    if (!same)
+        return fail(c, MBMD_EINVAL,
+                    "a continuation takes the arguments of the run it continues (n, box, mass, "
+                    "dt, rebuild_every, precision, policy and the pos, vel, types and F "
+                    "buffers)%s");
+    if (thermo && !r.ring_valid)
+        return fail(c, MBMD_EINVAL,
+                    "thermo rows of a continuation need a thermo array in the run it "
+                    "continues%s");
+    if (n == 0) return MBMD_OK;
+    if (prec == MBMD_MIXED)
+        return nve_impl<float>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every,
+                               U, F, W, J, thermo, true);
+    return nve_impl<double>(c, n, b, mass_amu, pos, vel, types, dt_fs, n_steps, rebuild_every, U,
+                            F, W, J, thermo, true);
 }
 
 mbmd_status mbmd_npt_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, double box[3],
@@ -1316,6 +1468,7 @@ mbmd_status mbmd_batch_open(mbmd_ctx* c, int64_t max_atoms, int max_structures,
                             int rebuild_every)
 {
     if (!c) return MBMD_EINVAL;
+    c->resume.valid = false;
     if (c->potential < 0) return fail(c, MBMD_ENOPOT, "no potential set%s");
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is already open%s");
     if (max_atoms < 1 || max_atoms > (int64_t)0x3fffffff || max_structures < 1 ||
@@ -1330,6 +1483,7 @@ mbmd_status mbmd_batch_open(mbmd_ctx* c, int64_t max_atoms, int max_structures,
     if (!B) return MBMD_ENOMEM;
     B->max_atoms = max_atoms;
     B->max_structs = max_structures;
+    B->sidx_used.assign(max_structures, 0);
     B->rebuild_every = rebuild_every;
     c->batch = B;
     for (int k = 0; k < 2; ++k) {
@@ -1394,6 +1548,9 @@ mbmd_status mbmd_batch_add(mbmd_ctx* c, int64_t n, const double box[3], const do
     const int64_t at = find_range(B, n);
     if (at < 0) return fail(c, MBMD_EBUSY, "no free atom range of this size%s");
     Slot sl;
+    // the lowest free status word (one exists: slots and words are as many)
+    while (sl.sidx < B.max_structs && B.sidx_used[sl.sidx]) ++sl.sidx;
+    if (sl.sidx >= B.max_structs) return fail(c, MBMD_EDEVICE, "no free status word%s");
     sl.handle = B.next_handle++;
     sl.atom_off = (int)at;
     sl.n = (int)n;
@@ -1405,8 +1562,10 @@ mbmd_status mbmd_batch_add(mbmd_ctx* c, int64_t n, const double box[3], const do
     // positions into the buffer the next launch reads, velocities into the
     // batch state
     hipError_t e = launch_batch_admit(pos, vel, n, b, (int)at, c->buf.xw[0], c->buf.xw[1],
-                                      c->buf.vel, c->buf.ostride, c->buf.status, c->stream);
+                                      c->buf.vel, c->buf.ostride, c->buf.status,
+                                      c->buf.sstat + sl.sidx, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "batch add");
+    B.sidx_used[sl.sidx] = 1;
     auto it = std::lower_bound(B.slots.begin(), B.slots.end(), (int)at,
                                [](const Slot& x, int off) { return x.atom_off < off; });
     B.slots.insert(it, sl);
@@ -1441,7 +1600,7 @@ mbmd_status mbmd_batch_finished(const mbmd_ctx* c, int* handles, int capacity, i
 }
 
 mbmd_status mbmd_batch_retire(mbmd_ctx* c, int handle, double* pos, double* vel, double* U,
-                              double* F, double* W, double* J)
+                              double* F, double* W, double* J, int32_t* status)
 {
     if (!c) return MBMD_EINVAL;
     if (!c->batch) return fail(c, MBMD_EINVAL, "no serving batch is open%s");
@@ -1453,8 +1612,12 @@ mbmd_status mbmd_batch_retire(mbmd_ctx* c, int handle, double* pos, double* vel,
     hipError_t e = hipSetDevice(c->device);
     if (e == hipSuccess)
         e = launch_batch_copy_out(b.xw[sl->final_buf], b.vel, b.U, b.F, b.W, b.J, b.ostride,
-                                  sl->atom_off, sl->n, pos, vel, U, F, W, J, c->stream);
+                                  sl->atom_off, sl->n, pos, vel, U, F, W, J,
+                                  b.sstat + sl->sidx, status, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "batch retire");
+    // the status word can be reused at once too: a later admission clears it
+    // on the stream after this copy-out has read it
+    B.sidx_used[sl->sidx] = 0;
     // the range can be handed out at once: a later admission's copy-in is
     // ordered after this copy-out on the stream
     B.slots.erase(B.slots.begin() + (sl - B.slots.data()));

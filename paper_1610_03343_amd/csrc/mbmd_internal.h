@@ -39,6 +39,9 @@ enum : unsigned {
     ST_ASYMMETRIC = 1u << 3,       // list or cutoff mask not symmetric (internal)
     ST_TYPES = 1u << 4,            // an atom type other than 0
     ST_BAROSTAT = 1u << 5,         // Berendsen box factor mu^3 <= 0 (mu set to 1)
+    ST_SKIN = 1u << 6,             // serving batch: an atom moved more than skin/2 from
+                                   // its position at the last list build before the
+                                   // next scheduled build (per-structure word only)
 };
 
 constexpr int kBlock = 256;          // threads per block of every per-atom kernel
@@ -70,6 +73,7 @@ struct Seg {
     int blk, blk_quad;      // first block for 256-atom and 64-atom blocks
     int nsteps;             // steps of its run (0: a single force evaluation)
     int build;              // nonzero: its list is (re)built by the next build launch
+    int sidx;               // index of its per-structure status word (batch; 0 alone)
     double half_dt_acc;     // dt/2 kappa/m
     double dt;
     double kin_scale;       // m / (2 kappa)
@@ -160,6 +164,7 @@ struct Buffers {
     int* ovf_count;          // atoms whose in-cutoff count exceeds the fast path
     int* ovf_list;           // [N]
     unsigned* status;
+    unsigned* sstat;         // [segments] per-structure status (indexed by Seg::sidx)
     double4* xsnap;          // [N] positions at the start of a checked chunk
     double* vsnap;           // [3][N] velocities at the start of a checked chunk
     unsigned long long* step_disp2;  // [kMaxChunk] largest squared displacement per step
@@ -216,17 +221,21 @@ hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, in
                                  unsigned* status, hipStream_t s);
 // Serving batch: wraps positions pos[3][n] into xw0 and xw1 at atom_off and
 // copies velocities vel[3][n] into vel_dst (row stride `stride`) at atom_off.
+// A non-finite position raises ST_NONFINITE in the batch word and in the
+// structure's own word *sst (which the launch first clears).
 hipError_t launch_batch_admit(const double* pos, const double* vel, int64_t n, Box box,
                               int atom_off, double4* xw0, double4* xw1, double* vel_dst,
-                              int64_t stride, unsigned* status, hipStream_t s);
+                              int64_t stride, unsigned* status, unsigned* sst, hipStream_t s);
 // Serving batch: copies one structure's final positions (from xw), velocities
 // and U, F, W, J (row stride `stride`, from atom_off) into caller arrays of n
-// atoms; any output may be null.
+// atoms; any output may be null.  status_o (or null) receives the status
+// code (an mbmd_status value) of the structure's own status word *sst.
 hipError_t launch_batch_copy_out(const double4* xw, const double* vel, const double* U,
                                  const double* F, const double* W, const double* J,
                                  int64_t stride, int atom_off, int64_t n, double* pos_o,
                                  double* vel_o, double* U_o, double* F_o, double* W_o,
-                                 double* J_o, hipStream_t s);
+                                 double* J_o, const unsigned* sst, int32_t* status_o,
+                                 hipStream_t s);
 // Copies xw[atom_off ..) back to pos[3][n].
 hipError_t launch_store_positions(const double4* xw, int atom_off, int64_t n, double* pos_soa,
                                   hipStream_t s);
@@ -269,6 +278,9 @@ struct StepArgs {
     double* part_row;        // this step's row of block partials (null: no thermo)
     bool hold;               // second half-kick only: no drift, positions stay in
                              // buffer cur (the weak-coupling loop drifts separately)
+    unsigned* seg_status;    // with check_skin: ST_SKIN is OR-ed into seg_status[sidx]
+                             // of a structure whose displacement exceeds skin/2
+                             // (null: not reported per structure)
 };
 
 // Berendsen weak coupling in the library's units: T0 in K, P0 in eV/A^3,
@@ -307,6 +319,11 @@ size_t gk_scratch_bytes(int64_t S, int max_lag);
 hipError_t launch_green_kubo(const double* thermo, int64_t S, int every, int max_lag,
                              double scale, double* scratch, double* hac, double* kappa,
                              hipStream_t s);
+// Continuation: v <- v + (dt/2) kappa F / m, x <- wrap(x + dt v) from
+// buffer cur into cur ^ 1 (the pairwise pass's arithmetic); with slot (or
+// null) the largest squared displacement from the list-build positions.
+hipError_t launch_kick_drift(const Buffers& b, const Segs& S, int cur,
+                             unsigned long long* slot, hipStream_t s);
 // Weak coupling: v <- lambda v + (dt/2) kappa F / m, x <- wrap(mu x + dt v)
 // in the (already scaled) box, in place in position buffer `cur`.
 hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_t s);

@@ -275,7 +275,8 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
          double rc2, ListRadii R, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
          const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
-         int* __restrict__ rev, int* __restrict__ maxnn, unsigned* __restrict__ status)
+         int* __restrict__ rev, int* __restrict__ maxnn, unsigned* __restrict__ status,
+         unsigned* __restrict__ sstat)
 {
     extern __shared__ int lbuf[];
     __shared__ int lds_max[kSearchBlock / 64];
@@ -411,7 +412,10 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         }
         // On overflow the stored entries are the M smallest keys; the status
         // bit turns the call into an error.
-        if (cnt > M) atomicOr(status, ST_NEIGH_OVERFLOW);
+        if (cnt > M) {
+            atomicOr(status, ST_NEIGH_OVERFLOW);
+            atomicOr(&sstat[S.seg[sid].sidx], ST_NEIGH_OVERFLOW);
+        }
         nn[i] = cnt;
         const int w = cnt < M ? cnt : M;
         for (int m = 0; m < w; ++m) {
@@ -499,12 +503,12 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
         k_search<true><<<2 * S.nblk, kSearchBlock, lds, s>>>(
             S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut, *typed,
             b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn,
-            b.status);
+            b.status, b.sstat);
     else
         k_search<false><<<2 * S.nblk, kSearchBlock, lds, s>>>(
             S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut,
             ListRadii{}, b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev,
-            b.maxnn, b.status);
+            b.maxnn, b.status, b.sstat);
     k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
 }

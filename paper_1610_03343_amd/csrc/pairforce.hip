@@ -206,7 +206,9 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
         }
     }
 
-    // largest squared displacement since the list build: one atomic per block
+    // largest squared displacement since the list build: one atomic per
+    // block into the run's slot, and (serving batch) the skin bit of the
+    // block's structure
     if (a.check_skin) {
         double m = disp2;
 #pragma unroll
@@ -218,7 +220,8 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
 #pragma unroll
             for (int k = 1; k < kBlock / 64; ++k) bm = fmax(bm, lds_max[k]);
             // non-negative doubles order like their bit patterns
-            atomicMax(a.disp_slot, (unsigned long long)__double_as_longlong(bm));
+            if (a.disp_slot) atomicMax(a.disp_slot, (unsigned long long)__double_as_longlong(bm));
+            if (a.seg_status && bm > a.skin_half2) atomicOr(&a.seg_status[g.sidx], ST_SKIN);
         }
     }
 
@@ -405,6 +408,76 @@ hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_
     if (S.nblk <= 0) return hipSuccess;
     if (!segs_ready(S, b) || !b.vel || !b.F || !b.coupling) return hipErrorInvalidValue;
     k_npt_drift<<<S.nblk, kBlock, 0, s>>>(S, b.ostride, b.coupling, b.xw[cur], b.vel, b.F);
+    return hipGetLastError();
+}
+
+// Continuation of a run: the first half-kick and drift that the pairwise
+// pass of the previous run's last step left out, from its full-step
+// velocities and forces, v <- v + (dt/2) kappa F / m and x_next <- wrap(x +
+// dt v), with the pairwise pass's unfused arithmetic in the same order, so a
+// continued run takes the same steps, bit for bit, as one that never
+// stopped.  With `slot` the largest squared displacement of x_next from the
+// list-build positions is formed as in the pairwise pass (one atomic per
+// block).
+__global__ void __launch_bounds__(kBlock)
+k_kick_drift(Segs S, int64_t os, const double4* __restrict__ xw, double4* __restrict__ xw_next,
+             const double4* __restrict__ xbuild, double* __restrict__ vel,
+             const double* __restrict__ F, unsigned long long* __restrict__ slot)
+{
+    __shared__ double lds_max[kBlock / 64];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const Box box = g.box;
+    const int local = (lb - g.blk) * kBlock + threadIdx.x;
+    const int64_t i = g.atom_off + local;
+    double disp2 = 0.0;
+    if (local < g.n) {
+#pragma clang fp contract(off)
+        const double4 xi = xw[i];
+        double hdt, kin;
+        atom_mass_factors(g, xi.w, hdt, kin);
+        double vn[3], x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vn[c] = vel[c * os + i] + hdt * F[c * os + i];
+            x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
+        }
+        vel[i] = vn[0];
+        vel[os + i] = vn[1];
+        vel[2 * os + i] = vn[2];
+        xw_next[i] = make_double4(x[0], x[1], x[2], xi.w);
+        if (slot) {
+            const double4 xb = xbuild[i];
+            double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
+                disp2 += d[c] * d[c];
+            }
+        }
+    }
+    if (!slot) return;
+    double m = disp2;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bm = lds_max[0];
+#pragma unroll
+        for (int k = 1; k < kBlock / 64; ++k) bm = fmax(bm, lds_max[k]);
+        atomicMax(slot, (unsigned long long)__double_as_longlong(bm));
+    }
+}
+
+hipError_t launch_kick_drift(const Buffers& b, const Segs& S, int cur,
+                             unsigned long long* slot, hipStream_t s)
+{
+    if (S.nblk <= 0) return hipSuccess;
+    if (!segs_ready(S, b) || !b.vel || !b.F) return hipErrorInvalidValue;
+    k_kick_drift<<<S.nblk, kBlock, 0, s>>>(S, b.ostride, b.xw[cur], b.xw[cur ^ 1], b.xbuild,
+                                           b.vel, b.F, slot);
     return hipGetLastError();
 }
 

@@ -14,10 +14,18 @@ pinned host memory are followed by an event that later iterations poll, and
 the host stays at most MAX_STEPS_AHEAD batch steps ahead of the GPU (it waits
 on the event of an older step), so the GPU always has queued work while the
 host admits and retires.  A request's latency ends when the host sees its
-copy complete.  The batch's device status is checked once at the end.
+copy complete.  Each retired structure's own status comes back with its
+results: a structure whose atoms outran the skin between two scheduled list
+builds (MBMD_ESKIN) is served again alone under the rebuild-on-skin policy,
+whose results then stand (and its latency ends when they are on the host);
+a structure with any other error is dropped (its rid and code are kept in
+the statistics) while the loop serves the rest.  At the end the batch's
+device status is checked, and the loop raises if a request failed.
 
 The one-structure-per-launch path serves the same trace in arrival order
-through mbmd_compute / mbmd_nve_run, one structure at a time.
+through mbmd_compute / mbmd_nve_run, one structure at a time, rebuilding on
+the skin: a run that never outruns the skin rebuilds only on the fixed
+schedule, so every request gets the same bits on both paths.
 
 All arithmetic runs in libmbmd; this module only schedules.
 """
@@ -30,7 +38,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import THERMO_COLS, Context, MbmdError, MBMD_EBUSY
+from . import THERMO_COLS, Context, MbmdError, MBMD_EBUSY, MBMD_ESKIN, MBMD_OK
 
 # rows of the stacked per-request result: U, F (3), W (9), J (3), pos (3), vel (3)
 RESULT_ROWS = 22
@@ -63,6 +71,8 @@ class ServeStats:
     loop_steps: int = 0
     max_in_flight: int = 0
     capacity_atoms: int = 0
+    skin_reruns: int = 0
+    failed: dict = field(default_factory=dict)        # rid -> mbmd_status code
 
     def summary(self) -> dict:
         lat = np.array(sorted(self.latencies_s.values()))
@@ -77,6 +87,8 @@ class ServeStats:
             "loop_steps": self.loop_steps,
             "max_in_flight": self.max_in_flight,
             "capacity_atoms": self.capacity_atoms or None,
+            "skin_reruns": self.skin_reruns,
+            "failed": len(self.failed),
         }
 
 
@@ -120,14 +132,36 @@ def batch_capacity_atoms(ctx: Context, hbm_budget_bytes: int, max_structures: in
     return lo
 
 
+def rerun_alone(ctx: Context, job: Job, precision, rebuild_every):
+    """One structure on its own under the rebuild-on-skin policy; returns
+    the stacked result rows on the host and its thermo rows (or None)."""
+    dev = ctx.device
+    ctx.set_rebuild_policy("skin")
+    buf = torch.empty(RESULT_ROWS, job.n, dtype=torch.float64, device=dev)
+    out = _result_views(buf)
+    out["pos"].copy_(_dev(job.pos, dev))
+    out["vel"].copy_(_dev(job.vel, dev))
+    th = None
+    if job.n_steps == 0:
+        ctx.compute(out["pos"], job.box, vel=out["vel"], precision=precision, out=out)
+    else:
+        th = torch.empty(job.n_steps + 1, THERMO_COLS, dtype=torch.float64, device=dev)
+        ctx.nve_run(out["pos"], out["vel"], job.box, job.mass, job.dt, job.n_steps,
+                    rebuild_every, precision=precision, thermo=th, out=out)
+    return buf.cpu(), (th.cpu() if th is not None else None)
+
+
 def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
                   max_structures=256, rebuild_every=10, keep_results=False, saturate=False,
-                  clock=time.perf_counter):
+                  rerun_ctx: Context | None = None, clock=time.perf_counter):
     """Continuous batching over the arrival trace `jobs`.
 
     hbm_budget_bytes: device memory the batch may use (default: half of the
     free memory, but no more than max_structures of the largest request need).
     saturate: every request is taken as arrived at time 0 (capacity runs).
+    rerun_ctx: a context with the same potential and skin, on which a
+    structure reported with MBMD_ESKIN is served again alone (rebuilding on
+    the skin); without one such a structure fails.
     """
     dev = ctx.device
     largest_job = max(j.n for j in jobs)
@@ -159,7 +193,16 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
             ev, done = copies.popleft()
             ev.synchronize()
             now = clock() - t0
-            for job, host, th_host in done:
+            for job, host, th_host, st_host in done:
+                code = int(st_host[0])
+                if code == MBMD_ESKIN and rerun_ctx is not None:
+                    host, th_alone = rerun_alone(rerun_ctx, job, precision, rebuild_every)
+                    th_host = th_alone if th_host is not None else None
+                    stats.skin_reruns += 1
+                    now = clock() - t0
+                elif code != MBMD_OK:
+                    stats.failed[job.rid] = code
+                    continue
                 stats.latencies_s[job.rid] = now - (0.0 if saturate else job.arrival_s)
                 stats.atom_steps += job.n * max(1, job.n_steps)
                 if keep_results:
@@ -211,17 +254,21 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
             # retire every finished structure: asynchronous copies into pinned
             # host buffers, marked by one event that later iterations poll
             done = []
-            for h in fin:
+            st = torch.empty(len(fin), dtype=torch.int32, device=dev)
+            for k, h in enumerate(fin):
                 job = in_flight.pop(h)
                 buf = torch.empty(RESULT_ROWS, job.n, dtype=torch.float64, device=dev)
-                th = ctx.batch_retire(h, job.n, _result_views(buf)).get("thermo")
+                th = ctx.batch_retire(h, job.n, _result_views(buf), status=st[k:k + 1]).get("thermo")
                 host = torch.empty(RESULT_ROWS, job.n, dtype=torch.float64, pin_memory=True)
                 host.copy_(buf, non_blocking=True)
                 th_host = None
                 if keep_results and th is not None:
                     th_host = torch.empty(th.shape, dtype=torch.float64, pin_memory=True)
                     th_host.copy_(th, non_blocking=True)
-                done.append((job, host, th_host))
+                done.append((job, host, th_host, k))
+            st_host = torch.empty(len(fin), dtype=torch.int32, pin_memory=True)
+            st_host.copy_(st, non_blocking=True)
+            done = [(job, host, th_host, st_host[k:k + 1]) for job, host, th_host, k in done]
             ev = torch.cuda.Event()
             ev.record(stream)
             copies.append((ev, done))
@@ -229,6 +276,10 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
         collect(True)
         stats.makespan_s = clock() - t0
         ctx.batch_sync()
+        if stats.failed:
+            rid, code = next(iter(stats.failed.items()))
+            raise MbmdError(code, f"{len(stats.failed)} request(s) failed in the batch "
+                                  f"(request {rid} first)")
     finally:
         ctx.batch_close()
     return results, stats
@@ -236,11 +287,13 @@ def serve_batched(ctx: Context, jobs, precision="fp64", hbm_budget_bytes=None,
 
 def serve_sequential(ctx: Context, jobs, precision="fp64", rebuild_every=10, keep_results=False,
                      saturate=False, clock=time.perf_counter):
-    """The same trace, one structure per launch sequence, in arrival order."""
+    """The same trace, one structure per launch sequence, in arrival order
+    (lists rebuilt every rebuild_every steps and whenever an atom has moved
+    skin/2 since the last build)."""
     dev = ctx.device
     stats = ServeStats()
     results = {}
-    ctx.set_rebuild_policy("fixed")
+    ctx.set_rebuild_policy("skin")
     order = sorted(jobs, key=lambda j: (0.0 if saturate else j.arrival_s, j.rid))
     t0 = clock()
     for job in order:

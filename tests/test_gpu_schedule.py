@@ -138,3 +138,83 @@ def test_npt_resume_is_bitwise(pot):
     assert np.array_equal(fb[20:], second["box_traj"].cpu().numpy())
     for k in ("U", "F", "W", "J"):
         assert torch.equal(full[k], second[k]), k
+
+
+def _drifting(seed, drift):
+    """1,000-atom crystal at 300 K with a uniform drift (A/fs) added to
+    every velocity: under the skin policy it outruns the skin every few
+    steps, so runs rebuild off the fixed schedule too."""
+    s = wl.silicon_crystal(5, seed=seed, sigma=0.05)
+    s.vel = s.vel + np.asarray(drift)
+    return s
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("policy", ["fixed", "skin"])
+def test_nve_continue_is_bitwise(pot, precision, policy):
+    """mbmd_nve_continue: 40 steps equal 13 continued by 0, 14 and 13 steps,
+    bit for bit: x, v, the last step's U, F, W, J, the thermo rows (row 0 of
+    a continuation is the last row of the run it continues) and the number
+    of list builds.  Under the skin policy the drift makes the runs rebuild
+    off the schedule, on both sides of the splits."""
+    s = _drifting(71, [0.03, -0.02, 0.015])
+    every = 10
+    with context(pot) as ctx:
+        ctx.set_rebuild_policy(policy)
+        pa, va = to_dev(s.pos), to_dev(s.vel)
+        full = ctx.nve_run(pa, va, s.box, wl.M_SI, 1.0, 40, rebuild_every=every,
+                           precision=precision)
+        torch.cuda.synchronize()
+        st_full = ctx.run_stats()
+        full = {k: v.cpu().numpy() for k, v in full.items()}
+        pb, vb = to_dev(s.pos), to_dev(s.vel)
+        out = None
+        rows, builds = [], 0
+        for k, steps in enumerate((13, 0, 14, 13)):
+            r = ctx.nve_run(pb, vb, s.box, wl.M_SI, 1.0, steps, rebuild_every=every,
+                            precision=precision, out=out, cont=k > 0)
+            out = {key: r[key] for key in ("U", "F", "W", "J")}
+            torch.cuda.synchronize()
+            rows.append(r["thermo"].cpu().numpy())
+            builds += ctx.run_stats()["rebuilds"]
+    if policy == "skin":
+        # builds off the schedule (which alone builds at 0, 10, ..., 40)
+        assert st_full["rebuilds"] > 5 and st_full["rollbacks"] >= 1, st_full
+    assert builds == st_full["rebuilds"]
+    assert torch.equal(pa, pb) and torch.equal(va, vb)
+    for k in ("U", "F", "W", "J"):
+        assert np.array_equal(full[k], out[k].cpu().numpy()), k
+    th = full["thermo"]
+    assert np.array_equal(rows[0], th[:14])
+    assert np.array_equal(rows[1], th[13:14])
+    assert np.array_equal(rows[2], th[13:28])
+    assert np.array_equal(rows[3], th[27:41])
+
+
+def test_nve_continue_errors():
+    """A continuation names the run it continues: anything else is refused
+    with MBMD_EINVAL, and a refused call leaves the run continuable."""
+    import paper_1610_03343_amd as mb
+    s = wl.silicon_crystal(3, seed=72)
+    with context("tersoff") as ctx:
+        p, v = to_dev(s.pos), to_dev(s.vel)
+        with pytest.raises(mb.MbmdError) as e:                # nothing ran yet
+            ctx.nve_run(p, v, s.box, wl.M_SI, 1.0, 5, cont=True)
+        assert e.value.code == mb.MBMD_EINVAL
+        out = ctx.nve_run(p, v, s.box, wl.M_SI, 1.0, 5, thermo=None)
+        for kw in (dict(box=s.box * 1.01), dict(dt=0.5), dict(every=7), dict(prec="mixed"),
+                   dict(F=True), dict(thermo=True)):
+            o = dict(out)
+            if kw.get("F"):
+                o["F"] = out["F"].clone()
+            with pytest.raises(mb.MbmdError) as e:
+                ctx.nve_run(p, v, kw.get("box", s.box), wl.M_SI, kw.get("dt", 1.0), 5,
+                            rebuild_every=kw.get("every", 20), precision=kw.get("prec", "fp64"),
+                            thermo=kw.get("thermo", None), out=o, cont=True)
+            assert e.value.code == mb.MBMD_EINVAL, kw
+        ctx.nve_run(p, v, s.box, wl.M_SI, 1.0, 5, thermo=None, out=out, cont=True)
+        ctx.compute(to_dev(s.pos), s.box)                      # reuses the workspace
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.nve_run(p, v, s.box, wl.M_SI, 1.0, 5, thermo=None, out=out, cont=True)
+        assert e.value.code == mb.MBMD_EINVAL

@@ -208,15 +208,19 @@ def test_batch_admission_limits_and_errors():
 def test_serving_loop_trace_and_identity():
     """A short Poisson trace through the request loop: every request is
     served, latencies are recorded, and the results equal the
-    one-structure-per-launch baseline bit for bit."""
+    one-structure-per-launch baseline bit for bit.  Several of these
+    disordered requests (sigma up to 0.15 A, vacancies) outrun the skin
+    within 10 steps: the batch reports them and the loop serves them again
+    under the rebuild-on-skin policy, which the baseline uses throughout."""
     import paper_1610_03343_amd as mb
     from paper_1610_03343_amd import serving
     reqs = wl.serving_trace(24, rate_hz=400.0, seed=2001, max_cells=6, nve_steps=20)
     jobs = serving.jobs_from_requests(reqs)
-    with context("tersoff") as ctx:
+    with context("tersoff") as ctx, context("tersoff") as rctx:
         res_b, st_b = serving.serve_batched(ctx, jobs, hbm_budget_bytes=256 << 20,
                                             max_structures=16, rebuild_every=10,
-                                            keep_results=True)
+                                            keep_results=True, rerun_ctx=rctx)
+    assert st_b.skin_reruns >= 1
     with context("tersoff") as ctx:
         res_s, st_s = serving.serve_sequential(ctx, jobs, rebuild_every=10, keep_results=True)
     assert len(res_b) == len(jobs) == len(res_s)
@@ -248,3 +252,106 @@ def test_serving_loop_reports_device_errors():
                                   rebuild_every=5)
         assert e.value.code == mb.MBMD_ENONFINITE
         ctx.sync()
+
+
+def _hot_and_cool(seed):
+    """Two 216-atom crystals at 300 K; the hot one also drifts uniformly at
+    0.08 A/fs, so its atoms move more than skin/2 = 0.25 A from their build
+    positions within four steps, while the cool one's stay within ~0.1 A."""
+    cool = wl.silicon_crystal(3, seed=seed, sigma=0.05)
+    hot = wl.silicon_crystal(3, seed=seed + 1, sigma=0.05)
+    hot.vel = hot.vel + np.array([0.06, -0.04, 0.03])
+    return cool, hot
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_batch_reports_skin_violation_per_structure(pot):
+    """Lists are rebuilt every 10 batch steps; the drifting structure outruns
+    the skin in between and its retire call reports MBMD_ESKIN, the other
+    structure of the same batch reports MBMD_OK and still equals its run
+    alone bit for bit (the check only reads positions)."""
+    import paper_1610_03343_amd as mb
+    import torch
+    cool, hot = _hot_and_cool(310)
+    with context(pot) as ctx:
+        ctx.set_rebuild_policy("fixed")
+        alone = _alone(ctx, cool, 25, "fp64", 10)
+    with context(pot) as ctx:
+        ctx.batch_open(1000, 4, 10)
+        hc = ctx.batch_add(to_dev(cool.pos), to_dev(cool.vel), cool.box, wl.M_SI, 1.0, 25)
+        hh = ctx.batch_add(to_dev(hot.pos), to_dev(hot.vel), hot.box, wl.M_SI, 1.0, 25)
+        outs = {}
+        while len(outs) < 2:
+            ctx.batch_step()
+            for h in ctx.batch_finished():
+                outs[h] = ctx.batch_retire(h, cool.n)
+        ctx.batch_sync()          # skin violations are not batch-wide errors
+        torch.cuda.synchronize()
+        ctx.batch_close()
+    assert int(outs[hh]["status"][0]) == mb.MBMD_ESKIN
+    assert int(outs[hc]["status"][0]) == mb.MBMD_OK
+    for k in ("U", "F", "W", "J", "pos", "vel"):
+        assert np.array_equal(outs[hc][k].cpu().numpy(), alone[k]), k
+
+
+def test_batch_reports_list_overflow_per_structure():
+    """With room for 4 list entries, a compressed crystal overflows its
+    lists and is reported MBMD_ENEIGH by its retire call (and by the batch
+    sync), while a crystal at the equilibrium lattice constant, whose lists
+    hold exactly its 4 bonds, is reported MBMD_OK."""
+    import paper_1610_03343_amd as mb
+    ok = wl.silicon_crystal(3, seed=320, sigma=0.03)
+    squeezed = wl.silicon_crystal(3, seed=321, sigma=0.03, a=4.9)
+    with context("tersoff", max_neighbors=4) as ctx:
+        ctx.batch_open(1000, 4, 10)
+        h_ok = ctx.batch_add(to_dev(ok.pos), to_dev(ok.vel), ok.box, wl.M_SI, 1.0, 3)
+        h_sq = ctx.batch_add(to_dev(squeezed.pos), to_dev(squeezed.vel), squeezed.box, wl.M_SI,
+                             1.0, 3)
+        outs = {}
+        while len(outs) < 2:
+            ctx.batch_step()
+            for h in ctx.batch_finished():
+                outs[h] = ctx.batch_retire(h, ok.n)
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.batch_sync()
+        assert e.value.code == mb.MBMD_ENEIGH
+        ctx.batch_close()
+    assert int(outs[h_sq]["status"][0]) == mb.MBMD_ENEIGH
+    assert int(outs[h_ok]["status"][0]) == mb.MBMD_OK
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_serving_loop_reruns_skin_violations(precision):
+    """The request loop serves a structure reported with MBMD_ESKIN again
+    alone under the rebuild-on-skin policy: its results equal that run bit
+    for bit, and the other requests still equal their runs alone on the
+    batch's fixed schedule.  Without a context to rerun on, the loop raises
+    MBMD_ESKIN."""
+    import paper_1610_03343_amd as mb
+    from paper_1610_03343_amd import serving
+    cool, hot = _hot_and_cool(330)
+    jobs = [serving.Job(0, 0.0, cool.pos, cool.vel, cool.box, 30),
+            serving.Job(1, 0.0, hot.pos, hot.vel, hot.box, 30),
+            serving.Job(2, 0.0, cool.pos, cool.vel, cool.box, 0)]
+    with context("tersoff") as ctx, context("tersoff") as rctx:
+        res, st = serving.serve_batched(ctx, jobs, precision=precision,
+                                        hbm_budget_bytes=64 << 20, max_structures=4,
+                                        rebuild_every=10, keep_results=True, saturate=True,
+                                        rerun_ctx=rctx)
+        with pytest.raises(mb.MbmdError) as e:
+            serving.serve_batched(ctx, jobs, precision=precision, hbm_budget_bytes=64 << 20,
+                                  max_structures=4, rebuild_every=10, saturate=True)
+        assert e.value.code == mb.MBMD_ESKIN
+        ctx.sync()
+    assert st.skin_reruns == 1 and len(res) == 3 and not st.failed
+    with context("tersoff") as ctx:
+        ctx.set_rebuild_policy("skin")
+        hot_alone = _alone(ctx, hot, 30, precision, 10)
+        assert ctx.run_stats()["rollbacks"] >= 1
+        ctx.set_rebuild_policy("fixed")
+        cool_alone = _alone(ctx, cool, 30, precision, 10)
+        cool_single = _alone(ctx, cool, 0, precision, 10)
+    for rid, want in ((1, hot_alone), (0, cool_alone), (2, cool_single)):
+        for k in ("U", "F", "W", "J", "pos", "vel"):
+            assert np.array_equal(res[rid][k].numpy(), want[k]), (rid, k)
+    assert np.array_equal(res[1]["thermo"].numpy(), hot_alone["thermo"])
