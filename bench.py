@@ -62,7 +62,13 @@ sys.path.insert(0, ROOT)
 METRIC = "atom-steps/s, Tersoff Si 512k atoms (FP64 vs mixed); p50/p99 batched latency"
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tersoff_512k_fp64_hbm_traffic.md")
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROFILES = os.path.join(ROOT, "profiles")
+# Compulsory HBM bytes per atom-step of a whole MD step (read x, v, F and the
+# lists, write and read the bond data, write U, F, W, J and v), NN = 4 for
+# the Tersoff crystal and 16 list entries for SW: FP64 Tersoff 517, mixed
+# Tersoff (bond data in FP32) 453, FP64 SW (no bond-order pass) 390.
+STEP_BYTES_PER_ATOM = {"tersoff_fp64": 517.0, "tersoff_mixed": 453.0, "sw_fp64": 390.0}
 
 
 def log(msg):
@@ -80,20 +86,23 @@ def algorithmic_bytes(kernel: str, k_cut: float, l_list: float, dsize: int) -> f
         # read x_i (24), list count (4), list (4 l); write mask (8), U (8), partials
         return 24 + 4 + 4 * l_list + 8 + 8 + part
     if kernel == "pair_gather":
-        # read x (24), mask (8), count (4), list + reverse slots (8 l), own partials,
-        # U (8), v (24); write F (24), W (72), J (24), v (24), x_next (24)
-        return 24 + 8 + 4 + 8 * l_list + part + 8 + 24 + 24 + 72 + 24 + 24 + 24
+        # read x (24), mask (8), list + reverse slots of the in-cutoff entries
+        # (8 k), own partials, U (8), v (24); write F (24), W (72), J (24),
+        # v (24), x_next (24)
+        return 24 + 8 + 8 * k_cut + part + 8 + 24 + 24 + 72 + 24 + 24 + 24
     if kernel == "neighbor_build":
         return 24 + 4 + 8 * l_list
     return 0.0
 
 
 # FP64 operations (FMA = 2) of the special functions as hipcc compiles them
-# for gfx950 (read from the kernels' assembly), used as their weights
-EXP_FLOPS, LOG_FLOPS, RCP_FLOPS, RSQRT_FLOPS = 30, 80, 9, 13
+# for gfx950 (read from the kernels' assembly), used as their weights; the
+# unweighted count takes each special function as one operation
+FP64_WEIGHTS = {"exp": 30, "log": 80, "rcp": 9, "rsqrt": 13}
+UNWEIGHTED = {"exp": 1, "log": 1, "rcp": 1, "rsqrt": 1}
 
 
-def tersoff_site_flops(mean_L, mean_K, mean_KK):
+def tersoff_site_flops(mean_L, mean_K, mean_KK, w=FP64_WEIGHTS):
     """Algorithmic FP64 operations per atom of the Tersoff site pass.
 
     mean_L: list entries, mean_K: in-cutoff bonds K, mean_KK: mean of K(K-1)
@@ -105,10 +114,96 @@ def tersoff_site_flops(mean_L, mean_K, mean_KK):
     term (2) and the partial-derivative accumulation (27).  Bonds in the
     cutoff taper (none in the 300 K crystal) would add a sincos each.
     """
-    per_bond = (RSQRT_FLOPS + 4) + 2 * (EXP_FLOPS + 2) + (LOG_FLOPS + EXP_FLOPS + 14 + RCP_FLOPS + 2) + 17
-    per_pair = 5 + 10 + RCP_FLOPS
+    per_bond = ((w["rsqrt"] + 4) + 2 * (w["exp"] + 2) + (w["log"] + w["exp"] + 14 + w["rcp"] + 2)
+                + 17)
+    per_pair = 5 + 10 + w["rcp"]
     per_ordered = 2 + 27
     return 20 * mean_L + per_bond * mean_K + per_pair * mean_KK / 2 + per_ordered * mean_KK
+
+
+def sw_site_flops(mean_L, mean_K, mean_KK, w=FP64_WEIGHTS):
+    """Algorithmic FP64 operations per atom of the SW site pass (FMA = 2;
+    special functions weighted as for Tersoff).  Per list entry: displacement
+    and r^2 (20).  Per bond: length and unit vector (rsqrt + 4), the two-body
+    term and its derivative with E = exp(gamma sigma/(r - a sigma)) (two exp,
+    a reciprocal and 21), its share of U_i (2), the radial factor of the
+    partial (rcp + 4).  Per unordered angle: the three-body energy (11).  Per
+    ordered angle: the three-body part of the partial (28)."""
+    per_bond = (w["rsqrt"] + 4) + (2 * w["exp"] + w["rcp"] + 21) + 2 + (w["rcp"] + 4)
+    return 20 * mean_L + per_bond * mean_K + 11 * mean_KK / 2 + 28 * mean_KK
+
+
+def profile_value(fname, pattern):
+    """A machine-read value from a committed profile summary, or None if the
+    file is missing, has no such line, or was taken on other kernel sources."""
+    try:
+        text = open(os.path.join(PROFILES, fname)).read()
+    except OSError:
+        return None
+    m = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(pattern, text, re.M)
+    return m.groups() if m else None
+
+
+def path_roofline(path, n, ms_per_step, kernels, site_flops_atom, site_peak_tflops,
+                  bytes_pair_atom, bytes_site_atom):
+    """Roofline figures of one path: the whole step against HBM with its
+    compulsory bytes, the site pass against the vector peak of its precision
+    (algorithmic FLOP) and its VALU issue share (counters), the pairwise pass
+    against HBM (algorithmic bytes) and its counted traffic.  Durations are
+    the HIP-event averages of the bench's profiled pass; where a committed
+    rocprofv3 summary of the same kernel sources exists, its average and the
+    fractions it gives are reported beside them."""
+    sb = STEP_BYTES_PER_ATOM[path]
+    step_gbs = sb * n / (ms_per_step * 1e-3) / 1e9
+    out = {"step": {"bound": "hbm", "bytes_per_atom_step": sb, "achieved": round(step_gbs, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                    "ms_per_step": ms_per_step}}
+    stats = f"{path.replace('tersoff', 'tersoff_512k').replace('sw', 'sw_1m')}"
+    for kind, unit in (("site_partials", "TFLOP/s"), ("pair_gather", "GB/s")):
+        k = kernels.get(kind)
+        if not k:
+            continue
+        us = k["avg_us"]
+        rp = profile_value(f"{stats}_kernel_stats.md", rf"^avg_us\s+{kind}:\s*([0-9.]+)")
+        us_rp = float(rp[0]) if rp else None
+        d = {"avg_us": us, "avg_us_rocprof": us_rp}
+        if kind == "site_partials":
+            if site_flops_atom:
+                f = site_flops_atom * n
+                d.update({"bound": "alu", "algorithmic_flops_per_atom": round(site_flops_atom, 1),
+                          "achieved": round(f / (us * 1e-6) / 1e12, 3), "peak": site_peak_tflops,
+                          "unit": "TFLOP/s"})
+                d["frac"] = round(d["achieved"] / site_peak_tflops, 4)
+                if us_rp:
+                    d["frac_rocprof"] = round(f / (us_rp * 1e-6) / 1e12 / site_peak_tflops, 4)
+            d["bytes_per_atom"] = bytes_site_atom
+            d["hbm_GBs"] = round(bytes_site_atom * n / (us * 1e-6) / 1e9, 1)
+            v = profile_value(f"{stats}_valu_counters.md",
+                              r"^valu\s+site_partials:\s*insts_per_launch=([0-9.e+]+)")
+            if v:
+                d["valu_issue_frac"] = round(float(v[0]) / VALU_ISSUE_PER_S /
+                                             ((us_rp or us) * 1e-6), 4)
+        else:
+            b = bytes_pair_atom * n
+            d.update({"bound": "hbm", "algorithmic_bytes_per_atom": round(bytes_pair_atom, 1),
+                      "achieved": round(b / (us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s"})
+            d["frac"] = round(d["achieved"] / HBM_PEAK_GBS, 4)
+            if us_rp:
+                d["frac_rocprof"] = round(b / (us_rp * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        t = profile_value(f"{stats}_hbm_traffic.md",
+                          rf"^traffic\s+{kind}:\s*fetch_bytes=([0-9.e+]+)\s+write_bytes=([0-9.e+]+)")
+        if t:
+            tb = float(t[0]) + float(t[1])
+            d["traffic"] = tb
+            d["traffic_over_algorithmic"] = round(
+                tb / ((bytes_pair_atom if kind == "pair_gather" else bytes_site_atom) * n), 3)
+            d["traffic_GBs"] = round(tb / ((us_rp or us) * 1e-6) / 1e9, 1)
+        out[kind] = d
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -125,42 +220,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kind: str):
-    """HBM bytes per launch of a kernel class from the committed counter
-    summary, or None if it is missing or was taken on other kernel sources."""
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
-        return None, None
-    m = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
-    if not m or m.group(1) != kernel_source_hash():
-        return None, None
-    m = re.search(rf"^traffic\s+{re.escape(kind)}:\s*fetch_bytes=([0-9.e+]+)\s+"
-                  rf"write_bytes=([0-9.e+]+)", text, re.M)
-    if not m:
-        return None, None
-    return float(m.group(1)) + float(m.group(2)), {"fetch": float(m.group(1)),
-                                                   "write": float(m.group(2))}
-
-
-COUNTER_PROFILE = os.path.join(ROOT, "profiles", "tersoff_512k_fp64_valu_counters.md")
 # wave64 VALU instruction issue: 4 cycles per instruction on each of
 # 256 CUs x 4 SIMDs at 2.4 GHz
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
-
-
-def measured_valu_insts(kind: str):
-    """VALU instructions per launch of a kernel class from the committed
-    counter summary, or None if missing or taken on other kernel sources."""
-    try:
-        text = open(COUNTER_PROFILE).read()
-    except OSError:
-        return None
-    m = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
-    if not m or m.group(1) != kernel_source_hash():
-        return None
-    m = re.search(rf"^valu\s+{re.escape(kind)}:\s*insts_per_launch=([0-9.e+]+)", text, re.M)
-    return float(m.group(1)) if m else None
 
 
 def list_statistics(ctx, pos_dev, sysm, cutoff):
@@ -296,7 +358,15 @@ def bench_mixed(W, args):
     W.ctx.set_profiling(False)
     kernels = {k: {"launches": c, "avg_us": round(1e3 * ms / c, 3)}
                for k, (c, ms) in prof.items() if c}
+    # FP32 arithmetic: the algorithmic count with each special function as one
+    # operation, against the FP32 vector peak
+    roof = path_roofline("tersoff_mixed", n, 1e3 * tmx / steps, kernels,
+                         tersoff_site_flops(W.l_list, W.k_cut, W.k_kk, UNWEIGHTED),
+                         FP32_VECTOR_PEAK_TFLOPS,
+                         algorithmic_bytes("pair_gather", W.k_cut, W.l_list, 4),
+                         algorithmic_bytes("site_partials", W.k_cut, W.l_list, 4))
     return {
+        "roofline": roof,
         "value": n * steps / tmx, "unit": "atom-steps/s", "steps": steps,
         "ms_per_step": 1e3 * tmx / steps, "rebuilds": stmx["rebuilds"],
         "fp64_same_steps_s": t64,
@@ -486,8 +556,8 @@ def bench_sw(mb, wl, torch, args):
     steps = args.sw_steps
     log(f"SW 1M: timed {steps} steps (+{args.warmup} warmup)")
     t, st, th, _, _ = W.timed("fp64", steps, args.warmup)
-    l_list, k_cut, _ = list_statistics(W.ctx, W.pos0, s,
-                                       wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
+    l_list, k_cut, k_kk = list_statistics(W.ctx, W.pos0, s,
+                                          wl.SW_SI_1985["a"] * wl.SW_SI_1985["sigma"])
     psteps = min(args.profile_steps, steps)
     W.ctx.set_profiling(True)
     W.ctx.reset_profile()
@@ -498,13 +568,20 @@ def bench_sw(mb, wl, torch, args):
                for k, (c, ms) in prof.items() if c}
     W.close()
     log(f"SW 1M: {t:.3f} s, {s.n * steps / t:.4e} atom-steps/s")
-    return {"value": s.n * steps / t, "unit": "atom-steps/s", "dtype": "f64", "steps": steps,
+    roof = path_roofline("sw_fp64", s.n, 1e3 * t / steps, kernels,
+                         sw_site_flops(l_list, k_cut, k_kk), FP64_VECTOR_PEAK_TFLOPS,
+                         algorithmic_bytes("pair_gather", k_cut, l_list, 8),
+                         algorithmic_bytes("site_partials", k_cut, l_list, 8))
+    roof["site_partials"]["flop_weights"] = FP64_WEIGHTS
+    return {"roofline": roof,
+            "value": s.n * steps / t, "unit": "atom-steps/s", "dtype": "f64", "steps": steps,
             "ms_per_step": 1e3 * t / steps, "rebuilds": st["rebuilds"],
             "energy_change_eV_per_atom": float((th[-1, 14] - th[0, 14]) / s.n),
             "kernels": kernels,
             "config": {"workload": "sw_si_diamond_50x50x50_1000000_atoms_nve", "atoms": s.n,
                        "rebuild_every": 20, "skin_A": 0.5, "seed": 1003,
-                       "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4)}}
+                       "mean_list_length": round(l_list, 4), "mean_in_cutoff": round(k_cut, 4),
+                       "mean_ordered_angles": round(k_kk, 4)}}
 
 
 def bench_serving(mb, wl, torch, args):
@@ -558,9 +635,15 @@ def bench_serving(mb, wl, torch, args):
 
 def bench_sweep(mb, wl, torch, args):
     """Throughput against system size: diamond crystals of n^3 cells
-    (N = 8 n^3), 300 K, sigma 0.05 A, both potentials and precisions, list
-    rebuilt every 20 steps, plus the Tersoff FP64 case rebuilt every 5."""
-    rows = []
+    (N = 8 n^3), 300 K, sigma 0.05 A, both potentials and precisions.
+
+    speed_vs_n: NVE, list rebuilt every 20 steps, plus the Tersoff FP64 case
+    rebuilt every 5 (the paper's rebuild-every-5 comparison).
+    speed_vs_n_npt: the protocol of the paper's size sweep (Section 3):
+    Berendsen NPT at 300 K and 0 Pa, the list built once before the run and
+    never rebuilt, --sweep-npt-steps steps (1,000 in the paper); the time
+    includes that one build and the step-0 force evaluation."""
+    rows, npt_rows = [], []
     sizes = [int(x) for x in args.sweep_cells.split(",") if x]
     for n in sizes:
         sysm = wl.silicon_crystal(n, seed=1100 + n, sigma=0.05)
@@ -573,8 +656,38 @@ def bench_sweep(mb, wl, torch, args):
                          "rebuild_every": every,
                          "atom_steps_per_s": sysm.n * args.sweep_steps / t,
                          "us_per_step": 1e6 * t / args.sweep_steps})
+        steps = args.sweep_npt_steps
+        if steps > 0:
+            for pot, prec in (("tersoff", "fp64"), ("tersoff", "mixed"), ("sw", "fp64"),
+                              ("sw", "mixed")):
+                W = Workload(mb, wl, torch, sysm, pot, steps + 1, 0.5,
+                             16 if pot == "tersoff" else 32)
+                run = lambda k, pos, vel: W.ctx.npt_run(pos, vel, sysm.box, wl.M_SI, 1.0, k,
+                                                        k + 1, precision=prec, out=W.out,
+                                                        **NPT_COUPLING)
+                run(20, W.pos0.clone(), W.vel0.clone())          # warm-up
+                pos, vel = W.pos0.clone(), W.vel0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = run(steps, pos, vel)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                st = W.ctx.run_stats()
+                th = out["thermo"][-1].cpu().numpy()
+                W.close()
+                npt_rows.append({"cells": n, "atoms": sysm.n, "potential": pot,
+                                 "precision": prec, "rebuilds": st["rebuilds"],
+                                 "atom_steps_per_s": sysm.n * steps / t,
+                                 "us_per_step": 1e6 * t / steps,
+                                 "T_end_K": round(float(th[15]), 2),
+                                 "box_end_A": round(float(out["box"][0]), 5)})
         log(f"sweep: {n}^3 cells ({sysm.n} atoms) done")
-    return {"steps": args.sweep_steps, "rows": rows}
+    res = {"nve": {"steps": args.sweep_steps, "rows": rows}}
+    if npt_rows:
+        res["npt_list_built_once"] = {
+            "steps": args.sweep_npt_steps, "ensemble": "Berendsen NPT", "coupling": NPT_COUPLING,
+            "rebuilds_per_run": 1, "rows": npt_rows}
+    return res
 
 
 def host_cpu():
@@ -589,19 +702,42 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def run_cpu_baseline(sysm, steps):
+def run_cpu_baseline(sysm, steps, steps_all):
+    """The oracle on the headline input: single-threaded for `steps` NVE
+    steps, and with OpenMP over atoms on every host CPU this process may use
+    for `steps_all` steps (per-thread force buffers summed in thread order).
+    The all-cores figure is the reported baseline; the single-thread one is
+    kept beside it."""
     import oracle
     import workload as wl
-    log(f"cpu baseline: oracle NVE, {sysm.n} atoms, {steps} steps, 1 thread")
-    t0 = time.perf_counter()
-    oracle.nve("tersoff", wl.TERSOFF_SI_1989, sysm.pos, sysm.vel, sysm.box, wl.M_SI, steps, 1.0,
-               3.5, 20, 16, check_skin=False)
-    dt = time.perf_counter() - t0
+
+    def run(threads, k):
+        used = oracle.set_threads(threads)
+        log(f"cpu baseline: oracle NVE, {sysm.n} atoms, {k} steps, {used} thread(s)")
+        t0 = time.perf_counter()
+        oracle.nve("tersoff", wl.TERSOFF_SI_1989, sysm.pos, sysm.vel, sysm.box, wl.M_SI, k, 1.0,
+                   3.5, 20, 16, check_skin=False)
+        dt = time.perf_counter() - t0
+        oracle.set_threads(1)
+        return used, dt
+
     model, ncpu = host_cpu()
-    return {"value": sysm.n * steps / dt, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sysm.n}-atom Tersoff Si, {steps} NVE steps (one list build, "
-                      f"{steps + 1} force evaluations), single thread, {dt:.1f} s",
-            "host_cpu": model, "host_logical_cpus": ncpu}
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = ncpu or 1
+    one_used, one_dt = run(1, steps)
+    all_used, all_dt = run(avail, steps_all)
+    single = {"value": sysm.n * steps / one_dt, "unit": "atom-steps/s", "cores": one_used,
+              "sample": f"{sysm.n}-atom Tersoff Si, {steps} NVE steps (one list build, "
+                        f"{steps + 1} force evaluations), {one_dt:.1f} s"}
+    return {"value": sysm.n * steps_all / all_dt, "unit": "atom-steps/s", "cores": all_used,
+            "kind": "oracle",
+            "sample": f"{sysm.n}-atom Tersoff Si, {steps_all} NVE steps "
+                      f"({1 + steps_all // 20} list build(s), {steps_all + 1} force "
+                      f"evaluations), OpenMP over atoms on {all_used} threads, {all_dt:.1f} s",
+            "single_thread": single, "host_cpu": model, "host_logical_cpus": ncpu,
+            "cpus_available": avail}
 
 
 def main():
@@ -610,7 +746,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle sample length")
+    ap.add_argument("--cpu-steps", type=int, default=10,
+                    help="oracle sample length, single thread")
+    ap.add_argument("--cpu-steps-all", type=int, default=20,
+                    help="oracle sample length on all host cores")
     ap.add_argument("--mixed-steps", type=int, default=10000)
     ap.add_argument("--mixed-check", type=int, default=1000)
     ap.add_argument("--sw-steps", type=int, default=1000)
@@ -626,6 +765,8 @@ def main():
     ap.add_argument("--sweep-cells", default="5,10,15,20,30,40,50,60,70",
                     help="cells per axis of the size sweep (empty: no sweep)")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--sweep-npt-steps", type=int, default=1000,
+                    help="steps of each run of the NPT, list-built-once size sweep (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-sw", action="store_true")
@@ -656,6 +797,7 @@ def main():
     every, skin = 20, 0.5
     W = Workload(mb, wl, torch, s, "tersoff", every, skin, 16)
     l_list, k_cut, k_kk = list_statistics(W.ctx, W.pos0, s, wl.TERSOFF_SI_1989["S"])
+    W.l_list, W.k_cut, W.k_kk = l_list, k_cut, k_kk
 
     log(f"timed FP64 run: {args.warmup} warmup + {args.steps} steps")
     t64, st64, th64, _, _ = W.timed("fp64", args.steps, args.warmup)
@@ -695,34 +837,41 @@ def main():
                          "algorithmic_bytes_per_atom": round(b, 1),
                          "achieved_GBs": round(b * n / (avg_us * 1e-6) / 1e9, 1) if b else None}
     flops_atom = tersoff_site_flops(l_list, k_cut, k_kk)
+    flops_unw = tersoff_site_flops(l_list, k_cut, k_kk, UNWEIGHTED)
     sk = kernels["site_partials"]
     sk["algorithmic_flops_per_atom"] = round(flops_atom, 1)
     sk["achieved_TFLOPs"] = round(flops_atom * n / (sk["avg_us"] * 1e-6) / 1e12, 3)
+    ms_step = 1e3 * t64 / args.steps
+    paths = {"tersoff_fp64": path_roofline(
+        "tersoff_fp64", n, ms_step, kernels, flops_atom, FP64_VECTOR_PEAK_TFLOPS,
+        algorithmic_bytes("pair_gather", k_cut, l_list, 8),
+        algorithmic_bytes("site_partials", k_cut, l_list, 8))}
+    # the dominant kernel of the headline path (longest total time)
     dom = max(("site_partials", "pair_gather"), key=lambda k: prof[k][1])
-    dk = kernels[dom]
-    traffic, traffic_parts = measured_traffic(dom)
+    pr = paths["tersoff_fp64"][dom]
+    roofline = {k: pr[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roofline["traffic"] = pr.get("traffic")
+    roofline.update({"kernel": dom, "avg_us": pr["avg_us"], "avg_us_rocprof": pr["avg_us_rocprof"],
+                     "frac_rocprof": pr.get("frac_rocprof")})
     if dom == "site_partials":
-        # bound by FP64 vector arithmetic (transcendentals), not by HBM
-        achieved = dk["achieved_TFLOPs"]
-        roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                    "traffic": traffic, "kernel": dom, "avg_us": dk["avg_us"],
-                    "algorithmic_flops_per_launch": round(flops_atom * n),
-                    "hbm_achieved_GBs": dk["achieved_GBs"]}
+        # bound by FP64 vector arithmetic (transcendentals), not by HBM; the
+        # special functions weighted by the FP64 operations of their
+        # implementation, and, beside it, each taken as one operation
+        roofline.update({
+            "algorithmic_flops_per_launch": round(flops_atom * n), "flop_weights": FP64_WEIGHTS,
+            "achieved_unweighted": round(flops_unw * n / (pr["avg_us"] * 1e-6) / 1e12, 3),
+            "hbm_achieved_GBs": pr["hbm_GBs"]})
+        roofline["frac_unweighted"] = round(roofline["achieved_unweighted"] /
+                                            FP64_VECTOR_PEAK_TFLOPS, 4)
+        if "valu_issue_frac" in pr:
+            roofline["valu_issue_frac"] = pr["valu_issue_frac"]
     else:
-        achieved = dk["achieved_GBs"]
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": dom, "avg_us": dk["avg_us"],
-                    "algorithmic_bytes_per_launch": round(dk["algorithmic_bytes_per_atom"] * n)}
-    if traffic_parts:
-        roofline["traffic_parts"] = traffic_parts
-    insts = measured_valu_insts(dom)
-    if insts is not None:
-        # share of the kernel's time the vector units spend issuing its
-        # counted VALU instructions (counters from the committed summary)
-        roofline["valu_issue_frac"] = round(insts / VALU_ISSUE_PER_S / (dk["avg_us"] * 1e-6), 4)
-    log(f"dominant kernel {dom}: {dk['avg_us']} us, {achieved} {roofline['unit']}")
+        roofline["algorithmic_bytes_per_launch"] = round(pr["algorithmic_bytes_per_atom"] * n)
+    t = profile_value("tersoff_512k_fp64_hbm_traffic.md",
+                      rf"^traffic\s+{dom}:\s*fetch_bytes=([0-9.e+]+)\s+write_bytes=([0-9.e+]+)")
+    if t:
+        roofline["traffic_parts"] = {"fetch": float(t[0]), "write": float(t[1])}
+    log(f"dominant kernel {dom}: {pr['avg_us']} us, {pr['achieved']} {pr['unit']}")
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib * (1 << 20)
@@ -747,7 +896,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(s, args.cpu_steps)
+        cpu = run_cpu_baseline(s, args.cpu_steps, args.cpu_steps_all)
         log(f"cpu baseline: {cpu['value']:.4e} atom-steps/s")
 
     line = {
@@ -779,8 +928,11 @@ def main():
         "sic_512k": sic,
         "sw_1m": sw,
         "serving": serve,
-        "speed_vs_n": sweep,
+        "speed_vs_n": sweep["nve"] if sweep else None,
+        "speed_vs_n_npt": sweep.get("npt_list_built_once") if sweep else None,
         "roofline": roofline,
+        "paths": dict(paths, **({"tersoff_mixed": mixed["roofline"]} if mixed else {}),
+                      **({"sw_fp64": sw["roofline"]} if sw else {})),
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

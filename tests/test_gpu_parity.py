@@ -167,6 +167,19 @@ def test_full_size_fp64_parity(pot):
         assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
 
 
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_largest_sweep_size_fp64_parity(pot):
+    """The largest crystal of the size sweep, 70^3 cells = 2,744,000 atoms
+    (seed 1170, the sweep's input): every atom's U, F, W, J against the
+    oracle (a 1.26M-cell grid for Tersoff, lists of 16 for SW)."""
+    s = wl.silicon_crystal(70, seed=1170, sigma=0.05)
+    ref = oracle_compute(pot, s, maxnb=32)
+    with context(pot) as ctx:
+        got = gpu_compute(ctx, s)
+    for k in ("U", "F", "W", "J"):
+        assert rel(got[k], ref[k]) <= TOL_FP64, (k, rel(got[k], ref[k]))
+
+
 def test_full_size_mixed_force_error():
     s = _full("tersoff")
     ref = oracle_compute("tersoff", s, maxnb=32)
