@@ -222,6 +222,25 @@ mbmd_status mbmd_compute(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
                          const double *pos, const double *vel, const int32_t *types,
                          double *U, double *F, double *W, double *J);
 
+/* mbmd_compute for callers that cannot allocate memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit for bit) as mbmd_compute, but the
+ * call's whole workspace lies in a static device array of the library
+ * (64 MiB on each device the library runs on, held until the process ends)
+ * instead of the context's workspace, and the call makes no hipMalloc,
+ * hipFree, pinned-memory or other allocating call; profiling is off for it.
+ * The array holds the workspace of about 76,000 Tersoff atoms at 16 list
+ * slots (the need grows with max_neighbors: about 48,000 SW atoms at 32);
+ * a larger n is refused with MBMD_ENOMEM.  Every call on one device shares
+ * that device's array and leaves its contents there (the call clears what
+ * it needs cleared), so calls that overlap on one device, from any contexts
+ * or streams, race: serialise them.  Like every call it ends by
+ * synchronising the context's stream. */
+mbmd_status mbmd_compute_noalloc(mbmd_ctx *ctx, mbmd_precision prec, int64_t n,
+                                 const double box[3], const double *pos, const double *vel,
+                                 const int32_t *types, double *U, double *F, double *W,
+                                 double *J);
+
 /* n_steps of NVE velocity-Verlet integration (the integrator of Section 3,
  * without thermostat or barostat) at time step dt_fs for atoms of mass
  * mass_amu.  pos[3][n] and vel[3][n] (device) are advanced in place.  The

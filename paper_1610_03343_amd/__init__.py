@@ -85,6 +85,7 @@ def _load():
         "mbmd_bind_workspace": ([P, P, C.c_size_t], I),
         "mbmd_neighbors": ([P, I64, P, P, P, P, P], I),
         "mbmd_compute": ([P, I, I64, P, P, P, P, P, P, P, P], I),
+        "mbmd_compute_noalloc": ([P, I, I64, P, P, P, P, P, P, P, P], I),
         "mbmd_nve_run": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
         "mbmd_nve_continue": ([P, I, I64, P, D, P, P, P, D, I, I, P, P, P, P, P], I),
         "mbmd_npt_run": ([P, I, I64, P, D, P, P, P, D, I, I, C.POINTER(mbmd_berendsen), P, P,
@@ -296,6 +297,19 @@ class Context:
             _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32),
             _dptr(out["U"], (n,), "U"), _dptr(out["F"], (3, n), "F"),
             _dptr(out["W"], (9, n), "W"), _dptr(out["J"], (3, n), "J")), "mbmd_compute")
+        return out
+
+    def compute_noalloc(self, pos, box, out, vel=None, types=None, precision="fp64"):
+        """mbmd_compute_noalloc: the single point of compute() with the
+        workspace in the library's static device scratch; allocates nothing,
+        so the caller passes the outputs (dict U, F, W, J)."""
+        n = pos.shape[1]
+        self._check(_lib.mbmd_compute_noalloc(
+            self._h, _prec(precision), n, _box(box), _dptr(pos, (3, n), "pos"),
+            _dptr(vel, (3, n), "vel"), _dptr(types, (n,), "types", torch.int32),
+            _dptr(out["U"], (n,), "U"), _dptr(out["F"], (3, n), "F"),
+            _dptr(out["W"], (9, n), "W"), _dptr(out["J"], (3, n), "J")),
+            "mbmd_compute_noalloc")
         return out
 
     def nve_run(self, pos, vel, box, mass, dt, n_steps, rebuild_every=20, types=None,

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,35 @@
 #include "mbmd_internal.h"
 
 using namespace mbmd;
+
+// Device scratch of mbmd_compute_noalloc: the whole workspace of one single
+// point, so that entry point allocates nothing.  Each device holds its own
+// copy while the process runs; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device (kept in scratch_ptr), never by
+// its name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+bool scratch_looked_up[kScratchDevices] = {};
+hipError_t scratch_err[kScratchDevices] = {};
+void* scratch_ptr[kScratchDevices] = {};
+
+// Looks up the scratch's address on `device` once (that device current).
+void lookup_scratch(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_looked_up[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    scratch_err[device] = e;
+    scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    scratch_looked_up[device] = true;
+}
+}  // namespace
 
 namespace {
 // Kernel classes timed by the optional HIP-event profile.
@@ -554,12 +584,19 @@ double* ring_row(mbmd_ctx* c, int row)
 mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
                          const int32_t* types, int nsteps, double mass, double dt, double* vel,
                          double* U, double* F, double* W, double* J, int* total_cells,
-                         bool dt_run = false)
+                         bool dt_run = false, char* scratch_base = nullptr)
 {
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     c->resume.valid = false;     // this call reuses the workspace
-    mbmd_status s = ensure_workspace(c, n, 1, false);
-    if (s != MBMD_OK) return s;
+    if (scratch_base) {
+        // the call's whole workspace is laid out over the device scratch; the
+        // next ordinary call lays out the context's own workspace again
+        layout(n, resolved_M(c), 1, false, scratch_base, &c->buf);
+        c->laid_cap = -1;
+    } else {
+        mbmd_status s = ensure_workspace(c, n, 1, false);
+        if (s != MBMD_OK) return s;
+    }
     Buffers& b = c->buf;
     b.vel = vel;
     b.U = U;
@@ -1066,6 +1103,9 @@ mbmd_status mbmd_create(mbmd_ctx** out, int device, void* hip_stream)
     if (!c) return MBMD_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the address of the no-allocation scratch on this device (once per
+    // device; a failure is reported by mbmd_compute_noalloc)
+    lookup_scratch(device);
     *out = c;
     return MBMD_OK;
 }
@@ -1324,6 +1364,56 @@ mbmd_status mbmd_compute(mbmd_ctx* c, mbmd_precision prec, int64_t n, const doub
     if (!pos || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
     if (prec == MBMD_MIXED) return compute_impl<float>(c, n, b, pos, vel, types, U, F, W, J);
     return compute_impl<double>(c, n, b, pos, vel, types, U, F, W, J);
+}
+
+mbmd_status mbmd_compute_noalloc(mbmd_ctx* c, mbmd_precision prec, int64_t n,
+                                 const double box[3], const double* pos, const double* vel,
+                                 const int32_t* types, double* U, double* F, double* W,
+                                 double* J)
+{
+    if (!c) return MBMD_EINVAL;
+    Box b{};
+    mbmd_status s = common_checks(c, n, box, &b);
+    if (s != MBMD_OK) return s;
+    if (prec != MBMD_FP64 && prec != MBMD_MIXED) return fail(c, MBMD_EINVAL, "bad precision%s");
+    if (n == 0) return MBMD_OK;
+    if (!pos || !U || !F || !W || !J) return fail(c, MBMD_EINVAL, "null device pointer%s");
+    if (c->device < 0 || c->device >= kScratchDevices || !scratch_ptr[c->device]) {
+        char msg[256];
+        snprintf(msg, sizeof msg, "no device scratch on device %d (%s)", c->device,
+                 c->device >= 0 && c->device < kScratchDevices
+                     ? hipGetErrorString(scratch_err[c->device]) : "device index too large");
+        c->err = msg;
+        return MBMD_EDEVICE;
+    }
+    const size_t need = layout(n, resolved_M(c), 1, false, nullptr, nullptr);
+    if (need > kScratchBytes) {
+        char msg[256];
+        snprintf(msg, sizeof msg,
+                 "%lld atoms need %zu bytes of workspace, more than the %zu-byte static "
+                 "scratch of mbmd_compute_noalloc", (long long)n, need, kScratchBytes);
+        c->err = msg;
+        return MBMD_ENOMEM;
+    }
+    // no HIP events either: profiling is off for this call
+    const bool prof = c->profiling;
+    c->profiling = false;
+    int cells = 0;
+    s = begin_single(c, n, b, pos, types, 0, 0.0, 0.0, const_cast<double*>(vel), U, F, W, J,
+                     &cells, false, static_cast<char*>(scratch_ptr[c->device]));
+    hipError_t e = hipSuccess;
+    if (s == MBMD_OK) {
+        // no list counts are read back (that needs pinned host memory): the
+        // overflow pass is enqueued and exits at once if no site overflowed
+        e = build(c, cells, 0, false);
+        c->max_nn = kMaxSlots;
+        if (e == hipSuccess)
+            e = prec == MBMD_MIXED ? force_step<float>(c, 0, false, nullptr, nullptr)
+                                   : force_step<double>(c, 0, false, nullptr, nullptr);
+        s = e != hipSuccess ? hip_fail(c, e, "compute launch") : finish(c);
+    }
+    c->profiling = prof;
+    return s;
 }
 
 mbmd_status mbmd_nve_run(mbmd_ctx* c, mbmd_precision prec, int64_t n, const double box[3],
