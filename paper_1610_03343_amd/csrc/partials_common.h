@@ -61,6 +61,45 @@ __device__ __forceinline__ float nr_rsqrt(float x)
     return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
 }
 
+// A 64-bit constant placed in scalar registers where it is used: moved there
+// by the scalar unit, then read as the scalar operand of a vector
+// instruction.  Written as a plain literal, a coefficient can instead be
+// moved into vector registers, two vector instructions per use, in kernels
+// whose scalar registers are otherwise full.
+__device__ __forceinline__ double sgpr_const(double c)
+{
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
+// e^x for |x| < 708 (the range of every exponential of the potentials
+// here: bond terms of lengths inside the cutoff, the bond order's
+// (beta zeta)^n): x = k ln 2 + r with k = rint(x / ln 2) and |r| <= ln 2 / 2
+// by Cody and Waite's reduction (ln 2 as its double and the rounded
+// remainder, each product exact in the fused multiply-add), e^r by its
+// Taylor series to r^13 (truncation below 5e-18 relative), and 2^k applied
+// exactly.  Within 1 ulp of the correctly rounded e^x.
+__device__ __forceinline__ double fast_exp(double x)
+{
+    const double k = rint(x * sgpr_const(0x1.71547652b82fep+0));
+    double r = fma(-k, sgpr_const(0x1.62e42fefa39efp-1), x);
+    r = fma(-k, sgpr_const(0x1.abc9e3b39803fp-56), r);
+    double p = fma(sgpr_const(0x1.6124613a86d09p-33), r, sgpr_const(0x1.1eed8eff8d898p-29));
+    p = fma(p, r, sgpr_const(0x1.ae64567f544e4p-26));
+    p = fma(p, r, sgpr_const(0x1.27e4fb7789f5cp-22));
+    p = fma(p, r, sgpr_const(0x1.71de3a556c734p-19));
+    p = fma(p, r, sgpr_const(0x1.a01a01a01a01ap-16));
+    p = fma(p, r, sgpr_const(0x1.a01a01a01a01ap-13));
+    p = fma(p, r, sgpr_const(0x1.6c16c16c16c17p-10));
+    p = fma(p, r, sgpr_const(0x1.1111111111111p-7));
+    p = fma(p, r, sgpr_const(0x1.5555555555555p-5));
+    p = fma(p, r, sgpr_const(0x1.5555555555555p-3));
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
 // Bit m of the returned mask is set iff list slot m of atom i is inside the
 // cutoff (r^2 < rc2).
 __device__ __forceinline__ unsigned long long cutoff_mask(const double4& xi, int64_t i, int64_t cap,

@@ -43,7 +43,7 @@ SWK<T> sw_constants(const SWParams& p)
     return k;
 }
 
-__device__ __forceinline__ double s_exp(double x) { return exp(x); }
+__device__ __forceinline__ double s_exp(double x) { return fast_exp(x); }
 __device__ __forceinline__ float s_exp(float x) { return expf(x); }
 __device__ __forceinline__ double s_pow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float s_pow(float x, float y) { return powf(x, y); }

@@ -180,7 +180,7 @@ __device__ __forceinline__ void fill_lds_table(const TersoffArg<T, true>& K, Ter
     __syncthreads();
 }
 
-__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+__device__ __forceinline__ double t_exp(double x) { return fast_exp(x); }
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 // Natural logarithm of a positive normal double for the bond order, from
 // ln x = e ln 2 + ln m with x = m 2^e, m in [sqrt(1/2), sqrt(2)), and the
@@ -190,28 +190,28 @@ __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 // arithmetic; (beta zeta)^n needs far less.
 __device__ __forceinline__ double t_log(double x)
 {
+    // (the constants go through scalar registers: see sgpr_const)
     int e;
     double m = frexp(x, &e);               // x = m 2^e, m in [0.5, 1)
-    if (m < 0.70710678118654752440) {
+    if (m < sgpr_const(0.70710678118654752440)) {
         m *= 2.0;
         e -= 1;
     }
     const double s = (m - 1.0) * nr_rcp(m + 1.0);
     const double s2 = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, s2, 1.0 / 19.0);
-    p = fma(p, s2, 1.0 / 17.0);
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
-    p = fma(p, s2, 1.0 / 7.0);
-    p = fma(p, s2, 1.0 / 5.0);
-    p = fma(p, s2, 1.0 / 3.0);
+    double p = fma(sgpr_const(1.0 / 21.0), s2, sgpr_const(1.0 / 19.0));
+    p = fma(p, s2, sgpr_const(1.0 / 17.0));
+    p = fma(p, s2, sgpr_const(1.0 / 15.0));
+    p = fma(p, s2, sgpr_const(1.0 / 13.0));
+    p = fma(p, s2, sgpr_const(1.0 / 11.0));
+    p = fma(p, s2, sgpr_const(1.0 / 9.0));
+    p = fma(p, s2, sgpr_const(1.0 / 7.0));
+    p = fma(p, s2, sgpr_const(1.0 / 5.0));
+    p = fma(p, s2, sgpr_const(1.0 / 3.0));
     const double lnm = 2.0 * s + 2.0 * s * s2 * p;
     // ln 2 = ln2_hi + ln2_lo, ln2_hi with 32 significant bits (e * ln2_hi is
     // exact for |e| < 2^21), ln2_lo the rounded remainder
-    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    const double ln2_hi = sgpr_const(0x1.62e42fee00000p-1), ln2_lo = sgpr_const(0x1.a39ef35793c76p-33);
     const double de = (double)e;
     return fma(de, ln2_hi, fma(de, ln2_lo, lnm));
 }
@@ -433,8 +433,11 @@ __device__ __forceinline__ unsigned long long quad_cutoff_mask_typed(
 // Partner terms of the partials of the quad site pass: for each own bond c
 // and partner bond e of the same atom (fetched from the other lanes),
 //   dU_i/dr_c += -1/2 (P_c f_C(r_e) + P_e f_C(r_c)) g'(cos_ce) (u_e - cos_ce u_c) / r_c
-//               [- 1/2 P_e f_C'(r_c) g(cos_ce) u_c   when TAPER].
-template <class T, int SLOTS, bool TAPER, class P>
+//               - 1/2 P_e f_C'(r_c) g(cos_ce) u_c.
+// FULL: every bond of the wave lies below R, where f_C = 1 and f_C' = 0, so
+// the partners' f_C are not fetched and the last term vanishes (the same
+// values: products by 1 and sums with 0 are exact).
+template <class T, int SLOTS, bool FULL, class P>
 __device__ __forceinline__ void tersoff_partner_terms(
     const P& pc, int q, int kc, int tmax, const T (&ux)[SLOTS], const T (&uy)[SLOTS],
     const T (&uz)[SLOTS], const T (&ir)[SLOTS], const T (&fc)[SLOTS], const T (&dfc)[SLOTS],
@@ -449,7 +452,7 @@ __device__ __forceinline__ void tersoff_partner_terms(
             const T ex = k ? quad_xor(ux[t], k) : ux[t];
             const T ey = k ? quad_xor(uy[t], k) : uy[t];
             const T ez = k ? quad_xor(uz[t], k) : uz[t];
-            const T ef = k ? quad_xor(fc[t], k) : fc[t];
+            const T ef = FULL ? T(1) : (k ? quad_xor(fc[t], k) : fc[t]);
             const T ep = k ? quad_xor(zp[t], k) : zp[t];
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
@@ -464,16 +467,17 @@ __device__ __forceinline__ void tersoff_partner_terms(
                     } else {
                         angular_g(pc, cs, g, dg);
                     }
-                    const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
-                    if constexpr (TAPER) {
+                    if constexpr (FULL) {
+                        const T a = T(-0.5) * (zp[s] + ep) * dg * ir[s];
+                        gx[s] += a * (ex - cs * ux[s]);
+                        gy[s] += a * (ey - cs * uy[s]);
+                        gz[s] += a * (ez - cs * uz[s]);
+                    } else {
+                        const T a = T(-0.5) * (zp[s] * ef + ep * fc[s]) * dg * ir[s];
                         const T bb = T(-0.5) * ep * dfc[s] * g;
                         gx[s] += a * (ex - cs * ux[s]) + bb * ux[s];
                         gy[s] += a * (ey - cs * uy[s]) + bb * uy[s];
                         gz[s] += a * (ez - cs * uz[s]) + bb * uz[s];
-                    } else {
-                        gx[s] += a * (ex - cs * ux[s]);
-                        gy[s] += a * (ey - cs * uy[s]);
-                        gz[s] += a * (ez - cs * uz[s]);
                     }
                 }
             }
@@ -575,6 +579,11 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
         }
     }
     const int tmax = wave_partner_slots<SLOTS>(kc);
+    // every bond of the wave below R (f_C = 1, f_C' = 0): wave-uniform
+    bool partial = false;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) partial = partial || (q + kQuad * s < kc && fc[s] != T(1));
+    const bool full = !__any(partial);
 
     // zeta_c = sum over partner bonds e != c of f_C(r_e) g(cos_ce).  g and g'
     // of the angles between first-slot bonds (every angle of an atom with at
@@ -609,11 +618,20 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
         dg0[2] = dgB;
         g0[3] = even ? gP : gA;
         dg0[3] = even ? dgP : dgA;
-        const T ef1 = quad_xor_k<1>(fc[0]), ef2 = quad_xor_k<2>(fc[0]), ef3 = quad_xor_k<3>(fc[0]);
-        if (q < kc) {
-            if ((q ^ 1) < kc) zp[0] += ef1 * g0[1];
-            if ((q ^ 2) < kc) zp[0] += ef2 * g0[2];
-            if ((q ^ 3) < kc) zp[0] += ef3 * g0[3];
+        if (full) {   // wave-uniform: partners' f_C are 1
+            if (q < kc) {
+                if ((q ^ 1) < kc) zp[0] += g0[1];
+                if ((q ^ 2) < kc) zp[0] += g0[2];
+                if ((q ^ 3) < kc) zp[0] += g0[3];
+            }
+        } else {
+            const T ef1 = quad_xor_k<1>(fc[0]), ef2 = quad_xor_k<2>(fc[0]),
+                    ef3 = quad_xor_k<3>(fc[0]);
+            if (q < kc) {
+                if ((q ^ 1) < kc) zp[0] += ef1 * g0[1];
+                if ((q ^ 2) < kc) zp[0] += ef2 * g0[2];
+                if ((q ^ 3) < kc) zp[0] += ef3 * g0[3];
+            }
         }
     }
 #pragma unroll
@@ -666,19 +684,17 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     if (q == 0 && kc > 0) U[i] = 0.5 * u_i;
     if (q == 0 && valid && !ovf && kc == 0) U[i] = 0.0;
 
-    // partials dU_i/dr_c.  The term in f_C'(r_c) vanishes for bonds below
-    // R; a wave none of whose bonds is in the taper skips it (a uniform
-    // branch, so only one body is issued).
+    // partials dU_i/dr_c.  A wave all of whose bonds lie below R takes the
+    // body without f_C and f_C' (a uniform branch, so only one body is
+    // issued).
     T gx[SLOTS], gy[SLOTS], gz[SLOTS];
-    bool taper = false;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         gx[s] = T(0.5) * pd[s] * ux[s];
         gy[s] = T(0.5) * pd[s] * uy[s];
         gz[s] = T(0.5) * pd[s] * uz[s];
-        taper = taper || dfc[s] != T(0);
     }
-    if (__any(taper))
+    if (full)
         tersoff_partner_terms<T, SLOTS, true>(pc, q, kc, tmax, ux, uy, uz, ir, fc, dfc, zp, g0, dg0,
                                               gx, gy, gz);
     else
