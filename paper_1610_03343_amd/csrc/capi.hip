@@ -579,12 +579,17 @@ double* ring_row(mbmd_ctx* c, int row)
 
 // ---- one structure ----------------------------------------------------------
 
-// Sets up a one-segment launch set over caller-owned arrays and stages the
-// positions into buffer 0.
+// Sets up a one-segment launch set over caller-owned arrays and (unless
+// `stage` is false: the caller stages them with its first kernel) stages the
+// positions into buffer 0.  The table entry goes to the device as a kernel
+// argument of the launch that also clears the status, overflow and phase
+// words (and, with clear_disp, the first step-displacement slot): two
+// launches and no host-to-device copy.
 mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* pos,
                          const int32_t* types, int nsteps, double mass, double dt, double* vel,
                          double* U, double* F, double* W, double* J, int* total_cells,
-                         bool dt_run = false, char* scratch_base = nullptr)
+                         bool dt_run = false, char* scratch_base = nullptr, bool stage = true,
+                         bool clear_disp = false)
 {
     if (c->batch) return fail(c, MBMD_EINVAL, "a serving batch is open on this context%s");
     c->resume.valid = false;     // this call reuses the workspace
@@ -611,11 +616,11 @@ mbmd_status begin_single(mbmd_ctx* c, int64_t n, const Box& box, const double* p
     g.build = 1;
     c->segs_host.assign(1, g);
     c->pp = 0;
-    hipError_t e = upload_segs(c, total_cells);
-    if (e == hipSuccess) e = launch_fill_int((int*)b.status, 1, 0, c->stream);
-    if (e == hipSuccess) e = launch_fill_int(b.ovf_count, 1, 0, c->stream);
-    if (e == hipSuccess) e = launch_fill_int(b.phase[0], 1, 0, c->stream);
-    if (e == hipSuccess) {
+    assign_offsets(c, total_cells);
+    hipError_t e = launch_begin_single(c->segs_host[0], b.seg, b.status, b.ovf_count, b.phase[0],
+                                       clear_disp ? (int*)b.step_disp2 : nullptr,
+                                       clear_disp ? 2 : 0, c->stream);
+    if (e == hipSuccess && stage) {
         ProfScope ps(c, P_STAGE);
         e = launch_load_positions(pos, types, ntypes_of(c), n, box, 0, b.xw[0], b.status,
                                   c->stream);
@@ -647,6 +652,18 @@ hipError_t flush_thermo(mbmd_ctx* c, double* thermo)
     hipError_t e = launch_thermo_fold(c->buf, c->segs, 0, c->fold_from, c->fold_to - c->fold_from,
                                       0, thermo, c->stream);
     c->fold_from = c->fold_to;
+    return e;
+}
+
+// End of a one-structure run: the pending thermo rows and the final
+// positions (buffer cur) back to the caller, in one launch.
+hipError_t end_single(mbmd_ctx* c, double* thermo, int cur, double* pos)
+{
+    const int count = thermo && c->fold_to > c->fold_from ? c->fold_to - c->fold_from : 0;
+    ProfScope ps(c, P_THERMO);
+    hipError_t e = launch_end_single(c->buf, c->segs, c->fold_from, count, thermo, cur, pos,
+                                     c->stream);
+    if (thermo) c->fold_from = c->fold_to;
     return e;
 }
 
@@ -705,8 +722,13 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
     // ring the previous run left in the workspace
     const ResumeState prev = c->resume;
     int cells = 0;
+    // a continuation that takes steps stages the positions with its prologue
+    // (whose displacement from the list-build positions is tracked under the
+    // skin policy unless the schedule rebuilds at step 1 anyway)
+    const bool fused = resume && n_steps > 0;
+    const bool chk = fused && c->policy == MBMD_REBUILD_ON_SKIN && 1 + prev.since_build != every;
     mbmd_status s = begin_single(c, n, box, pos, types, n_steps, mass, dt, vel, U, F, W, J,
-                                 &cells, true);
+                                 &cells, true, nullptr, !fused, chk);
     if (s != MBMD_OK) return s;
     const Buffers& b = c->buf;
     mbmd_run_stats st{};
@@ -725,14 +747,15 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         // half-kick and drift its last step left out come first.
         last_build = -prev.since_build;
         c->fold_from = c->fold_to = 1;
-        if (thermo) e = launch_thermo_fold(b, c->segs, 0, 0, 1, prev.ring_row, thermo, c->stream);
-        if (e == hipSuccess && n_steps > 0) {
-            const bool chk = c->policy == MBMD_REBUILD_ON_SKIN && (1 - last_build) != every;
-            if (chk) e = launch_fill_int((int*)b.step_disp2, 2, 0, c->stream);
-            if (e == hipSuccess)
-                e = launch_kick_drift(b, c->segs, cur, chk ? b.step_disp2 : nullptr, c->stream);
+        if (!fused && thermo)
+            e = launch_thermo_fold(b, c->segs, 0, 0, 1, prev.ring_row, thermo, c->stream);
+        if (e == hipSuccess && fused) {
+            // one launch: staging, half-kick and drift into buffer 1, the
+            // previous run's last thermo row, and the phase of step 1
+            e = launch_resume_prologue(b, c->segs, pos, types, ntypes_of(c), cur,
+                                       chk ? b.step_disp2 : nullptr, prev.ring_row, thermo,
+                                       b.phase[c->pp], 1, c->stream);
             cur = 1;
-            if (e == hipSuccess) e = launch_fill_int(b.phase[c->pp], 1, 1, c->stream);
             if (e == hipSuccess && chk) {
                 unsigned long long bits = 0;
                 e = hipMemcpyAsync(&bits, b.step_disp2, sizeof bits, hipMemcpyDeviceToHost,
@@ -769,8 +792,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
             if (e == hipSuccess) e = md_step<T>(c, step, cur, false, nullptr, thermo);
             cur ^= 1;
         }
-        if (e == hipSuccess) e = flush_thermo(c, thermo);
-        if (e == hipSuccess) e = launch_store_positions(b.xw[cur], 0, n, pos, c->stream);
+        if (e == hipSuccess) e = end_single(c, thermo, cur, pos);
         if (e != hipSuccess) return hip_fail(c, e, "nve launch");
         s = finish(c);
         st.max_displacement = -1.0;
@@ -852,8 +874,7 @@ mbmd_status nve_impl(mbmd_ctx* c, int64_t n, const Box& box, double mass, double
         ++st.rollbacks;
         chunk = bad - cs > 0 ? bad - cs : 1;
     }
-    if (e == hipSuccess) e = flush_thermo(c, thermo);
-    if (e == hipSuccess) e = launch_store_positions(b.xw[cur], 0, n, pos, c->stream);
+    if (e == hipSuccess) e = end_single(c, thermo, cur, pos);
     if (e != hipSuccess) return hip_fail(c, e, "nve launch");
     s = finish(c);
     st.max_displacement = std::sqrt(committed_max2);

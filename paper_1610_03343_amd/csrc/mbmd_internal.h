@@ -208,11 +208,39 @@ __device__ __forceinline__ double wrap_coord(double x, double L)
     return r;
 }
 
+// Atom i of a caller's positions pos[3][n] as the workspace holds it:
+// wrapped into the box, type in w.  A non-finite coordinate raises
+// ST_NONFINITE (the atom is placed at the origin) and a type outside
+// [0, ntypes) raises ST_TYPES (stored as 0).
+__device__ __forceinline__ double4 staged_position(const double* __restrict__ pos,
+                                                   const int32_t* __restrict__ types, int ntypes,
+                                                   int64_t n, int64_t i, const Box& box,
+                                                   unsigned* __restrict__ status)
+{
+    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        atomicOr(status, ST_NONFINITE);
+        x = y = z = 0.0;
+    }
+    int t = types ? types[i] : 0;
+    if (t < 0 || t >= ntypes) {
+        atomicOr(status, ST_TYPES);
+        t = 0;
+    }
+    return make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]), wrap_coord(z, box.L[2]),
+                        (double)t);
+}
+
 __host__ __device__ inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 __host__ __device__ inline int quad_blocks_for(int64_t n) { return (int)((n + kQuadAtoms - 1) / kQuadAtoms); }
 
 // ---- launchers (host) -----------------------------------------------------
 hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s);
+// Start of a one-structure call in one launch: writes the segment table's
+// single entry g (passed by value) to dst, clears the status word, the
+// overflow count and the phase word, and zeroes clear[0 .. nclear).
+hipError_t launch_begin_single(const Seg& g, Seg* dst, unsigned* status, int* ovf_count,
+                               int* phase0, int* clear, int nclear, hipStream_t s);
 // Wraps positions pos[3][n] into xw[atom_off ..).
 // Types (null: all 0) go to the w component; a type outside [0, ntypes)
 // raises ST_TYPES and is stored as 0.
@@ -319,11 +347,22 @@ size_t gk_scratch_bytes(int64_t S, int max_lag);
 hipError_t launch_green_kubo(const double* thermo, int64_t S, int every, int max_lag,
                              double scale, double* scratch, double* hac, double* kappa,
                              hipStream_t s);
-// Continuation: v <- v + (dt/2) kappa F / m, x <- wrap(x + dt v) from
-// buffer cur into cur ^ 1 (the pairwise pass's arithmetic); with slot (or
-// null) the largest squared displacement from the list-build positions.
-hipError_t launch_kick_drift(const Buffers& b, const Segs& S, int cur,
-                             unsigned long long* slot, hipStream_t s);
+// End of a one-structure run (single segment at atom 0) in one launch:
+// positions of buffer cur back to pos[3][n], and thermo rows first ..
+// first + count - 1 folded from the ring (ring row = step % kThermoRing).
+hipError_t launch_end_single(const Buffers& b, const Segs& S, int first, int count,
+                             double* thermo, int cur, double* pos, hipStream_t s);
+// Continued one-structure run (single segment at atom 0): stages the
+// caller's positions pos[3][n] and applies v <- v + (dt/2) kappa F / m,
+// x <- wrap(x + dt v) (the pairwise pass's arithmetic) into buffer cur ^ 1
+// in one launch, with slot (or null) taking the largest squared
+// displacement from the list-build positions; with thermo (or null) ring row
+// ring_row is folded into thermo row 0 by one extra block; *phase_word
+// receives phase.
+hipError_t launch_resume_prologue(const Buffers& b, const Segs& S, const double* pos,
+                                  const int32_t* types, int ntypes, int cur,
+                                  unsigned long long* slot, int ring_row, double* thermo,
+                                  int* phase_word, int phase, hipStream_t s);
 // Weak coupling: v <- lambda v + (dt/2) kappa F / m, x <- wrap(mu x + dt v)
 // in the (already scaled) box, in place in position buffer `cur`.
 hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_t s);

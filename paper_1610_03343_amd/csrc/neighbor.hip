@@ -42,6 +42,28 @@ hipError_t launch_fill_int(int* p, int64_t count, int value, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_begin_single(Seg g, Seg* __restrict__ dst, unsigned* __restrict__ status,
+                               int* __restrict__ ovf_count, int* __restrict__ phase0,
+                               int* __restrict__ clear, int nclear)
+{
+    if (threadIdx.x == 0) {
+        *dst = g;
+        *status = 0u;
+        *ovf_count = 0;
+        *phase0 = 0;
+    }
+    for (int k = threadIdx.x; k < nclear; k += blockDim.x) clear[k] = 0;
+}
+
+hipError_t launch_begin_single(const Seg& g, Seg* dst, unsigned* status, int* ovf_count,
+                               int* phase0, int* clear, int nclear, hipStream_t s)
+{
+    if (!dst || !status || !ovf_count || !phase0 || (nclear > 0 && !clear))
+        return hipErrorInvalidValue;
+    k_begin_single<<<1, 64, 0, s>>>(g, dst, status, ovf_count, phase0, clear, nclear);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ types, int ntypes,
                  int64_t n, Box box, int atom_off, double4* __restrict__ xw,
@@ -49,18 +71,7 @@ k_load_positions(const double* __restrict__ pos, const int32_t* __restrict__ typ
 {
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= n) return;
-    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-        atomicOr(status, ST_NONFINITE);
-        x = y = z = 0.0;
-    }
-    int t = types ? types[i] : 0;
-    if (t < 0 || t >= ntypes) {
-        atomicOr(status, ST_TYPES);
-        t = 0;
-    }
-    xw[atom_off + i] = make_double4(wrap_coord(x, box.L[0]), wrap_coord(y, box.L[1]),
-                                    wrap_coord(z, box.L[2]), (double)t);
+    xw[atom_off + i] = staged_position(pos, types, ntypes, n, i, box, status);
 }
 
 hipError_t launch_load_positions(const double* pos_soa, const int32_t* types, int ntypes,

@@ -288,6 +288,44 @@ hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int firs
     return hipGetLastError();
 }
 
+// End of a one-structure run in one launch: blocks 0 .. nblk - 1 copy the
+// final positions xw back to the caller's pos[3][n] (as the store kernel
+// does), blocks nblk .. nblk + count - 1 fold thermo rows first .. first +
+// count - 1 from the ring (as k_thermo_fold with ring0 = 0).
+__global__ void __launch_bounds__(kFoldThreads)
+k_end_single(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int first,
+             double* __restrict__ thermo, const double4* __restrict__ xw,
+             double* __restrict__ pos)
+{
+    __shared__ double lds[kFoldThreads / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    const Seg& g = S.seg[0];
+    if ((int)blockIdx.x >= S.nblk) {
+        const int k = first + (int)blockIdx.x - S.nblk;
+        const double* rowp = part_b + (int64_t)(k % kThermoRing) * blk_cap * kPartialCols;
+        fold_segment_row(rowp, g, lds, lds_tot, thermo + (int64_t)k * kThermoCols);
+        return;
+    }
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, S.nblk) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const double4 p = xw[i];
+    pos[i] = p.x;
+    pos[g.n + i] = p.y;
+    pos[2 * g.n + i] = p.z;
+}
+
+hipError_t launch_end_single(const Buffers& b, const Segs& S, int first, int count,
+                             double* thermo, int cur, double* pos, hipStream_t s)
+{
+    if (!segs_ready(S, b) || S.nseg != 1 || !pos || count < 0 || (count > 0 && !thermo))
+        return hipErrorInvalidValue;
+    const int grid = S.nblk + count;
+    if (grid <= 0) return hipSuccess;
+    k_end_single<<<grid, kFoldThreads, 0, s>>>(b.part_b, b.blk_cap, S, first, thermo, b.xw[cur],
+                                               pos);
+    return hipGetLastError();
+}
+
 // One block per segment: its row of the step just taken (phase_in) from ring
 // row `ring_row`, for segments that took part and have a thermo pointer.
 __global__ void __launch_bounds__(kFoldThreads)
@@ -416,52 +454,50 @@ hipError_t launch_npt_drift(const Buffers& b, const Segs& S, int cur, hipStream_
 // velocities and forces, v <- v + (dt/2) kappa F / m and x_next <- wrap(x +
 // dt v), with the pairwise pass's unfused arithmetic in the same order, so a
 // continued run takes the same steps, bit for bit, as one that never
-// stopped.  With `slot` the largest squared displacement of x_next from the
-// list-build positions is formed as in the pairwise pass (one atomic per
-// block).
-__global__ void __launch_bounds__(kBlock)
-k_kick_drift(Segs S, int64_t os, const double4* __restrict__ xw, double4* __restrict__ xw_next,
-             const double4* __restrict__ xbuild, double* __restrict__ vel,
-             const double* __restrict__ F, unsigned long long* __restrict__ slot)
+// stopped.  Returns the squared displacement of x_next from the list-build
+// position when `track` (formed as in the pairwise pass), else 0.
+__device__ __forceinline__ double kick_drift_atom(const Seg& g, int64_t os, int64_t i,
+                                                  const double4& xi,
+                                                  double4* __restrict__ xw_next,
+                                                  const double4* __restrict__ xbuild,
+                                                  double* __restrict__ vel,
+                                                  const double* __restrict__ F, bool track)
 {
-    __shared__ double lds_max[kBlock / 64];
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int sid = seg_of_block(S, lb, false);
-    const Seg& g = S.seg[sid];
-    const Box box = g.box;
-    const int local = (lb - g.blk) * kBlock + threadIdx.x;
-    const int64_t i = g.atom_off + local;
-    double disp2 = 0.0;
-    if (local < g.n) {
 #pragma clang fp contract(off)
-        const double4 xi = xw[i];
-        double hdt, kin;
-        atom_mass_factors(g, xi.w, hdt, kin);
-        double vn[3], x[3] = {xi.x, xi.y, xi.z};
+    const Box& box = g.box;
+    double hdt, kin;
+    atom_mass_factors(g, xi.w, hdt, kin);
+    double vn[3], x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        vn[c] = vel[c * os + i] + hdt * F[c * os + i];
+        x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
+    }
+    vel[i] = vn[0];
+    vel[os + i] = vn[1];
+    vel[2 * os + i] = vn[2];
+    xw_next[i] = make_double4(x[0], x[1], x[2], xi.w);
+    double disp2 = 0.0;
+    if (track) {
+        const double4 xb = xbuild[i];
+        double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            vn[c] = vel[c * os + i] + hdt * F[c * os + i];
-            x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
-        }
-        vel[i] = vn[0];
-        vel[os + i] = vn[1];
-        vel[2 * os + i] = vn[2];
-        xw_next[i] = make_double4(x[0], x[1], x[2], xi.w);
-        if (slot) {
-            const double4 xb = xbuild[i];
-            double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
-                disp2 += d[c] * d[c];
-            }
+            d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
+            disp2 += d[c] * d[c];
         }
     }
-    if (!slot) return;
-    double m = disp2;
+    return disp2;
+}
+
+// Largest value of v over the block into *slot (one atomic per block;
+// non-negative doubles order like their bit patterns).  Every thread calls it.
+__device__ __forceinline__ void block_max_to_slot(double v, double* lds_max,
+                                                  unsigned long long* __restrict__ slot)
+{
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = m;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double bm = lds_max[0];
@@ -471,13 +507,52 @@ k_kick_drift(Segs S, int64_t os, const double4* __restrict__ xw, double4* __rest
     }
 }
 
-hipError_t launch_kick_drift(const Buffers& b, const Segs& S, int cur,
-                             unsigned long long* slot, hipStream_t s)
+// Prologue of a continued one-structure run in one launch: blocks
+// 0 .. nblk - 1 stage the caller's positions (as the staging kernel does)
+// and apply the half-kick and drift into x_next (kick_drift_atom); block
+// nblk, when `thermo` is set, folds the previous run's last step (ring row
+// `ring_row`) into thermo row 0; the first atom block sets the phase word to
+// `phase`.
+__global__ void __launch_bounds__(kBlock)
+k_resume_prologue(Segs S, int64_t os, const double* __restrict__ pos,
+                  const int32_t* __restrict__ types, int ntypes, double4* __restrict__ xw_next,
+                  const double4* __restrict__ xbuild, double* __restrict__ vel,
+                  const double* __restrict__ F, unsigned* __restrict__ status,
+                  unsigned long long* __restrict__ slot, const double* __restrict__ part_b,
+                  int64_t blk_cap, int ring_row, double* __restrict__ thermo,
+                  int* __restrict__ phase_word, int phase)
+{
+    __shared__ double lds[kFoldThreads / 64][kPartialCols];
+    __shared__ double lds_tot[kPartialCols];
+    const Seg& g = S.seg[0];
+    if ((int)blockIdx.x == S.nblk) {
+        const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
+        fold_segment_row(rowp, g, lds, lds_tot, thermo);
+        return;
+    }
+    const int lb = xcd_block(blockIdx.x, S.nblk);
+    if (lb == 0 && threadIdx.x == 0) *phase_word = phase;
+    const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
+    double disp2 = 0.0;
+    if (i < g.n) {
+        const double4 xi = staged_position(pos, types, ntypes, g.n, i, g.box, status);
+        disp2 = kick_drift_atom(g, os, i, xi, xw_next, xbuild, vel, F, slot);
+    }
+    if (slot) block_max_to_slot(disp2, lds[0], slot);
+}
+
+hipError_t launch_resume_prologue(const Buffers& b, const Segs& S, const double* pos,
+                                  const int32_t* types, int ntypes, int cur,
+                                  unsigned long long* slot, int ring_row, double* thermo,
+                                  int* phase_word, int phase, hipStream_t s)
 {
     if (S.nblk <= 0) return hipSuccess;
-    if (!segs_ready(S, b) || !b.vel || !b.F) return hipErrorInvalidValue;
-    k_kick_drift<<<S.nblk, kBlock, 0, s>>>(S, b.ostride, b.xw[cur], b.xw[cur ^ 1], b.xbuild,
-                                           b.vel, b.F, slot);
+    if (!segs_ready(S, b) || S.nseg != 1 || !pos || !b.vel || !b.F || !phase_word ||
+        ring_row < 0 || ring_row >= kThermoRing)
+        return hipErrorInvalidValue;
+    k_resume_prologue<<<S.nblk + (thermo ? 1 : 0), kBlock, 0, s>>>(
+        S, b.ostride, pos, types, ntypes, b.xw[cur ^ 1], b.xbuild, b.vel, b.F, b.status, slot,
+        b.part_b, b.blk_cap, ring_row, thermo, phase_word, phase);
     return hipGetLastError();
 }
 

@@ -201,13 +201,16 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
         qg[SLOTS], gx[SLOTS], gy[SLOTS], gz[SLOTS];
     int slot[SLOTS];
     double u_i = 0.0;
+    // bond slots any atom of the wave needs (wave-uniform): slots past it
+    // are empty in every lane and not issued
+    const int tmax = wave_partner_slots<SLOTS>(kc);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int c = q + kQuad * s;
         ux[s] = uy[s] = uz[s] = ex[s] = qg[s] = gx[s] = gy[s] = gz[s] = T(0);
         ir[s] = T(1);
         slot[s] = 0;
-        if (c < kc) {
+        if (s < tmax && c < kc) {
             const int m = nth_set_bit(msk, c);
             slot[s] = m;
             T r, phi, dphi;
@@ -220,7 +223,6 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
             gz[s] = T(0.5) * dphi * uz[s];
         }
     }
-    const int tmax = wave_partner_slots<SLOTS>(kc);
 #pragma unroll
     for (int t = 0; t < SLOTS; ++t) {
         if (t >= tmax) break;   // wave-uniform
@@ -233,6 +235,7 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
+                if (s >= tmax) break;   // wave-uniform: own slots past it are empty
                 const int c = q + kQuad * s;
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * fx + uy[s] * fy + uz[s] * fz;

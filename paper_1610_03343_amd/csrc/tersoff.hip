@@ -457,6 +457,7 @@ __device__ __forceinline__ void tersoff_partner_terms(
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
+                if (s >= tmax) break;   // wave-uniform: own slots past it are empty
                 const int c = q + kQuad * s;
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
@@ -646,6 +647,7 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
             const int e = (q ^ k) + kQuad * t;
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
+                if (s >= tmax) break;   // wave-uniform: own slots past it are empty
                 const int c = q + kQuad * s;
                 if (c < kc && e < kc && e != c) {
                     const T cs = ux[s] * ex + uy[s] * ey + uz[s] * ez;
