@@ -27,11 +27,44 @@
 
 namespace mbmd {
 
+// Value of another lane by a DPP move (a register move inside the vector
+// unit): CTRL selects the pattern.  Every lane of the wave is active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Largest value over the wave, the same value in every lane (fmax is exact,
+// so the order does not matter).
+__device__ __forceinline__ double wave_max(double v)
+{
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x124>(v));
+    v = fmax(v, dpp_move<0x128>(v));
+    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+
+// Sum over the wave, the same value in every lane: quads by DPP xor 1 and
+// 2, rows of 16 lanes by DPP rotations by 4 and 8, then the four row totals
+// (read from lanes 0, 16, 32, 48) added in a fixed order.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xB1>(v);    // quad_perm 1,0,3,2: lane xor 1
+    v += dpp_move<0x4E>(v);    // quad_perm 2,3,0,1: lane xor 2
+    v += dpp_move<0x124>(v);   // row_ror:4
+    v += dpp_move<0x128>(v);   // row_ror:8
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Fixed-order sum over a block of NT threads of kPartialCols values per
@@ -92,6 +125,7 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     if (local < g.n) {
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
+        ui = U[i];
         // One bond (list slot m, neighbour j): F_ij, W_i and M_i terms.
         auto bond = [&](const T* pij, const T* pji, const double4& xj) {
             const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
@@ -143,7 +177,6 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
             for (int u = 0; u < 4; ++u)
                 if (u < nk) bond(dpart + e[u] * 3, dpart + ((int64_t)rk[u] * cap + jk[u]) * 3, xk[u]);
         }
-        ui = U[i];
         double hdt, kin;
         atom_mass_factors(g, xi.w, hdt, kin);
         // The integrator arithmetic is kept unfused so that it rounds exactly
@@ -210,9 +243,7 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     // block into the run's slot, and (serving batch) the skin bit of the
     // block's structure
     if (a.check_skin) {
-        double m = disp2;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        const double m = wave_max(disp2);
         if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = m;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -495,8 +526,7 @@ __device__ __forceinline__ double kick_drift_atom(const Seg& g, int64_t os, int6
 __device__ __forceinline__ void block_max_to_slot(double v, double* lds_max,
                                                   unsigned long long* __restrict__ slot)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    v = wave_max(v);
     if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
