@@ -247,6 +247,19 @@ k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell
 // ---- neighbour search -----------------------------------------------------
 
 constexpr int kSearchBlock = kBlock / 2;
+// Launches of at most this many 256-atom blocks search and fill the reverse
+// slots with four lanes per atom (shorter serial walks when the chip would
+// otherwise hold few waves); larger ones with one.  The lists do not depend
+// on the choice.
+constexpr int kQuadBuildBlocks = 512;
+
+// Value of lane (lane xor K) of the same quad (DPP quad permutation).
+template <int K>
+__device__ __forceinline__ int search_quad_xor(int v)
+{
+    constexpr int ctrl = K == 1 ? 0xB1 : (K == 2 ? 0x4E : 0x1B);
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
+}
 
 // One thread per atom; its sorted list is kept in LDS (column-major over the
 // block so that neighbouring threads hit distinct banks), then written out
@@ -268,10 +281,14 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
     return list_r2(a, b, box) < rl2;
 }
 
-// One thread per atom of a segment being built; its sorted list is kept in
-// LDS (column-major over the block so that neighbouring threads hit distinct
-// banks), then written out slot-major.  Search blocks hold kBlock atoms like
-// the other per-atom kernels but run as two halves of kSearchBlock threads.
+// LANES (1 or 4) lanes per atom of a segment being built: lane q walks the
+// stencil offsets k = q, q + LANES, ... into a sorted list of its own, kept
+// in LDS (column-major over the block so that neighbouring threads hit
+// distinct banks); each lane then writes its entries at their ranks in the
+// union of the lanes' lists, slot-major.  The union's order does not depend
+// on how the offsets were split, so the list is the one a single walk
+// gives.  A search block covers kSearchBlock / LANES atoms; 256 LANES /
+// kSearchBlock of them make one 256-atom block of the other per-atom kernels.
 // The list is ordered by the key (r^2 >= rc2, j): the neighbours inside the
 // potential cutoff at build time first, each group by ascending index, so
 // the pairwise pass can stop at the last in-cutoff slot.  The grouping only
@@ -280,7 +297,7 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // TYPED: the radii of each pair come from R (copied to LDS), indexed by the
 // types in the w lanes, and the stencil is pruned with the largest radius of
 // atom i's type.
-template <bool TYPED>
+template <bool TYPED, int LANES>
 __global__ void __launch_bounds__(kSearchBlock)
 k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, double rl2_hi,
          double rc2, ListRadii R, int M,
@@ -300,19 +317,26 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         }
         __syncthreads();
     }
+    static_assert(LANES == 1 || LANES == 4, "one or four lanes per atom");
+    constexpr int kAtoms = kSearchBlock / LANES;       // atoms per search block
+    constexpr int kPerBlock = kBlock / kAtoms;         // search blocks per 256-atom block
+    const int q = threadIdx.x & (LANES - 1);
     const int lb2 = xcd_block(blockIdx.x, gridDim.x);
-    const int lb = lb2 >> 1;
+    const int lb = lb2 / kPerBlock;
     const int sid = seg_of_block(S, lb, false);
     const Seg& g = S.seg[sid];
-    // Thread k of the segment takes the k-th atom in cell order, so the
-    // lanes of a wave sit in a run of neighbouring cells along x and, at
+    // Quad k of the segment takes the k-th atom in cell order, so the
+    // quads of a wave sit in a run of neighbouring cells along x and, at
     // each stencil offset, read candidates from one stretch of xcell.
-    const int local = (lb - g.blk) * kBlock + (lb2 & 1) * kSearchBlock + threadIdx.x;
-    int cnt = 0;
-    if (local < g.n && g.build) {
+    const int local = (lb - g.blk) * kBlock + (lb2 % kPerBlock) * kAtoms +
+                      (int)(threadIdx.x / LANES);
+    const bool active = local < g.n && g.build;
+    int cnt = 0;               // entries this lane found
+    int64_t i = 0;
+    int* buf = lbuf + threadIdx.x;
+    if (active) {
         const int p0 = start[g.cell_off] + local;
-        const int64_t i = cell_atoms[p0];
-        int* buf = lbuf + threadIdx.x;
+        i = cell_atoms[p0];
         const double4 xi = xcell[p0];
         const int ti = TYPED ? min(max((int)xi.w, 0), R.nt - 1) : 0;
         double rl2_i = rl2;   // largest list radius squared of i's pairs
@@ -370,12 +394,12 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
             }
             if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
                 const unsigned key = (unsigned)j | (r2 < pc2 ? 0u : 0x80000000u);
-                int q = cnt < M ? cnt : M;
-                while (q > 0 && (unsigned)buf[(q - 1) * kSearchBlock] > key) {
-                    if (q < M) buf[q * kSearchBlock] = buf[(q - 1) * kSearchBlock];
-                    --q;
+                int pos = cnt < M ? cnt : M;
+                while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
+                    if (pos < M) buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
+                    --pos;
                 }
-                if (q < M) buf[q * kSearchBlock] = (int)key;
+                if (pos < M) buf[pos * kSearchBlock] = (int)key;
                 ++cnt;
             }
         };
@@ -395,16 +419,16 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                 e = start[cc + 1];
             }
         };
-        // Every lane walks the offsets in the same order (a pruned cell is an
-        // empty iteration), which keeps the wave's reads together; the next
-        // cell's range is fetched before the current cell is scanned, and the
-        // scan takes two candidates per iteration, so more loads are in
-        // flight per lane.
+        // Lane q of every quad walks the same offsets in the same order (a
+        // pruned cell is an empty iteration), which keeps the wave's reads
+        // together; the next cell's range is fetched before the current cell
+        // is scanned, and the scan takes two candidates per iteration, so
+        // more loads are in flight per lane.
         int b, e;
-        cell_range(0, b, e);
-        for (int k = 0; k < 27; ++k) {
+        cell_range(q, b, e);
+        for (int k = q; k < 27; k += LANES) {
             int nb, ne;
-            cell_range(k + 1, nb, ne);
+            cell_range(k + LANES, nb, ne);
             for (int p = b; p < e; p += 2) {
                 const bool two = p + 1 < e;
                 const int j0 = cell_atoms[p];
@@ -421,21 +445,46 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
             b = nb;
             e = ne;
         }
-        // On overflow the stored entries are the M smallest keys; the status
-        // bit turns the call into an error.
-        if (cnt > M) {
-            atomicOr(status, ST_NEIGH_OVERFLOW);
-            atomicOr(&sstat[S.seg[sid].sidx], ST_NEIGH_OVERFLOW);
+    }
+    // counts of the quad's other lanes (every lane of the wave takes part)
+    int c1 = 0, c2 = 0, c3 = 0;
+    if constexpr (LANES == 4) {
+        c1 = search_quad_xor<1>(cnt);
+        c2 = search_quad_xor<2>(cnt);
+        c3 = search_quad_xor<3>(cnt);
+        __syncthreads();   // the quad's lists are complete in LDS
+    }
+    const int total = cnt + c1 + c2 + c3;
+    if (active) {
+        // On overflow the stored entries are the M smallest keys (each lane
+        // kept its M smallest); the status bit turns the call into an error.
+        if (q == 0) {
+            if (total > M) {
+                atomicOr(status, ST_NEIGH_OVERFLOW);
+                atomicOr(&sstat[S.seg[sid].sidx], ST_NEIGH_OVERFLOW);
+            }
+            nn[i] = total;
         }
-        nn[i] = cnt;
         const int w = cnt < M ? cnt : M;
-        for (int m = 0; m < w; ++m) {
-            nl[(int64_t)m * cap + i] = buf[m * kSearchBlock] & 0x7fffffff;
-            rev[(int64_t)m * cap + i] = 0;   // an in-range slot until k_reverse sets it
+        const int wr[3] = {min(c1, M), min(c2, M), min(c3, M)};
+        for (int p = 0; p < w; ++p) {
+            const unsigned key = (unsigned)buf[p * kSearchBlock];
+            // rank in the union: own position plus the smaller keys of the
+            // other three (sorted) lists; keys are distinct
+            int rank = p;
+#pragma unroll
+            for (int r = 1; r < LANES; ++r) {
+                const int* col = lbuf + (threadIdx.x ^ r);
+                for (int t = 0; t < wr[r - 1] && (unsigned)col[t * kSearchBlock] < key; ++t) ++rank;
+            }
+            if (rank < M) {
+                nl[(int64_t)rank * cap + i] = (int)(key & 0x7fffffffu);
+                rev[(int64_t)rank * cap + i] = 0;   // an in-range slot until k_reverse sets it
+            }
         }
     }
     // largest count of the block, one atomic per block
-    int mx = cnt;
+    int mx = active ? total : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = mx;
@@ -448,15 +497,24 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
     }
 }
 
+// LANES (1 or 4) lanes per atom: lane q takes the list slots q, q + LANES,
+// ... of its atom (kBlock / LANES atoms per block, LANES blocks per 256-atom
+// block).
+template <int LANES>
 __global__ void __launch_bounds__(kBlock)
 k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M, int64_t cap,
           int* __restrict__ rev, unsigned* __restrict__ status)
 {
-    int sid;
-    int64_t i;
-    if (!block_atom(S, sid, i) || !S.seg[sid].build) return;
+    const int lbl = xcd_block(blockIdx.x, gridDim.x);
+    const int lb = lbl / LANES;
+    const int sid = seg_of_block(S, lb, false);
+    const Seg& g = S.seg[sid];
+    const int local =
+        (lb - g.blk) * kBlock + (lbl % LANES) * (kBlock / LANES) + (int)(threadIdx.x / LANES);
+    if (local >= g.n || !g.build) return;
+    const int64_t i = g.atom_off + local;
     const int cnt = min(nn[i], M);
-    for (int m = 0; m < cnt; ++m) {
+    for (int m = (int)(threadIdx.x % LANES); m < cnt; m += LANES) {
         const int j = nl[(int64_t)m * cap + i];
         // Complete lists are symmetric (the inclusion test gives the same
         // bits for (i, j) and (j, i)), so such a pair is settled once, by
@@ -510,17 +568,33 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
     if (typed && (typed->nt < 1 || typed->nt > kMaxTypes)) return hipErrorInvalidValue;
-    if (typed && typed->nt > 1)
-        k_search<true><<<2 * S.nblk, kSearchBlock, lds, s>>>(
-            S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut, *typed,
-            b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn,
-            b.status, b.sstat);
+    const bool quad = S.nblk <= kQuadBuildBlocks;
+    const int nsb = (quad ? 8 : 2) * S.nblk;   // search blocks of kSearchBlock threads
+    const double lo = rl2 * (1.0 - 1e-10), hi = rl2 * (1.0 + 1e-10);
+    const ListRadii R = typed ? *typed : ListRadii{};
+    if (typed && typed->nt > 1) {
+        if (quad)
+            k_search<true, 4><<<nsb, kSearchBlock, lds, s>>>(
+                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+        else
+            k_search<true, 1><<<nsb, kSearchBlock, lds, s>>>(
+                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+    } else {
+        if (quad)
+            k_search<false, 4><<<nsb, kSearchBlock, lds, s>>>(
+                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+        else
+            k_search<false, 1><<<nsb, kSearchBlock, lds, s>>>(
+                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+    }
+    if (quad)
+        k_reverse<4><<<4 * S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     else
-        k_search<false><<<2 * S.nblk, kSearchBlock, lds, s>>>(
-            S, b.xcell, rl2, rl2 * (1.0 - 1e-10), rl2 * (1.0 + 1e-10), rcut * rcut,
-            ListRadii{}, b.M, b.cap, b.cell_of, b.cell_start, b.cell_atoms, b.nn, b.nl, b.rev,
-            b.maxnn, b.status, b.sstat);
-    k_reverse<<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
+        k_reverse<1><<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
 }
 

@@ -93,6 +93,36 @@ def test_batch_equals_alone_bitwise(pot, precision):
 
 
 @pytest.mark.parametrize("pot", ["tersoff", "sw"])
+def test_build_lane_split_does_not_change_lists(pot):
+    """The list build takes four lanes per atom in launches of at most 512
+    blocks of 256 atoms and one lane above; the lists, and so every force,
+    are the same either way.  Five 32,768-atom structures alone (four lanes)
+    and in one batch of 163,840 atoms (one lane) give the same bits."""
+    import torch
+    systems = [wl.silicon_crystal(16, seed=260 + k, sigma=0.08) for k in range(5)]
+    assert all(s.n <= 512 * 256 for s in systems) and sum(s.n for s in systems) > 512 * 256
+    with context(pot) as ctx:
+        alone = [_alone(ctx, s, 0, "fp64", 5) for s in systems]
+    got = {}
+    with context(pot) as ctx:
+        ctx.batch_open(sum(s.n for s in systems), len(systems), 5)
+        handles = {ctx.batch_add(to_dev(s.pos), to_dev(s.vel), s.box, wl.M_SI, 1.0, 0): k
+                   for k, s in enumerate(systems)}
+        ctx.batch_step("fp64")
+        for h in ctx.batch_finished():
+            k = handles.pop(h)
+            out = ctx.batch_retire(h, systems[k].n)
+            ctx.batch_sync()
+            got[k] = {key: v.cpu().numpy() for key, v in out.items()}
+        ctx.batch_close()
+        torch.cuda.synchronize()
+    assert sorted(got) == list(range(len(systems)))
+    for k, a in enumerate(alone):
+        for key in ("U", "F", "W", "J"):
+            assert np.array_equal(a[key], got[k][key]), (k, key)
+
+
+@pytest.mark.parametrize("pot", ["tersoff", "sw"])
 def test_batch_single_points_match_oracle(pot):
     import torch
     systems = _systems()
