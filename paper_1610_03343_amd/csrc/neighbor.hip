@@ -14,6 +14,8 @@
 // by any IEEE evaluation of the same expression.
 #include "mbmd_internal.h"
 
+#include <type_traits>
+
 namespace mbmd {
 
 __device__ __forceinline__ double list_r2(const double4& a, const double4& b, const Box& box)
@@ -249,9 +251,12 @@ k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell
 constexpr int kSearchBlock = kBlock / 2;
 // Launches of at most this many 256-atom blocks search and fill the reverse
 // slots with four lanes per atom (shorter serial walks when the chip would
-// otherwise hold few waves); larger ones with one.  The lists do not depend
-// on the choice.
+// otherwise hold few waves); larger ones search with one lane per atom and
+// fill the reverse slots with two (measured best at 512,000 and 1,000,000
+// atoms).  The lists do not depend on the choice.
 constexpr int kQuadBuildBlocks = 512;
+constexpr int kSearchLanesLarge = 1;    // lanes per atom above that size
+constexpr int kReverseLanesLarge = 2;
 
 // Value of lane (lane xor K) of the same quad (DPP quad permutation).
 template <int K>
@@ -281,7 +286,7 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
     return list_r2(a, b, box) < rl2;
 }
 
-// LANES (1 or 4) lanes per atom of a segment being built: lane q walks the
+// LANES (1, 2 or 4) lanes per atom of a segment being built: lane q walks the
 // stencil offsets k = q, q + LANES, ... into a sorted list of its own, kept
 // in LDS (column-major over the block so that neighbouring threads hit
 // distinct banks); each lane then writes its entries at their ranks in the
@@ -317,7 +322,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         }
         __syncthreads();
     }
-    static_assert(LANES == 1 || LANES == 4, "one or four lanes per atom");
+    static_assert(LANES == 1 || LANES == 2 || LANES == 4, "one, two or four lanes per atom");
     constexpr int kAtoms = kSearchBlock / LANES;       // atoms per search block
     constexpr int kPerBlock = kBlock / kAtoms;         // search blocks per 256-atom block
     const int q = threadIdx.x & (LANES - 1);
@@ -448,12 +453,12 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
     }
     // counts of the quad's other lanes (every lane of the wave takes part)
     int c1 = 0, c2 = 0, c3 = 0;
+    if constexpr (LANES >= 2) c1 = search_quad_xor<1>(cnt);
     if constexpr (LANES == 4) {
-        c1 = search_quad_xor<1>(cnt);
         c2 = search_quad_xor<2>(cnt);
         c3 = search_quad_xor<3>(cnt);
-        __syncthreads();   // the quad's lists are complete in LDS
     }
+    if constexpr (LANES > 1) __syncthreads();   // the atom's lists are complete in LDS
     const int total = cnt + c1 + c2 + c3;
     if (active) {
         // On overflow the stored entries are the M smallest keys (each lane
@@ -497,7 +502,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
     }
 }
 
-// LANES (1 or 4) lanes per atom: lane q takes the list slots q, q + LANES,
+// LANES (1, 2 or 4) lanes per atom: lane q takes the list slots q, q + LANES,
 // ... of its atom (kBlock / LANES atoms per block, LANES blocks per 256-atom
 // block).
 template <int LANES>
@@ -568,31 +573,35 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
     if (typed && (typed->nt < 1 || typed->nt > kMaxTypes)) return hipErrorInvalidValue;
-    const bool quad = S.nblk <= kQuadBuildBlocks;
-    const int nsb = (quad ? 8 : 2) * S.nblk;   // search blocks of kSearchBlock threads
+    const bool small = S.nblk <= kQuadBuildBlocks;
+    const int sl = small ? 4 : kSearchLanesLarge, rl = small ? 4 : kReverseLanesLarge;
+    const int nsb = sl * (kBlock / kSearchBlock) * S.nblk;   // search blocks
     const double lo = rl2 * (1.0 - 1e-10), hi = rl2 * (1.0 + 1e-10);
     const ListRadii R = typed ? *typed : ListRadii{};
-    if (typed && typed->nt > 1) {
-        if (quad)
-            k_search<true, 4><<<nsb, kSearchBlock, lds, s>>>(
-                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
-                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
-        else
-            k_search<true, 1><<<nsb, kSearchBlock, lds, s>>>(
-                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
-                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+    auto search = [&](auto typed_tag, auto lanes_tag) {
+        constexpr bool TY = decltype(typed_tag)::value;
+        constexpr int LN = decltype(lanes_tag)::value;
+        k_search<TY, LN><<<nsb, kSearchBlock, lds, s>>>(
+            S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+            b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+    };
+    using T1 = std::integral_constant<int, 1>;
+    using T2 = std::integral_constant<int, 2>;
+    using T4 = std::integral_constant<int, 4>;
+    const bool ty = typed && typed->nt > 1;
+    if (ty) {
+        if (sl == 4) search(std::true_type{}, T4{});
+        else if (sl == 2) search(std::true_type{}, T2{});
+        else search(std::true_type{}, T1{});
     } else {
-        if (quad)
-            k_search<false, 4><<<nsb, kSearchBlock, lds, s>>>(
-                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
-                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
-        else
-            k_search<false, 1><<<nsb, kSearchBlock, lds, s>>>(
-                S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
-                b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+        if (sl == 4) search(std::false_type{}, T4{});
+        else if (sl == 2) search(std::false_type{}, T2{});
+        else search(std::false_type{}, T1{});
     }
-    if (quad)
+    if (rl == 4)
         k_reverse<4><<<4 * S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
+    else if (rl == 2)
+        k_reverse<2><<<2 * S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     else
         k_reverse<1><<<S.nblk, kBlock, 0, s>>>(S, b.nn, b.nl, b.M, b.cap, b.rev, b.status);
     return hipGetLastError();
