@@ -254,7 +254,9 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     const int64_t nn = cap > 0 ? cap : 1;
     const int64_t ccap = cell_cap_for(nn, segs);
     const int64_t nscan = (ccap + kBlock * 4 - 1) / (kBlock * 4);
-    const int64_t blk_cap = blocks_for(nn) + segs;
+    // 256-atom blocks, and room for the four rows per block of the four-lane
+    // pairwise pass (at most kQuadPairBlocks blocks)
+    const int64_t blk_cap = blocks_for(nn) + segs + 3 * kQuadPairBlocks;
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
         char* p = base ? base + off : nullptr;

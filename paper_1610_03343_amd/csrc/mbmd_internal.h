@@ -56,6 +56,9 @@ constexpr int kThermoCols = 16;      // per-step thermo row
 constexpr int kPartialCols = 14;     // per-block partials: U, E_kin, W(9), J(3)
 constexpr int kMaxChunk = 256;       // steps enqueued between two checks of the skin
 constexpr int kThermoRing = 256;     // per-step rows of block partials kept before a fold
+// Launches of at most this many 256-atom blocks take the pairwise pass with
+// four lanes per atom, which leaves four thermo rows per block.
+constexpr int kQuadPairBlocks = 64;
 constexpr int kMaxTypes = 4;         // atom types of the multicomponent Tersoff form
 
 struct Box {
@@ -160,7 +163,8 @@ struct Buffers {
     double4* xcell;          // [N] positions in cell order (cell_atoms order)
     int64_t cell_cap;
     double* part_b;          // [kThermoRing][block capacity][kPartialCols]
-    int64_t blk_cap;         // 256-atom block capacity
+    int64_t blk_cap;         // 256-atom block capacity, plus the rows the four-lane
+                             // pairwise pass needs (rows of part_b per step)
     int* ovf_count;          // atoms whose in-cutoff count exceeds the fast path
     int* ovf_list;           // [N]
     unsigned* status;

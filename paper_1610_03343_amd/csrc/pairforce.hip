@@ -67,6 +67,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+// Value of lane u (0..3, a compile-time constant after unrolling) of the
+// same quad: DPP quad_perm u,u,u,u.
+__device__ __forceinline__ double quad_bcast(double v, int u)
+{
+    return u == 0 ? dpp_move<0x00>(v)
+                  : (u == 1 ? dpp_move<0x55>(v) : (u == 2 ? dpp_move<0xAA>(v) : dpp_move<0xFF>(v)));
+}
+
 // Fixed-order sum over a block of NT threads of kPartialCols values per
 // thread into lds_out (lds: one row per wave).
 template <int NT>
@@ -93,6 +101,53 @@ __device__ __forceinline__ void block_sum_cols(double (&vals)[kPartialCols],
 // Threads of the fold kernels (1024 threads, four times fewer rounds of
 // loads, measured slower: the fold is bound by launch latency).
 constexpr int kFoldThreads = kBlock;
+
+// The pairwise pass comes in two forms with the same bits: one thread per
+// atom (k_pair_gather) and, for launches of at most kQuadPairBlocks blocks of
+// 256 atoms, where that form leaves the chip mostly idle and each thread's
+// chain of dependent loads sets the time, four lanes per atom (k_pair_quad).
+// Both add the bond terms in ascending slot order with the explicit
+// operations below and integrate with the same unfused statements.  Their
+// thermo partials differ only in where the last additions happen: each
+// 64-atom group is summed by wave_sum with atom k in lane k; k_pair_gather
+// adds a block's four group sums in order (block_sum_cols) and stores one
+// row per 256-atom block, k_pair_quad stores the four group sums (rows 4b ..
+// 4b + 3) and the fold adds them in the same order.  So a launch may take
+// either form whatever structures it holds, and a structure gives the same
+// results alone and in a batch.
+
+struct Vec3 {
+    double v[3];
+};
+
+// Minimum-image r_ij = x_j - x_i.
+__device__ __forceinline__ Vec3 bond_vector(const double4& xi, const double4& xj, const Box& box)
+{
+#pragma clang fp contract(off)
+    Vec3 r{{xj.x - xi.x, xj.y - xi.y, xj.z - xi.z}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.v[c] = fma(-box.L[c], rint(r.v[c] * box.inv[c]), r.v[c]);
+    return r;
+}
+
+// F_i += F_ij, W_i -= 1/2 r_ij (x) F_ij, M_i += r_ij (x) p_ji.
+__device__ __forceinline__ void add_bond_terms(const double (&fij)[3], const double (&dji)[3],
+                                               const Vec3& r, double (&f)[3], double (&w)[9],
+                                               double (&mm)[9])
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = f[k] + fij[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double hr = -0.5 * r.v[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            w[3 * c + k] = fma(hr, fij[k], w[3 * c + k]);
+            mm[3 * c + k] = fma(r.v[c], dji[k], mm[3 * c + k]);
+        }
+    }
+}
 
 template <class T>
 __global__ void __launch_bounds__(kBlock)
@@ -126,27 +181,14 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
         ui = U[i];
-        // One bond (list slot m, neighbour j): F_ij, W_i and M_i terms.
+        // One bond (list slot m, neighbour j): F_ij, W_i and M_i terms, in
+        // the explicit operations of add_bond_terms.
         auto bond = [&](const T* pij, const T* pji, const double4& xj) {
             const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
-            const double fij0 = (double)pij[0] - dji0;
-            const double fij1 = (double)pij[1] - dji1;
-            const double fij2 = (double)pij[2] - dji2;
-            double r[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) r[c] -= box.L[c] * rint(r[c] * box.inv[c]);
-            f[0] += fij0;
-            f[1] += fij1;
-            f[2] += fij2;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                w[3 * c + 0] -= 0.5 * r[c] * fij0;
-                w[3 * c + 1] -= 0.5 * r[c] * fij1;
-                w[3 * c + 2] -= 0.5 * r[c] * fij2;
-                mm[3 * c + 0] += r[c] * dji0;
-                mm[3 * c + 1] += r[c] * dji1;
-                mm[3 * c + 2] += r[c] * dji2;
-            }
+            const double fij[3] = {(double)pij[0] - dji0, (double)pij[1] - dji1,
+                                   (double)pij[2] - dji2};
+            const double dji[3] = {dji0, dji1, dji2};
+            add_bond_terms(fij, dji, bond_vector(xi, xj, box), f, w, mm);
         };
         // The in-cutoff slots in ascending order, four per iteration with
         // every load of them issued first; the sums take the bonds in the
@@ -270,23 +312,213 @@ k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __rest
     if (threadIdx.x < kPartialCols) a.part_row[(int64_t)lb * kPartialCols + threadIdx.x] = lds_tot[threadIdx.x];
 }
 
+// Four lanes per atom, for launches of at most kQuadPairBlocks blocks of 256
+// atoms: a block is one 64-atom group (the 64-atom blocks of the site pass).
+// Lane q takes in-cutoff bonds q, q + 4, ...; in round t the quad's lanes
+// hold bonds 4t .. 4t + 3 and every lane adds the four (broadcast within the
+// quad) in slot order, so that each holds the atom's sums formed as one
+// thread forms them.  Lane 0 finishes the atom with the statements of
+// k_pair_gather; the thermo values pass through LDS so that wave 0 sums the
+// group with atom k in lane k, into row 4b + k of 256-atom block b.
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_pair_quad(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
+            double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
+            const int* __restrict__ nl,
+            const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
+            const T* __restrict__ dpart, const double* __restrict__ U,
+            double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
+            double* __restrict__ J, int* __restrict__ ovf_count)
+{
+    __shared__ double lds_max[kBlock / 64];
+    __shared__ double lds_vals[kPartialCols][kQuadAtoms];
+    const int q = threadIdx.x & (kQuad - 1);
+    const int atom = threadIdx.x >> 2;   // within the group
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int sid = seg_of_block(S, lb, true);
+    const Seg& g = S.seg[sid];
+    const int phase = S.phase_in[sid];
+    if (lb == g.blk_quad && threadIdx.x == 0)
+        S.phase_out[sid] = phase > g.nsteps ? phase : phase + 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ovf_count = 0;   // consumed by the partials pass
+    if (phase > g.nsteps) return;              // finished segment, kept for retrieval
+    const bool kick_before = phase > 0, advance = !a.hold && phase < g.nsteps;
+    const Box box = g.box;
+    const int group = lb - g.blk_quad;   // within the segment
+    const int local = group * kQuadAtoms + atom;
+    const int64_t i = g.atom_off + local;
+    const bool valid = local < g.n;
+
+    double f[3] = {0, 0, 0}, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, mm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double v[3] = {0, 0, 0}, jj[3] = {0, 0, 0}, ekin = 0.0, ui = 0.0, disp2 = 0.0;
+    const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const unsigned long long msk = valid ? mask[i] : 0ull;
+    if (valid) ui = U[i];
+    const int nb = __popcll(msk);
+    // rounds: as many as the wave's largest count needs (wave-uniform, so
+    // every lane joins the broadcasts)
+    const int rounds = (int)wave_max((double)((nb + kQuad - 1) / kQuad));
+    unsigned long long rem = msk;
+    for (int k = 0; k < q && rem; ++k) rem &= rem - 1;   // this lane's first bond: the q-th
+    for (int t = 0; t < rounds; ++t) {
+        double fij[3] = {0, 0, 0}, dji[3] = {0, 0, 0};
+        Vec3 r{{0, 0, 0}};
+        if (rem) {
+            const int m = __builtin_ctzll(rem);
+            const int64_t e = (int64_t)m * cap + i;
+            const int j = nl[e];
+            const int rv = rev[e];
+            const T* pij = dpart + e * 3;
+            const T* pji = dpart + ((int64_t)rv * cap + j) * 3;
+            const double dji0 = (double)pji[0], dji1 = (double)pji[1], dji2 = (double)pji[2];
+            fij[0] = (double)pij[0] - dji0;
+            fij[1] = (double)pij[1] - dji1;
+            fij[2] = (double)pij[2] - dji2;
+            dji[0] = dji0;
+            dji[1] = dji1;
+            dji[2] = dji2;
+            r = bond_vector(xi, xw[j], box);
+        }
+#pragma unroll
+        for (int k = 0; k < kQuad; ++k)
+            if (rem) rem &= rem - 1;   // next round: four bonds on
+#pragma unroll
+        for (int u = 0; u < kQuad; ++u) {
+            double bf[3], bd[3];
+            Vec3 br;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bf[c] = quad_bcast(fij[c], u);
+                bd[c] = quad_bcast(dji[c], u);
+                br.v[c] = quad_bcast(r.v[c], u);
+            }
+            if (kQuad * t + u < nb) add_bond_terms(bf, bd, br, f, w, mm);
+        }
+    }
+    if (valid) {
+        double hdt, kin;
+        atom_mass_factors(g, xi.w, hdt, kin);
+        // the statements of k_pair_gather
+        if (vel) {
+#pragma clang fp contract(off)
+            v[0] = vel[i];
+            v[1] = vel[os + i];
+            v[2] = vel[2 * os + i];
+            if (kick_before) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] += hdt * f[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                jj[c] = mm[3 * c + 0] * v[0] + mm[3 * c + 1] * v[1] + mm[3 * c + 2] * v[2];
+            ekin = kin * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        }
+        if (q == 0) {
+            __builtin_nontemporal_store(f[0], &F[i]);
+            __builtin_nontemporal_store(f[1], &F[os + i]);
+            __builtin_nontemporal_store(f[2], &F[2 * os + i]);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) __builtin_nontemporal_store(w[c], &W[(int64_t)c * os + i]);
+            __builtin_nontemporal_store(jj[0], &J[i]);
+            __builtin_nontemporal_store(jj[1], &J[os + i]);
+            __builtin_nontemporal_store(jj[2], &J[2 * os + i]);
+            if (vel && advance) {
+#pragma clang fp contract(off)
+                double vn[3], x[3] = {xi.x, xi.y, xi.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    vn[c] = v[c] + hdt * f[c];
+                    x[c] = wrap_coord(x[c] + g.dt * vn[c], box.L[c]);
+                }
+                vel[i] = vn[0];
+                vel[os + i] = vn[1];
+                vel[2 * os + i] = vn[2];
+                xw_next[i] = make_double4(x[0], x[1], x[2], xi.w);
+                if (a.check_skin) {
+                    const double4 xb = xbuild[i];
+                    double d[3] = {x[0] - xb.x, x[1] - xb.y, x[2] - xb.z};
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        d[c] -= box.L[c] * rint(d[c] * box.inv[c]);
+                        disp2 += d[c] * d[c];
+                    }
+                }
+            } else {
+                if (vel && kick_before) {
+                    vel[i] = v[0];
+                    vel[os + i] = v[1];
+                    vel[2 * os + i] = v[2];
+                }
+                if (!a.hold) xw_next[i] = xi;
+            }
+        }
+    }
+    if (a.check_skin) {
+        const double m = wave_max(disp2);
+        if ((threadIdx.x & 63) == 0) lds_max[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double bm = lds_max[0];
+#pragma unroll
+            for (int k = 1; k < kBlock / 64; ++k) bm = fmax(bm, lds_max[k]);
+            if (a.disp_slot) atomicMax(a.disp_slot, (unsigned long long)__double_as_longlong(bm));
+            if (a.seg_status && bm > a.skin_half2) atomicOr(&a.seg_status[g.sidx], ST_SKIN);
+        }
+    }
+
+    if (!a.part_row) return;
+    if (q == 0) {
+        lds_vals[0][atom] = ui;
+        lds_vals[1][atom] = ekin;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) lds_vals[2 + c][atom] = w[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lds_vals[11 + c][atom] = jj[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int64_t row = 4 * (int64_t)(g.blk + group / 4) + group % 4;
+#pragma unroll
+        for (int c = 0; c < kPartialCols; ++c) {
+            const double t = wave_sum(lds_vals[c][threadIdx.x]);
+            if (threadIdx.x == 0) a.part_row[row * kPartialCols + c] = t;
+        }
+    }
+}
+
 // Sums one segment's block partials of one step (ring row rowp), in a fixed
 // order, into its thermo row: 0 E_pot, 1 E_kin, 2..10 W, 11..13 J,
 // 14 E_pot + E_kin, 15 kinetic temperature (k_B in eV/K, 3N - 3 degrees of
 // freedom).  Called by every thread of a kFoldThreads block; thread 0 writes
 // the row.
-__device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp, const Seg& g,
-                                                 double (*lds)[kPartialCols], double* lds_tot,
-                                                 double* __restrict__ row)
+__device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp, const Segs& S,
+                                                 const Seg& g, double (*lds)[kPartialCols],
+                                                 double* lds_tot, double* __restrict__ row)
 {
+    // k_pair_quad's launches leave four group rows per block: their sum in
+    // block_sum_cols' order (a group past the segment's end adds 0, as an
+    // all-zero wave does there)
+    const bool groups = S.nblk <= kQuadPairBlocks;
     const int b0 = g.blk, b1 = g.blk + blocks_for(g.n);
     double vals[kPartialCols];
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
     for (int b = b0 + threadIdx.x; b < b1; b += kFoldThreads) {
-        const double* p = rowp + (int64_t)b * kPartialCols;
+        if (groups) {
+            const double* p = rowp + 4 * (int64_t)b * kPartialCols;
+            const int a0 = (b - g.blk) * kBlock;
 #pragma unroll
-        for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
+            for (int c = 0; c < kPartialCols; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) t += a0 + 64 * k < g.n ? p[k * kPartialCols + c] : 0.0;
+                vals[c] += t;
+            }
+        } else {
+            const double* p = rowp + (int64_t)b * kPartialCols;
+#pragma unroll
+            for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
+        }
     }
     block_sum_cols<kFoldThreads>(vals, lds, lds_tot);
     if (threadIdx.x == 0) {
@@ -307,7 +539,7 @@ k_thermo_fold(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int si
     __shared__ double lds_tot[kPartialCols];
     const int k = first + blockIdx.x;
     const double* rowp = part_b + (int64_t)((ring0 + k) % kThermoRing) * blk_cap * kPartialCols;
-    fold_segment_row(rowp, S.seg[sid], lds, lds_tot, thermo + (int64_t)k * kThermoCols);
+    fold_segment_row(rowp, S, S.seg[sid], lds, lds_tot, thermo + (int64_t)k * kThermoCols);
 }
 
 hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int first, int count,
@@ -334,7 +566,7 @@ k_end_single(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int fir
     if ((int)blockIdx.x >= S.nblk) {
         const int k = first + (int)blockIdx.x - S.nblk;
         const double* rowp = part_b + (int64_t)(k % kThermoRing) * blk_cap * kPartialCols;
-        fold_segment_row(rowp, g, lds, lds_tot, thermo + (int64_t)k * kThermoCols);
+        fold_segment_row(rowp, S, g, lds, lds_tot, thermo + (int64_t)k * kThermoCols);
         return;
     }
     const int64_t i = (int64_t)xcd_block(blockIdx.x, S.nblk) * kBlock + threadIdx.x;
@@ -369,7 +601,7 @@ k_thermo_fold_segments(const double* __restrict__ part_b, int64_t blk_cap, Segs 
     const int k = S.phase_in[sid];
     if (!g.thermo || k > g.nsteps) return;
     const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
-    fold_segment_row(rowp, g, lds, lds_tot, g.thermo + (int64_t)k * kThermoCols);
+    fold_segment_row(rowp, S, g, lds, lds_tot, g.thermo + (int64_t)k * kThermoCols);
 }
 
 hipError_t launch_thermo_fold_segments(const Buffers& b, const Segs& S, int ring_row,
@@ -402,7 +634,7 @@ k_npt_fold(const double* __restrict__ rowp, Segs S, Seg* __restrict__ seg_rw, Np
     __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     double* row = thermo + (int64_t)step * kThermoCols;
-    fold_segment_row(rowp, S.seg[0], lds, lds_tot, row);
+    fold_segment_row(rowp, S, S.seg[0], lds, lds_tot, row);
     if (threadIdx.x != 0) return;
     const Box box = S.seg[0].box;
     if (box_traj)
@@ -557,7 +789,7 @@ k_resume_prologue(Segs S, int64_t os, const double* __restrict__ pos,
     const Seg& g = S.seg[0];
     if ((int)blockIdx.x == S.nblk) {
         const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
-        fold_segment_row(rowp, g, lds, lds_tot, thermo);
+        fold_segment_row(rowp, S, g, lds, lds_tot, thermo);
         return;
     }
     const int lb = xcd_block(blockIdx.x, S.nblk);
@@ -591,9 +823,14 @@ hipError_t launch_pair_gather(const Buffers& b, const Segs& S, const StepArgs& a
 {
     if (S.nblk <= 0) return hipSuccess;
     if (!segs_ready(S, b) || !b.F || !b.W || !b.J || !b.U) return hipErrorInvalidValue;
-    k_pair_gather<T><<<S.nblk, kBlock, 0, s>>>(
-        S, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nl, b.rev,
-        b.mask, static_cast<const T*>(b.dpart), b.U, b.vel, b.F, b.W, b.J, b.ovf_count);
+    if (S.nblk <= kQuadPairBlocks)
+        k_pair_quad<T><<<S.nblk_quad, kBlock, 0, s>>>(
+            S, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nl, b.rev,
+            b.mask, static_cast<const T*>(b.dpart), b.U, b.vel, b.F, b.W, b.J, b.ovf_count);
+    else
+        k_pair_gather<T><<<S.nblk, kBlock, 0, s>>>(
+            S, b.cap, b.ostride, a, b.xw[a.cur], b.xw[a.cur ^ 1], b.xbuild, b.nl, b.rev,
+            b.mask, static_cast<const T*>(b.dpart), b.U, b.vel, b.F, b.W, b.J, b.ovf_count);
     return hipGetLastError();
 }
 
