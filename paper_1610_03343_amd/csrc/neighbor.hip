@@ -232,6 +232,51 @@ k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ b
     if (ncell == 0 && blockIdx.x == 0 && threadIdx.x == 0) start[0] = 0;
 }
 
+// The whole scan in one block, tile after tile with a running carry (grids
+// of at most kScanOneBlockTiles tiles: one launch instead of three).
+constexpr int kScanOneBlockTiles = 16;
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_one_block(const int* __restrict__ count, int ncell, int* __restrict__ start,
+                 int* __restrict__ fill)
+{
+    __shared__ int lds[kBlock / 64];
+    int carry = 0;
+    for (int tile = 0; tile * kScanTile < ncell; ++tile) {
+        const int base = tile * kScanTile + threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < ncell ? count[base + k] : 0;
+            s += v[k];
+        }
+        int total;
+        int run = carry + block_exclusive_scan(s, lds, total);
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < ncell) {
+                start[base + k] = run;
+                fill[base + k] = 0;
+            }
+            run += v[k];
+        }
+        if (base + kScanItems >= ncell && base < ncell) start[ncell] = run;
+        carry += total;
+    }
+    if (ncell == 0 && threadIdx.x == 0) start[0] = 0;
+}
+
+// Zeroes a[0 .. na) and b[0 .. nb) in one launch.
+__global__ void k_fill_zero2(int* __restrict__ a, int64_t na, int* __restrict__ b, int64_t nb)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+        if (i < na) a[i] = 0;
+        else b[i - na] = 0;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell_of,
             const int* __restrict__ start, int* __restrict__ fill, int* __restrict__ cell_atoms,
@@ -556,18 +601,26 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
 {
     if (S.nblk <= 0) return hipSuccess;
     if (!S.seg || S.nseg > b.seg_cap || total_cells > b.cell_cap) return hipErrorInvalidValue;
-    hipError_t e = launch_fill_int(b.cell_count, total_cells, 0, s);
-    if (e == hipSuccess) e = launch_fill_int(b.maxnn, S.nseg, 0, s);
-    if (e != hipSuccess) return e;
+    {
+        const int64_t nz = (int64_t)total_cells + S.nseg;
+        int64_t nb = (nz + kBlock - 1) / kBlock;
+        if (nb > 65536) nb = 65536;
+        k_fill_zero2<<<(int)nb, kBlock, 0, s>>>(b.cell_count, total_cells, b.maxnn, S.nseg);
+    }
     k_cell_count<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_count, b.xbuild);
     const int nscan = (total_cells + kScanTile - 1) / kScanTile;
-    // The block sums live in the fill array's tail: cell_fill has room for
-    // cell capacity + 1 + scan blocks ints.
-    int* bsum = b.cell_fill + total_cells + 1;
-    k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum);
-    k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
-    k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
-                                          b.cell_fill);
+    if (nscan <= kScanOneBlockTiles) {
+        k_scan_one_block<<<1, kBlock, 0, s>>>(b.cell_count, total_cells, b.cell_start,
+                                              b.cell_fill);
+    } else {
+        // The block sums live in the fill array's tail: cell_fill has room
+        // for cell capacity + 1 + scan blocks ints.
+        int* bsum = b.cell_fill + total_cells + 1;
+        k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum);
+        k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
+        k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
+                                              b.cell_fill);
+    }
     k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_start, b.cell_fill,
                                           b.cell_atoms, b.xcell);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
