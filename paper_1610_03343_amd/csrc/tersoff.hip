@@ -187,37 +187,41 @@ __device__ __forceinline__ float t_exp(float x) { return expf(x); }
 // series ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1),
 // |s| < 0.172, summed to s^21 (first omitted term below 1e-17 relative).
 // A few ulp, against the correctly rounded library log at about half the
-// arithmetic; (beta zeta)^n needs far less.
+// arithmetic; (beta zeta)^n needs far less.  SCONST false writes the
+// constants as literals: the bond order's second logarithm takes them so,
+// since a second set held in scalar registers overflowed them.
+template <bool SCONST = true>
 __device__ __forceinline__ double t_log(double x)
 {
-    // (the constants go through scalar registers: see sgpr_const)
+    // (the constants go through scalar registers unless SCONST is false:
+    // see sgpr_const)
+    auto K = [](double c) { return SCONST ? sgpr_const(c) : c; };
     int e;
     double m = frexp(x, &e);               // x = m 2^e, m in [0.5, 1)
-    if (m < sgpr_const(0.70710678118654752440)) {
+    if (m < K(0.70710678118654752440)) {
         m *= 2.0;
         e -= 1;
     }
     const double s = (m - 1.0) * nr_rcp(m + 1.0);
     const double s2 = s * s;
-    double p = fma(sgpr_const(1.0 / 21.0), s2, sgpr_const(1.0 / 19.0));
-    p = fma(p, s2, sgpr_const(1.0 / 17.0));
-    p = fma(p, s2, sgpr_const(1.0 / 15.0));
-    p = fma(p, s2, sgpr_const(1.0 / 13.0));
-    p = fma(p, s2, sgpr_const(1.0 / 11.0));
-    p = fma(p, s2, sgpr_const(1.0 / 9.0));
-    p = fma(p, s2, sgpr_const(1.0 / 7.0));
-    p = fma(p, s2, sgpr_const(1.0 / 5.0));
-    p = fma(p, s2, sgpr_const(1.0 / 3.0));
+    double p = fma(K(1.0 / 21.0), s2, K(1.0 / 19.0));
+    p = fma(p, s2, K(1.0 / 17.0));
+    p = fma(p, s2, K(1.0 / 15.0));
+    p = fma(p, s2, K(1.0 / 13.0));
+    p = fma(p, s2, K(1.0 / 11.0));
+    p = fma(p, s2, K(1.0 / 9.0));
+    p = fma(p, s2, K(1.0 / 7.0));
+    p = fma(p, s2, K(1.0 / 5.0));
+    p = fma(p, s2, K(1.0 / 3.0));
     const double lnm = 2.0 * s + 2.0 * s * s2 * p;
     // ln 2 = ln2_hi + ln2_lo, ln2_hi with 32 significant bits (e * ln2_hi is
     // exact for |e| < 2^21), ln2_lo the rounded remainder
-    const double ln2_hi = sgpr_const(0x1.62e42fee00000p-1), ln2_lo = sgpr_const(0x1.a39ef35793c76p-33);
+    const double ln2_hi = K(0x1.62e42fee00000p-1), ln2_lo = K(0x1.a39ef35793c76p-33);
     const double de = (double)e;
     return fma(de, ln2_hi, fma(de, ln2_lo, lnm));
 }
+template <bool SCONST = true>
 __device__ __forceinline__ float t_log(float x) { return logf(x); }
-__device__ __forceinline__ double t_log1p(double x) { return log1p(x); }
-__device__ __forceinline__ float t_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ void t_sincos(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void t_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
 
@@ -251,8 +255,12 @@ __device__ __forceinline__ void angular_g(const P& p, T cs, T& g, T& dg)
 }
 
 // b(zeta) and db/dzeta; b(0) = 1, db/dzeta(0) = 0.  With u = (beta zeta)^n,
-// b = (1 + u)^(-1/(2n)) is summed as its binomial series when u is small
-// (the usual case: u ~ 1e-4 in the crystal) and through exp/log1p otherwise.
+// b = (1 + u)^(-1/(2n)) is summed as its binomial series when u < 2^-9 (few
+// bonds or wide angles), else as exp(-ln(1 + u) / (2n)).  In the Si crystal
+// u ~ 0.07 (each tetrahedral angle gives g ~ 1.0e4, c^2/d^2 being ~4e7), so
+// the second form is the common one; ln(1 + u) is taken of the rounded sum,
+// whose absolute error (half an ulp of 1 + u) becomes a relative error of
+// about 1e-16 / (2n) in b for any u, so no log1p is needed.
 template <class P, class T>
 __device__ __forceinline__ void bond_order(const P& p, T zeta, T& b, T& db)
 {
@@ -263,7 +271,7 @@ __device__ __forceinline__ void bond_order(const P& p, T zeta, T& b, T& db)
         if (u < p.u_series)
             b = T(1) + u * (p.a1 + u * (p.a2 + u * (p.a3 + u * (p.a4 + u * p.a5))));
         else
-            b = t_exp(-t_log1p(u) * p.inv2n);
+            b = t_exp(-t_log<false>(T(1) + u) * p.inv2n);
         db = -b * u * nr_rcp(T(2) * zeta * (T(1) + u));
     }
 }
@@ -491,8 +499,12 @@ __device__ __forceinline__ void tersoff_partner_terms(
 // forms zeta_c, b_c and dU_i/dr_c for its own bonds c, fetching the partner
 // bonds' unit vectors, f_C and P from the other lanes.  Atoms with more than
 // kQuad * SLOTS in-cutoff bonds go to the overflow list.
+// The single-type FP64 pass is held to 96 VGPRs, five waves per SIMD (it
+// needs 97 otherwise and spills a few values instead, measured faster); the
+// others keep their natural allocation.
 template <class T, int SLOTS, bool MULTI>
 __global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(MULTI || sizeof(T) == 4 ? 1 : 5, 8)))
 k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t cap,
                     const double4* __restrict__ xw, const int* __restrict__ nn,
                     const int* __restrict__ nl, unsigned long long* __restrict__ mask,
