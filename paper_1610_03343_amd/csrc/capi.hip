@@ -279,7 +279,6 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     t.cell_count = (int*)take(sizeof(int) * ccap);
     t.cell_start = (int*)take(sizeof(int) * (ccap + 1));
     t.cell_fill = (int*)take(sizeof(int) * (ccap + 1 + nscan));
-    t.cell_atoms = (int*)take(sizeof(int) * nn);
     t.xcell = (double4*)take(sizeof(double4) * nn);
     t.blk_cap = blk_cap;
     t.part_b = (double*)take(sizeof(double) * kPartialCols * blk_cap * kThermoRing);

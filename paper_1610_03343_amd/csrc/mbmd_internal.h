@@ -13,10 +13,11 @@
 //                    so a neighbour gather is one 32-byte access; two buffers
 //                    because the drift writes while neighbours are still read
 //   xbuild[N]        double4 positions at the last list build
-//   xcell[N]         double4 positions in cell order at the last build
-//                    (xcell[p] = xw[cell_atoms[p]]), so the search's lanes,
-//                    which also take atoms in cell order, read neighbouring
-//                    cells' atoms from neighbouring addresses
+//   xcell[N]         double4 {x, y, z, (index, type)} in cell order at the
+//                    last build (the w lane holds the atom's index and type
+//                    as two 32-bit integers), so the search's lanes, which
+//                    also take atoms in cell order, read neighbouring cells'
+//                    atoms from neighbouring addresses, one access each
 //   nn[N]            int32 list count (true count, may exceed M on overflow)
 //   nl[M][N]         int32 neighbour index, slot-major (lane i reads nl[m*N+i]
 //                    coalesced); neighbours inside the potential cutoff at
@@ -159,8 +160,7 @@ struct Buffers {
     int* cell_count;
     int* cell_start;
     int* cell_fill;
-    int* cell_atoms;
-    double4* xcell;          // [N] positions in cell order (cell_atoms order)
+    double4* xcell;          // [N] positions, index and type in cell order
     int64_t cell_cap;
     double* part_b;          // [kThermoRing][block capacity][kPartialCols]
     int64_t blk_cap;         // 256-atom block capacity, plus the rows the four-lane

@@ -144,8 +144,8 @@ k_cell_count(Segs S, const double4* __restrict__ xw, int* __restrict__ cell_of,
     if (g.build) xbuild[i] = p;
 }
 
-// Three-pass exclusive scan of the cell counts: per-block sums, a scan of the
-// block sums in one block, then the per-block scan with its offset.
+// Two-pass exclusive scan of the cell counts: per-tile sums, then the
+// per-tile scan, each tile adding the sums of the tiles before it.
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -187,25 +187,6 @@ k_scan_block_sums(const int* __restrict__ count, int ncell, int* __restrict__ bs
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_scan_bsums(int* __restrict__ bsum, int nblocks)
-{
-    __shared__ int lds[kBlock / 64];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nblocks; base += kBlock) {
-        const int i = base + threadIdx.x;
-        const int v = i < nblocks ? bsum[i] : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, lds, total);
-        if (i < nblocks) bsum[i] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
 k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ bsum,
              int* __restrict__ start, int* __restrict__ fill)
 {
@@ -218,8 +199,12 @@ k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ b
         v[k] = base + k < ncell ? count[base + k] : 0;
         s += v[k];
     }
+    // the tile's offset: the totals of the tiles before it
+    int before = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) before += bsum[t];
     int total;
-    int run = bsum[blockIdx.x] + block_exclusive_scan(s, lds, total);
+    block_exclusive_scan(before, lds, total);
+    int run = total + block_exclusive_scan(s, lds, total);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < ncell) {
@@ -233,7 +218,7 @@ k_scan_write(const int* __restrict__ count, int ncell, const int* __restrict__ b
 }
 
 // The whole scan in one block, tile after tile with a running carry (grids
-// of at most kScanOneBlockTiles tiles: one launch instead of three).
+// of at most kScanOneBlockTiles tiles: one launch instead of two).
 constexpr int kScanOneBlockTiles = 16;
 
 __global__ void __launch_bounds__(kBlock)
@@ -277,18 +262,21 @@ __global__ void k_fill_zero2(int* __restrict__ a, int64_t na, int* __restrict__ 
     }
 }
 
+// Atom i's position in cell order, its index and type packed into the w
+// lane as two 32-bit integers (low word i, high word the type): the search
+// reads a candidate's position, index and type in one 32-byte access.  The
+// w lane is never used in arithmetic.
 __global__ void __launch_bounds__(kBlock)
 k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell_of,
-            const int* __restrict__ start, int* __restrict__ fill, int* __restrict__ cell_atoms,
-            double4* __restrict__ xcell)
+            const int* __restrict__ start, int* __restrict__ fill, double4* __restrict__ xcell)
 {
     int sid;
     int64_t i;
     if (!block_atom(S, sid, i)) return;
     const int c = cell_of[i];
     const int p = start[c] + atomicAdd(&fill[c], 1);
-    cell_atoms[p] = (int)i;
-    xcell[p] = xw[i];
+    const double4 x = xw[i];
+    xcell[p] = make_double4(x.x, x.y, x.z, __hiloint2double((int)x.w, (int)i));
 }
 
 // ---- neighbour search -----------------------------------------------------
@@ -301,6 +289,7 @@ constexpr int kSearchBlock = kBlock / 2;
 // atoms).  The lists do not depend on the choice.
 constexpr int kQuadBuildBlocks = 512;
 constexpr int kSearchLanesLarge = 1;    // lanes per atom above that size
+constexpr int kSearchCands = 2;         // candidates loaded together
 constexpr int kReverseLanesLarge = 2;
 
 // Value of lane (lane xor K) of the same quad (DPP quad permutation).
@@ -332,7 +321,7 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 }
 
 // LANES (1, 2 or 4) lanes per atom of a segment being built: lane q walks the
-// stencil offsets k = q, q + LANES, ... into a sorted list of its own, kept
+// stencil rows q, q + LANES, ... into a sorted list of its own, kept
 // in LDS (column-major over the block so that neighbouring threads hit
 // distinct banks); each lane then writes its entries at their ranks in the
 // union of the lanes' lists, slot-major.  The union's order does not depend
@@ -347,14 +336,15 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // TYPED: the radii of each pair come from R (copied to LDS), indexed by the
 // types in the w lanes, and the stencil is pruned with the largest radius of
 // atom i's type.
-template <bool TYPED, int LANES>
+// CW candidates of a cell are loaded together, so that a lane waits once
+// per CW candidates (a cell holds a few atoms).
+template <bool TYPED, int LANES, int CW>
 __global__ void __launch_bounds__(kSearchBlock)
 k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, double rl2_hi,
          double rc2, ListRadii R, int M,
          int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
-         const int* __restrict__ cell_atoms, int* __restrict__ nn, int* __restrict__ nl,
-         int* __restrict__ rev, int* __restrict__ maxnn, unsigned* __restrict__ status,
-         unsigned* __restrict__ sstat)
+         int* __restrict__ nn, int* __restrict__ nl, int* __restrict__ maxnn,
+         unsigned* __restrict__ status, unsigned* __restrict__ sstat)
 {
     extern __shared__ int lbuf[];
     __shared__ int lds_max[kSearchBlock / 64];
@@ -386,9 +376,10 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
     int* buf = lbuf + threadIdx.x;
     if (active) {
         const int p0 = start[g.cell_off] + local;
-        i = cell_atoms[p0];
+        const Box box = g.box;
         const double4 xi = xcell[p0];
-        const int ti = TYPED ? min(max((int)xi.w, 0), R.nt - 1) : 0;
+        i = __double2loint(xi.w);
+        const int ti = TYPED ? min(max(__double2hiint(xi.w), 0), R.nt - 1) : 0;
         double rl2_i = rl2;   // largest list radius squared of i's pairs
         if constexpr (TYPED) {
             rl2_i = t_rl2[ti * kMaxTypes];
@@ -429,71 +420,114 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                         if (gap2[2][oz + 1] + gap2[1][oy + 1] + gap2[0][ox + 1] <= skip2)
                             visit |= 1u << (9 * (oz + 1) + 3 * (oy + 1) + (ox + 1));
         }
-        // Candidate j (cell-order slot p) against the list radius of the pair,
-        // inserted into the LDS list (capacity M) ordered by key.
-        auto consider = [&](int j, const double4& xj) {
-            if (j == (int)i) return;
+        // Candidate at cell-order slot p (atom i itself sits at p0) against
+        // the list radius of the pair; an entry is appended to the lane's LDS
+        // list (capacity M), which is sorted by key once the walk is done.
+        // Past M entries (an overflow, which fails the call) an entry
+        // replaces the largest key if it is smaller, so the list keeps the
+        // M smallest keys.
+        auto consider = [&](int p, const double4& xj) {
+            if (p == p0) return;
+            const int j = __double2loint(xj.w);
             double r2;
             double pl2 = rl2, pl2_lo = rl2_lo, pl2_hi = rl2_hi, pc2 = rc2;
             if constexpr (TYPED) {
-                const int t = ti * kMaxTypes + min(max((int)xj.w, 0), R.nt - 1);
+                const int t = ti * kMaxTypes + min(max(__double2hiint(xj.w), 0), R.nt - 1);
                 pl2 = t_rl2[t];
                 pl2_lo = pl2 * (1.0 - 1e-10);
                 pl2_hi = pl2 * (1.0 + 1e-10);
                 pc2 = t_rc2[t];
             }
-            if (in_list(xi, xj, g.box, pl2, pl2_lo, pl2_hi, r2)) {
+            if (in_list(xi, xj, box, pl2, pl2_lo, pl2_hi, r2)) {
                 const unsigned key = (unsigned)j | (r2 < pc2 ? 0u : 0x80000000u);
-                int pos = cnt < M ? cnt : M;
-                while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
-                    if (pos < M) buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
-                    --pos;
+                if (cnt < M) {
+                    buf[cnt * kSearchBlock] = (int)key;
+                } else if (M > 0) {
+                    int top = 0;
+                    for (int t = 1; t < M; ++t)
+                        if ((unsigned)buf[t * kSearchBlock] > (unsigned)buf[top * kSearchBlock])
+                            top = t;
+                    if ((unsigned)buf[top * kSearchBlock] > key) buf[top * kSearchBlock] = (int)key;
                 }
-                if (pos < M) buf[pos * kSearchBlock] = (int)key;
                 ++cnt;
             }
         };
-        // First cell-order slot and end of the cell at stencil offset k
-        // (an empty range for a cell left out).
-        auto cell_range = [&](int k, int& b, int& e) {
-            b = e = 0;
-            if (k < 27 && ((visit >> k) & 1u)) {
-                const int oz = k / 9 - 1, oy = (k / 3) % 3 - 1, ox = k % 3 - 1;
+        // Stencil row rr = 3 (oz + 1) + (oy + 1): its visited cells, at x
+        // offsets -1 (if visited), 0 and +1 (if visited), are neighbours in
+        // cell order and so one run [b, e) of xcell, except where the row
+        // crosses the periodic boundary in x, whose far cell is a second run
+        // [b2, e2).  A row whose middle cell is left out is empty (the middle
+        // cell is the row's nearest, so its outer cells are left out too).
+        auto row_range = [&](int rr, int& b, int& e, int& b2, int& e2) {
+            b = e = b2 = e2 = 0;
+            const unsigned bits = rr < 9 ? (visit >> (3 * rr)) & 7u : 0u;
+            if (bits & 2u) {
+                const int oz = rr / 3 - 1, oy = rr % 3 - 1;
                 // periodic wrap by one cell (no integer division per offset)
                 auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-                const int zz = wrap(cz + oz, g.nc[2]);
-                const int yy = wrap(cy + oy, g.nc[1]);
-                const int xx = wrap(cx + ox, g.nc[0]);
-                const int cc = g.cell_off + (zz * g.nc[1] + yy) * g.nc[0] + xx;
-                b = start[cc];
-                e = start[cc + 1];
+                const int nx = g.nc[0];
+                const int row =
+                    g.cell_off + (wrap(cz + oz, g.nc[2]) * g.nc[1] + wrap(cy + oy, g.nc[1])) * nx;
+                int xa = cx - (int)(bits & 1u), xb = cx + (int)(bits >> 2);
+                if (xa < 0) {
+                    b2 = start[row + nx - 1];
+                    e2 = start[row + nx];
+                    xa = 0;
+                }
+                if (xb >= nx) {
+                    b2 = start[row];
+                    e2 = start[row + 1];
+                    xb = nx - 1;
+                }
+                b = start[row + xa];
+                e = start[row + xb + 1];
             }
         };
-        // Lane q of every quad walks the same offsets in the same order (a
-        // pruned cell is an empty iteration), which keeps the wave's reads
-        // together; the next cell's range is fetched before the current cell
-        // is scanned, and the scan takes two candidates per iteration, so
-        // more loads are in flight per lane.
-        int b, e;
-        cell_range(q, b, e);
-        for (int k = q; k < 27; k += LANES) {
-            int nb, ne;
-            cell_range(k + LANES, nb, ne);
-            for (int p = b; p < e; p += 2) {
-                const bool two = p + 1 < e;
-                const int j0 = cell_atoms[p];
-                const double4 x0 = xcell[p];
-                int j1 = -1;
-                double4 x1 = x0;
-                if (two) {
-                    j1 = cell_atoms[p + 1];
-                    x1 = xcell[p + 1];
-                }
-                consider(j0, x0);
-                if (two) consider(j1, x1);
+        // The candidates of one run, CW loaded before any is tested.
+        auto scan = [&](int b, int e) {
+            for (int p = b; p < e; p += CW) {
+                // slots past the run's end re-read its last atom (in bounds,
+                // no branch around the loads) and are not tested
+                double4 xv[CW];
+#pragma unroll
+                for (int u = 0; u < CW; ++u) xv[u] = xcell[min(p + u, e - 1)];
+                // every loaded word counts as used here: the loads are issued
+                // back to back (none sunk into the tests, none waiting on the
+                // reuse of an unused word's register) and waited on once
+#pragma unroll
+                for (int u = 0; u < CW; ++u)
+                    asm volatile("" ::"v"(xv[u].x), "v"(xv[u].y), "v"(xv[u].z), "v"(xv[u].w));
+#pragma unroll
+                for (int u = 0; u < CW; ++u)
+                    if (p + u < e) consider(p + u, xv[u]);
             }
+        };
+        // Lane q of every quad walks the rows q, q + LANES, ... in the same
+        // order (a row left out is an empty iteration), which keeps the
+        // wave's reads together; the next row's runs are fetched before the
+        // current row is scanned.
+        int b, e, b2, e2;
+        row_range(q, b, e, b2, e2);
+        for (int rr = q; rr < 9; rr += LANES) {
+            int nb, ne, nb2, ne2;
+            row_range(rr + LANES, nb, ne, nb2, ne2);
+            scan(b, e);
+            scan(b2, e2);
             b = nb;
             e = ne;
+            b2 = nb2;
+            e2 = ne2;
+        }
+        // the lane's entries in ascending key order (keys are distinct)
+        const int w = cnt < M ? cnt : M;
+        for (int t = 1; t < w; ++t) {
+            const unsigned key = (unsigned)buf[t * kSearchBlock];
+            int pos = t;
+            while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
+                buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
+                --pos;
+            }
+            buf[pos * kSearchBlock] = (int)key;
         }
     }
     // counts of the quad's other lanes (every lane of the wave takes part)
@@ -527,10 +561,8 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                 const int* col = lbuf + (threadIdx.x ^ r);
                 for (int t = 0; t < wr[r - 1] && (unsigned)col[t * kSearchBlock] < key; ++t) ++rank;
             }
-            if (rank < M) {
-                nl[(int64_t)rank * cap + i] = (int)(key & 0x7fffffffu);
-                rev[(int64_t)rank * cap + i] = 0;   // an in-range slot until k_reverse sets it
-            }
+            // (k_reverse, which always follows, writes every reverse slot)
+            if (rank < M) nl[(int64_t)rank * cap + i] = (int)(key & 0x7fffffffu);
         }
     }
     // largest count of the block, one atomic per block
@@ -617,12 +649,11 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
         // for cell capacity + 1 + scan blocks ints.
         int* bsum = b.cell_fill + total_cells + 1;
         k_scan_block_sums<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum);
-        k_scan_bsums<<<1, kBlock, 0, s>>>(bsum, nscan);
         k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
                                               b.cell_fill);
     }
     k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_start, b.cell_fill,
-                                          b.cell_atoms, b.xcell);
+                                          b.xcell);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
     if (typed && (typed->nt < 1 || typed->nt > kMaxTypes)) return hipErrorInvalidValue;
@@ -634,9 +665,9 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
     auto search = [&](auto typed_tag, auto lanes_tag) {
         constexpr bool TY = decltype(typed_tag)::value;
         constexpr int LN = decltype(lanes_tag)::value;
-        k_search<TY, LN><<<nsb, kSearchBlock, lds, s>>>(
+        k_search<TY, LN, kSearchCands><<<nsb, kSearchBlock, lds, s>>>(
             S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
-            b.cell_atoms, b.nn, b.nl, b.rev, b.maxnn, b.status, b.sstat);
+            b.nn, b.nl, b.maxnn, b.status, b.sstat);
     };
     using T1 = std::integral_constant<int, 1>;
     using T2 = std::integral_constant<int, 2>;
