@@ -271,7 +271,7 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     t.xbuild = (double4*)take(sizeof(double4) * nn);
     t.nn = (int*)take(sizeof(int) * nn);
     t.nl = (int*)take(sizeof(int) * nn * M);
-    t.rev = (int*)take(sizeof(int) * nn * M);
+    t.rev = (uint8_t*)take(sizeof(uint8_t) * nn * M);
     t.mask = (unsigned long long*)take(sizeof(unsigned long long) * nn);
     t.dpart = take(sizeof(double) * 3 * nn * M);
     t.cell_of = (int*)take(sizeof(int) * nn);

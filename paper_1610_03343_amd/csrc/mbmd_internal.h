@@ -22,7 +22,7 @@
 //   nl[M][N]         int32 neighbour index, slot-major (lane i reads nl[m*N+i]
 //                    coalesced); neighbours inside the potential cutoff at
 //                    build time first, each group by ascending index
-//   rev[M][N]        int32 slot of i inside the list of nl[m][i]
+//   rev[M][N]        uint8 slot of i inside the list of nl[m][i] (M <= 64)
 //   mask[N]          uint64 bit m set iff slot m lies inside the potential cutoff
 //   dpart[M][N][3]   T: dU_i/dr_ij for list slot m (written for in-cutoff slots only)
 //   U[N], F[3][N], W[9][N] (component 3a+b), J[3][N], v[3][N]: FP64 SoA
@@ -153,7 +153,7 @@ struct Buffers {
     double4* xbuild;
     int* nn;
     int* nl;
-    int* rev;
+    uint8_t* rev;
     unsigned long long* mask;
     void* dpart;
     int* cell_of;

@@ -585,7 +585,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
 template <int LANES>
 __global__ void __launch_bounds__(kBlock)
 k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M, int64_t cap,
-          int* __restrict__ rev, unsigned* __restrict__ status)
+          uint8_t* __restrict__ rev, unsigned* __restrict__ status)
 {
     const int lbl = xcd_block(blockIdx.x, gridDim.x);
     const int lb = lbl / LANES;
@@ -622,8 +622,8 @@ k_reverse(Segs S, const int* __restrict__ nn, const int* __restrict__ nl, int M,
             rev[(int64_t)m * cap + i] = 0;
             continue;
         }
-        rev[(int64_t)m * cap + i] = s;
-        if (both_complete) rev[(int64_t)s * cap + j] = m;
+        rev[(int64_t)m * cap + i] = (uint8_t)s;
+        if (both_complete) rev[(int64_t)s * cap + j] = (uint8_t)m;
     }
 }
 

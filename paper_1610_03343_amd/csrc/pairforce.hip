@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kBlock)
 k_pair_gather(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
               double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
               const int* __restrict__ nl,
-              const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
+              const uint8_t* __restrict__ rev, const unsigned long long* __restrict__ mask,
               const T* __restrict__ dpart, const double* __restrict__ U,
               double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
               double* __restrict__ J, int* __restrict__ ovf_count)
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kBlock)
 k_pair_quad(Segs S, int64_t cap, int64_t os, StepArgs a, const double4* __restrict__ xw,
             double4* __restrict__ xw_next, const double4* __restrict__ xbuild,
             const int* __restrict__ nl,
-            const int* __restrict__ rev, const unsigned long long* __restrict__ mask,
+            const uint8_t* __restrict__ rev, const unsigned long long* __restrict__ mask,
             const T* __restrict__ dpart, const double* __restrict__ U,
             double* __restrict__ vel, double* __restrict__ F, double* __restrict__ W,
             double* __restrict__ J, int* __restrict__ ovf_count)
