@@ -86,12 +86,12 @@ def algorithmic_bytes(kernel: str, k_cut: float, l_list: float, dsize: int) -> f
         # read x_i (24), list count (4), list (4 l); write mask (8), U (8), partials
         return 24 + 4 + 4 * l_list + 8 + 8 + part
     if kernel == "pair_gather":
-        # read x (24), mask (8), list + reverse slots of the in-cutoff entries
-        # (8 k), own partials, U (8), v (24); write F (24), W (72), J (24),
+        # read x (24), mask (8), list (4) + reverse slot (1) of each in-cutoff
+        # entry, own partials, U (8), v (24); write F (24), W (72), J (24),
         # v (24), x_next (24)
-        return 24 + 8 + 8 * k_cut + part + 8 + 24 + 24 + 72 + 24 + 24 + 24
+        return 24 + 8 + 5 * k_cut + part + 8 + 24 + 24 + 72 + 24 + 24 + 24
     if kernel == "neighbor_build":
-        return 24 + 4 + 8 * l_list
+        return 24 + 4 + 5 * l_list
     return 0.0
 
 
