@@ -16,7 +16,11 @@ mbmd_nve_continue of that run by --steps steps, bracketed by device
 synchronisation: each timed step has its one force evaluation, and the list
 builds are those the 20-step schedule puts among the timed steps (with
 --warmup 0 the timed run starts from the input instead, and its initial
-list build and step-0 force evaluation fall inside the time).
+list build and step-0 force evaluation fall inside the time).  The default
+--warmup of 500 steps (about 40 ms of sustained work) covers the rise of the
+GPU's clock under load: in kernel traces the site pass takes ~43 us in the
+first milliseconds of a run and ~36 us from about 30 ms on, so a short
+warm-up times the rise (the 20-step figure with --warmup 5 is mostly that).
 
 Also measured, as extra fields of the same line:
   mixed    the same input with FP32 bond-order/force arithmetic, --mixed-steps
@@ -745,7 +749,8 @@ def main():
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps before each timed run (the clock's rise under load)")
     ap.add_argument("--cpu-steps", type=int, default=10,
                     help="oracle sample length, single thread")
     ap.add_argument("--cpu-steps-all", type=int, default=20,
