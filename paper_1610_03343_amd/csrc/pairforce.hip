@@ -503,8 +503,8 @@ __device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp
     double vals[kPartialCols];
 #pragma unroll
     for (int c = 0; c < kPartialCols; ++c) vals[c] = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += kFoldThreads) {
-        if (groups) {
+    if (groups) {
+        for (int b = b0 + threadIdx.x; b < b1; b += kFoldThreads) {
             const double* p = rowp + 4 * (int64_t)b * kPartialCols;
             const int a0 = (b - g.blk) * kBlock;
 #pragma unroll
@@ -514,10 +514,30 @@ __device__ __forceinline__ void fold_segment_row(const double* __restrict__ rowp
                 for (int k = 0; k < 4; ++k) t += a0 + 64 * k < g.n ? p[k * kPartialCols + c] : 0.0;
                 vals[c] += t;
             }
-        } else {
+        }
+    } else {
+        // block rows b, b + kFoldThreads, ... in order; the next row's loads
+        // are issued before the current row is added (one wait per row
+        // instead of a load-then-add chain)
+        double cur[kPartialCols], nxt[kPartialCols];
+        int b = b0 + threadIdx.x;
+        if (b < b1) {
             const double* p = rowp + (int64_t)b * kPartialCols;
 #pragma unroll
-            for (int c = 0; c < kPartialCols; ++c) vals[c] += p[c];
+            for (int c = 0; c < kPartialCols; ++c) cur[c] = p[c];
+        }
+        for (; b < b1; b += kFoldThreads) {
+            const int bn = b + kFoldThreads;
+            if (bn < b1) {
+                const double* p = rowp + (int64_t)bn * kPartialCols;
+#pragma unroll
+                for (int c = 0; c < kPartialCols; ++c) nxt[c] = p[c];
+            }
+#pragma unroll
+            for (int c = 0; c < kPartialCols; ++c) {
+                vals[c] += cur[c];
+                cur[c] = nxt[c];
+            }
         }
     }
     block_sum_cols<kFoldThreads>(vals, lds, lds_tot);
@@ -551,10 +571,10 @@ hipError_t launch_thermo_fold(const Buffers& b, const Segs& S, int sid, int firs
     return hipGetLastError();
 }
 
-// End of a one-structure run in one launch: blocks 0 .. nblk - 1 copy the
-// final positions xw back to the caller's pos[3][n] (as the store kernel
-// does), blocks nblk .. nblk + count - 1 fold thermo rows first .. first +
-// count - 1 from the ring (as k_thermo_fold with ring0 = 0).
+// End of a one-structure run in one launch: blocks 0 .. count - 1 fold
+// thermo rows first .. first + count - 1 from the ring (as k_thermo_fold with
+// ring0 = 0), blocks count .. count + nblk - 1 copy the final positions xw
+// back to the caller's pos[3][n] (as the store kernel does).
 __global__ void __launch_bounds__(kFoldThreads)
 k_end_single(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int first,
              double* __restrict__ thermo, const double4* __restrict__ xw,
@@ -563,13 +583,15 @@ k_end_single(const double* __restrict__ part_b, int64_t blk_cap, Segs S, int fir
     __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     const Seg& g = S.seg[0];
-    if ((int)blockIdx.x >= S.nblk) {
-        const int k = first + (int)blockIdx.x - S.nblk;
+    const int count = (int)gridDim.x - S.nblk;
+    if ((int)blockIdx.x < count) {   // the folds' serial loops start first
+        const int k = first + (int)blockIdx.x;
         const double* rowp = part_b + (int64_t)(k % kThermoRing) * blk_cap * kPartialCols;
         fold_segment_row(rowp, S, g, lds, lds_tot, thermo + (int64_t)k * kThermoCols);
         return;
     }
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, S.nblk) * kBlock + threadIdx.x;
+    const int64_t i =
+        (int64_t)xcd_block((int)blockIdx.x - count, S.nblk) * kBlock + threadIdx.x;
     if (i >= g.n) return;
     const double4 p = xw[i];
     pos[i] = p.x;
@@ -769,12 +791,12 @@ __device__ __forceinline__ void block_max_to_slot(double v, double* lds_max,
     }
 }
 
-// Prologue of a continued one-structure run in one launch: blocks
-// 0 .. nblk - 1 stage the caller's positions (as the staging kernel does)
-// and apply the half-kick and drift into x_next (kick_drift_atom); block
-// nblk, when `thermo` is set, folds the previous run's last step (ring row
-// `ring_row`) into thermo row 0; the first atom block sets the phase word to
-// `phase`.
+// Prologue of a continued one-structure run in one launch: block 0, when
+// `thermo` is set, folds the previous run's last step (ring row `ring_row`)
+// into thermo row 0 (first, so that its serial loop overlaps the rest); the
+// nblk atom blocks after it stage the caller's positions (as the staging
+// kernel does) and apply the half-kick and drift into x_next
+// (kick_drift_atom); the first atom block sets the phase word to `phase`.
 __global__ void __launch_bounds__(kBlock)
 k_resume_prologue(Segs S, int64_t os, const double* __restrict__ pos,
                   const int32_t* __restrict__ types, int ntypes, double4* __restrict__ xw_next,
@@ -787,12 +809,13 @@ k_resume_prologue(Segs S, int64_t os, const double* __restrict__ pos,
     __shared__ double lds[kFoldThreads / 64][kPartialCols];
     __shared__ double lds_tot[kPartialCols];
     const Seg& g = S.seg[0];
-    if ((int)blockIdx.x == S.nblk) {
+    const int nfold = (int)gridDim.x - S.nblk;   // 0 or 1, dispatched first
+    if ((int)blockIdx.x < nfold) {
         const double* rowp = part_b + (int64_t)ring_row * blk_cap * kPartialCols;
         fold_segment_row(rowp, S, g, lds, lds_tot, thermo);
         return;
     }
-    const int lb = xcd_block(blockIdx.x, S.nblk);
+    const int lb = xcd_block((int)blockIdx.x - nfold, S.nblk);
     if (lb == 0 && threadIdx.x == 0) *phase_word = phase;
     const int64_t i = (int64_t)lb * kBlock + threadIdx.x;
     double disp2 = 0.0;
