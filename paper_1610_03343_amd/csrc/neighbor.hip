@@ -483,14 +483,18 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                 e = start[row + xb + 1];
             }
         };
-        // The candidates of one run, CW loaded before any is tested.
-        auto scan = [&](int b, int e) {
-            for (int p = b; p < e; p += CW) {
-                // slots past the run's end re-read its last atom (in bounds,
-                // no branch around the loads) and are not tested
+        // The candidates of a row's runs [b, e) and [b2, e2) in one loop (so
+        // that a wave whose lanes at the box's x faces have a second run
+        // does not loop twice), CW loaded before any is tested.
+        auto scan = [&](int b, int e, int b2, int e2) {
+            const int n1 = e - b, n = n1 + (e2 - b2);
+            auto slot = [&](int t) { return t < n1 ? b + t : b2 + (t - n1); };
+            for (int t = 0; t < n; t += CW) {
+                // positions past the row's end re-read its last atom (in
+                // bounds, no branch around the loads) and are not tested
                 double4 xv[CW];
 #pragma unroll
-                for (int u = 0; u < CW; ++u) xv[u] = xcell[min(p + u, e - 1)];
+                for (int u = 0; u < CW; ++u) xv[u] = xcell[slot(min(t + u, n - 1))];
                 // every loaded word counts as used here: the loads are issued
                 // back to back (none sunk into the tests, none waiting on the
                 // reuse of an unused word's register) and waited on once
@@ -499,7 +503,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
                     asm volatile("" ::"v"(xv[u].x), "v"(xv[u].y), "v"(xv[u].z), "v"(xv[u].w));
 #pragma unroll
                 for (int u = 0; u < CW; ++u)
-                    if (p + u < e) consider(p + u, xv[u]);
+                    if (t + u < n) consider(slot(t + u), xv[u]);
             }
         };
         // Lane q of every quad walks the rows q, q + LANES, ... in the same
@@ -511,8 +515,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         for (int rr = q; rr < 9; rr += LANES) {
             int nb, ne, nb2, ne2;
             row_range(rr + LANES, nb, ne, nb2, ne2);
-            scan(b, e);
-            scan(b2, e2);
+            scan(b, e, b2, e2);
             b = nb;
             e = ne;
             b2 = nb2;
