@@ -16,10 +16,12 @@ struct Disp {
     double x, y, z, r2;
 };
 
-// Minimum-image displacement r_ij = r_j - r_i and its square, with no
-// contraction to fused multiply-add: the kernels for atom i and for atom j
-// then agree bit for bit on r_ij^2 = r_ji^2, so the in-cutoff masks of the
-// two atoms are mutually consistent.
+// Minimum-image displacement r_ij = r_j - r_i and its square, in explicit
+// operations: r_j - r_i, the product by 1/L and the rounding are exactly
+// negated for the pair seen from j, and so are a fused multiply-add's
+// operands and exact result, so the kernels for atom i and for atom j agree
+// bit for bit on r_ij = -r_ji and r_ij^2 = r_ji^2, and the in-cutoff masks of
+// the two atoms are mutually consistent.
 __device__ __forceinline__ Disp cut_disp(const double4& a, const double4& b, const Box& box)
 {
 #pragma clang fp contract(off)
@@ -27,10 +29,10 @@ __device__ __forceinline__ Disp cut_disp(const double4& a, const double4& b, con
     d.x = b.x - a.x;
     d.y = b.y - a.y;
     d.z = b.z - a.z;
-    d.x = d.x - box.L[0] * rint(d.x * box.inv[0]);
-    d.y = d.y - box.L[1] * rint(d.y * box.inv[1]);
-    d.z = d.z - box.L[2] * rint(d.z * box.inv[2]);
-    d.r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    d.x = fma(-box.L[0], rint(d.x * box.inv[0]), d.x);
+    d.y = fma(-box.L[1], rint(d.y * box.inv[1]), d.y);
+    d.z = fma(-box.L[2], rint(d.z * box.inv[2]), d.z);
+    d.r2 = fma(d.x, d.x, fma(d.y, d.y, d.z * d.z));
     return d;
 }
 
