@@ -96,68 +96,81 @@ __device__ __forceinline__ void sw_geometry(const Disp& d, T& ux, T& uy, T& uz, 
     uz = dz * ir;
 }
 
-template <class T, int MAXC, bool FIXED>
+// Threads per block of the one-thread-per-atom overflow pass: its bond
+// table (seven values and the list slot per bond, up to 64 bonds) lives in
+// LDS, one column per thread, rather than in scratch memory (a launch with
+// scratch took ~4.5 us longer on an empty list).
+constexpr int kSWOvfThreads = 16;
+
+// Site energy and partials of atom i, one thread, any number of in-cutoff
+// bonds; tab and slot are the block's LDS bond table, col this thread's
+// column.
+template <class T>
 __device__ __forceinline__ void sw_site(const SWK<T>& p, int64_t i, int64_t cap, const double4& xi,
                                         unsigned long long msk, int cnt,
                                         const int* __restrict__ nl,
                                         const double4* __restrict__ xw, const Box& box,
-                                        double* __restrict__ U, T* __restrict__ dpart)
+                                        double* __restrict__ U, T* __restrict__ dpart,
+                                        T (*tab)[kMaxSlots][kSWOvfThreads],
+                                        int (*slot)[kSWOvfThreads], int col)
 {
-    T ux[MAXC], uy[MAXC], uz[MAXC], rr[MAXC], ex[MAXC], qg[MAXC], dph[MAXC];
-    int slot[MAXC];
+    // bond c's unit vector, length, E_c, qg_c and phi2'(r_c)
+    auto ux = [&](int c) -> T& { return tab[0][c][col]; };
+    auto uy = [&](int c) -> T& { return tab[1][c][col]; };
+    auto uz = [&](int c) -> T& { return tab[2][c][col]; };
+    auto rr = [&](int c) -> T& { return tab[3][c][col]; };
+    auto ex = [&](int c) -> T& { return tab[4][c][col]; };
+    auto qg = [&](int c) -> T& { return tab[5][c][col]; };
+    auto dph = [&](int c) -> T& { return tab[6][c][col]; };
     unsigned long long rem = msk;
     double u_i = 0.0;
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
-        ux[c] = uy[c] = uz[c] = rr[c] = ex[c] = qg[c] = dph[c] = T(0);
-        slot[c] = 0;
-        if (c < cnt) {
-            const int m = __builtin_ctzll(rem);
-            slot[c] = m;
-            rem &= rem - 1;
-            const int j = nl[(int64_t)m * cap + i];
-            T ir, phi;
-            sw_geometry(cut_disp(xi, xw[j], box), ux[c], uy[c], uz[c], rr[c], ir);
-            sw_bond(p, rr[c], ir, ex[c], qg[c], phi, dph[c]);
-            u_i += 0.5 * (double)phi;
-        }
+    for (int c = 0; c < cnt; ++c) {
+        const int m = __builtin_ctzll(rem);
+        slot[c][col] = m;
+        rem &= rem - 1;
+        const int j = nl[(int64_t)m * cap + i];
+        T x, y, z, r, ir, e, g, phi, d;
+        sw_geometry(cut_disp(xi, xw[j], box), x, y, z, r, ir);
+        sw_bond(p, r, ir, e, g, phi, d);
+        ux(c) = x;
+        uy(c) = y;
+        uz(c) = z;
+        rr(c) = r;
+        ex(c) = e;
+        qg(c) = g;
+        dph(c) = d;
+        u_i += 0.5 * (double)phi;
     }
     // three-body energy over unordered pairs (vertex i)
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
-#pragma unroll
-        for (int e = c + 1; e < (FIXED ? MAXC : cnt); ++e) {
-            if (e < cnt) {
-                const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
-                const T ang = cs + T(1) / T(3);
-                u_i += (double)(p.eps_lam * ex[c] * ex[e] * ang * ang);
-            }
+    for (int c = 0; c < cnt; ++c) {
+        for (int e = c + 1; e < cnt; ++e) {
+            const T cs = ux(c) * ux(e) + uy(c) * uy(e) + uz(c) * uz(e);
+            const T ang = cs + T(1) / T(3);
+            u_i += (double)(p.eps_lam * ex(c) * ex(e) * ang * ang);
         }
     }
     U[i] = u_i;
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
-        if (c < cnt) {
-            const T ir = nr_rcp(rr[c]);
-            T dx = T(0.5) * dph[c] * ux[c], dy = T(0.5) * dph[c] * uy[c], dz = T(0.5) * dph[c] * uz[c];
-#pragma unroll
-            for (int e = 0; e < (FIXED ? MAXC : cnt); ++e) {
-                if (e != c && e < cnt) {
-                    const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
-                    const T ang = cs + T(1) / T(3);
-                    const T ee = p.eps_lam * ex[c] * ex[e];
-                    const T radial = -ee * ang * ang * qg[c];
-                    const T angular = T(2) * ee * ang * ir;
-                    dx += radial * ux[c] + angular * (ux[e] - cs * ux[c]);
-                    dy += radial * uy[c] + angular * (uy[e] - cs * uy[c]);
-                    dz += radial * uz[c] + angular * (uz[e] - cs * uz[c]);
-                }
+    for (int c = 0; c < cnt; ++c) {
+        const T uxc = ux(c), uyc = uy(c), uzc = uz(c), exc = ex(c), qgc = qg(c);
+        const T ir = nr_rcp(rr(c));
+        T dx = T(0.5) * dph(c) * uxc, dy = T(0.5) * dph(c) * uyc, dz = T(0.5) * dph(c) * uzc;
+        for (int e = 0; e < cnt; ++e) {
+            if (e != c) {
+                const T uxe = ux(e), uye = uy(e), uze = uz(e);
+                const T cs = uxc * uxe + uyc * uye + uzc * uze;
+                const T ang = cs + T(1) / T(3);
+                const T ee = p.eps_lam * exc * ex(e);
+                const T radial = -ee * ang * ang * qgc;
+                const T angular = T(2) * ee * ang * ir;
+                dx += radial * uxc + angular * (uxe - cs * uxc);
+                dy += radial * uyc + angular * (uye - cs * uyc);
+                dz += radial * uzc + angular * (uze - cs * uzc);
             }
-            T* o = dpart + ((int64_t)slot[c] * cap + i) * 3;
-            o[0] = dx;
-            o[1] = dy;
-            o[2] = dz;
         }
+        T* o = dpart + ((int64_t)slot[c][col] * cap + i) * 3;
+        o[0] = dx;
+        o[1] = dy;
+        o[2] = dz;
     }
 }
 
@@ -267,23 +280,26 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kSWOvfThreads)
 k_sw_partials_ovf(SWK<T> p, Segs S, int64_t cap, const double4* __restrict__ xw,
                   const int* __restrict__ nl, const unsigned long long* __restrict__ mask,
                   double* __restrict__ U, T* __restrict__ dpart,
                   const int* __restrict__ ovf_count, const int* __restrict__ ovf_list)
 {
+    __shared__ T tab[7][kMaxSlots][kSWOvfThreads];
+    __shared__ int slot[kMaxSlots][kSWOvfThreads];
     const int total = *ovf_count;
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
+    for (int k = blockIdx.x * kSWOvfThreads + threadIdx.x; k < total;
+         k += gridDim.x * kSWOvfThreads) {
         const int64_t i = ovf_list[k];
         const double4 xi = xw[i];
         const unsigned long long msk = mask[i];
-        sw_site<T, kMaxSlots, false>(p, i, cap, xi, msk, __popcll(msk), nl, xw,
-                                     S.seg[seg_of_atom(S, i)].box, U, dpart);
+        sw_site<T>(p, i, cap, xi, msk, __popcll(msk), nl, xw, S.seg[seg_of_atom(S, i)].box, U,
+                   dpart, tab, slot, threadIdx.x);
     }
 }
 
-constexpr int kSWOvfGrid = 64;
+constexpr int kSWOvfGrid = 256;
 
 template <class T>
 hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SWParams& p,
@@ -301,8 +317,8 @@ hipError_t launch_sw_partials(const Buffers& b, const Segs& S, int cur, const SW
         return hipGetLastError();
     }
     if (b.M > kQuad * kSWSlots && max_nn > kQuad * kSWSlots)
-        k_sw_partials_ovf<T><<<kSWOvfGrid, kBlock, 0, s>>>(k, S, b.cap, b.xw[cur], b.nl, b.mask,
-                                                           b.U, dp, b.ovf_count, b.ovf_list);
+        k_sw_partials_ovf<T><<<kSWOvfGrid, kSWOvfThreads, 0, s>>>(
+            k, S, b.cap, b.xw[cur], b.nl, b.mask, b.U, dp, b.ovf_count, b.ovf_list);
     return hipGetLastError();
 }
 
