@@ -210,7 +210,10 @@ mbmd_status mbmd_bind_workspace(mbmd_ctx *ctx, void *dev_ptr, size_t bytes);
  * else each in [0, ntypes)); the run and compute calls build the same
  * lists.  Each list holds the neighbours inside the pair's cutoff first,
  * then the others, each group by ascending atom index: a deterministic
- * order, so every per-atom sum over the list is reproducible. */
+ * order, so every per-atom sum over the list is reproducible.  When a list
+ * needs more than max_neighbors slots the call returns MBMD_ENEIGH and still
+ * writes both arrays: nn the true counts, nl the first max_neighbors entries
+ * of each list in that order. */
 mbmd_status mbmd_neighbors(mbmd_ctx *ctx, int64_t n, const double box[3], const double *pos,
                            const int32_t *types, int32_t *nn, int32_t *nl);
 

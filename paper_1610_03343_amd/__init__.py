@@ -271,16 +271,20 @@ class Context:
         self._ws = buf
 
     # -- calls --------------------------------------------------------------
-    def neighbors(self, pos: torch.Tensor, box, types=None):
+    def neighbors(self, pos: torch.Tensor, box, types=None, allow_overflow=False):
+        """(nn, nl) of mbmd_neighbors.  A list longer than max_neighbors
+        raises MBMD_ENEIGH, unless allow_overflow: then the arrays are
+        returned as the call left them (true counts, the first entries)."""
         n = pos.shape[1]
         M = self.max_neighbors
         nn = torch.zeros(n, dtype=torch.int32, device=self.device)
         nl = torch.full((M, n), -1, dtype=torch.int32, device=self.device)
-        self._check(_lib.mbmd_neighbors(self._h, n, _box(box), _dptr(pos, (3, n), "pos"),
-                                        _dptr(types, (n,), "types", torch.int32),
-                                        _dptr(nn, (n,), "nn", torch.int32),
-                                        _dptr(nl, (M, n), "nl", torch.int32)),
-                    "mbmd_neighbors")
+        code = _lib.mbmd_neighbors(self._h, n, _box(box), _dptr(pos, (3, n), "pos"),
+                                   _dptr(types, (n,), "types", torch.int32),
+                                   _dptr(nn, (n,), "nn", torch.int32),
+                                   _dptr(nl, (M, n), "nl", torch.int32))
+        if not (allow_overflow and code == MBMD_ENEIGH):
+            self._check(code, "mbmd_neighbors")
         return nn, nl
 
     def _outputs(self, n, out):

@@ -70,6 +70,37 @@ def test_neighbor_lists_dense_lattice(pot, a):
                  max_neighbors=32)
 
 
+@pytest.mark.parametrize("pot,a,cells", [("tersoff", 4.2, 6), ("sw", 4.9, 5)])
+def test_overflowing_lists_keep_their_first_entries(pot, a, cells):
+    """With 8 slots for lists of up to 28 neighbours the build reports
+    MBMD_ENEIGH, and what it stored is still defined: the true count per atom
+    and, in the 8 slots, the first 8 entries of the full list in its stated
+    order (inside the cutoff first, then the others, each by ascending
+    index), the entries with the 8 smallest keys."""
+    import oracle
+    import torch
+    import paper_1610_03343_amd as mb
+    s = wl.silicon_crystal(cells, seed=322, sigma=0.05, a=a)
+    M = 8
+    with context(pot, max_neighbors=M) as ctx:
+        with pytest.raises(mb.MbmdError) as e:
+            ctx.neighbors(to_dev(s.pos), s.box)
+        assert e.value.code == mb.MBMD_ENEIGH
+        nn, nl = ctx.neighbors(to_dev(s.pos), s.box, allow_overflow=True)
+        torch.cuda.synchronize()
+        nn, nl = nn.cpu().numpy(), nl.cpu().numpy()
+    onn, onl = oracle.neighbors(s.pos, s.box, RLIST[pot], 64, method="brute")
+    assert np.array_equal(nn, onn)
+    assert onn.max() > M
+    rc = PARAMS[pot]["S"] if pot == "tersoff" else PARAMS[pot]["a"] * PARAMS[pot]["sigma"]
+    for i in range(s.n):
+        full = onl[i, :onn[i]]
+        d = min_image(s.pos[full] - s.pos[i], s.box)
+        inside = np.sum(d * d, axis=1) < rc * rc
+        want = np.concatenate([full[inside], full[~inside]])[:M]
+        assert np.array_equal(nl[:len(want), i], want), i
+
+
 @pytest.mark.parametrize("pot", ["tersoff", "sw"])
 @pytest.mark.parametrize("name", list(SYSTEMS))
 def test_compute_fp64_parity(pot, name):
