@@ -232,8 +232,8 @@ mbmd_status mbmd_compute(mbmd_ctx *ctx, mbmd_precision prec, int64_t n, const do
  * (64 MiB on each device the library runs on, held until the process ends)
  * instead of the context's workspace, and the call makes no hipMalloc,
  * hipFree, pinned-memory or other allocating call; profiling is off for it.
- * The array holds the workspace of 74,336 Tersoff atoms at 16 list slots
- * (the need grows with max_neighbors: 47,632 SW atoms at 32);
+ * The array holds the workspace of 74,712 Tersoff atoms at 16 list slots
+ * (the need grows with max_neighbors: 47,794 SW atoms at 32);
  * a larger n is refused with MBMD_ENOMEM.  Every call on one device shares
  * that device's array and leaves its contents there (the call clears what
  * it needs cleared), so calls that overlap on one device, from any contexts

@@ -274,7 +274,6 @@ size_t layout(int64_t cap, int M, int segs, bool state, char* base, Buffers* b)
     t.rev = (uint8_t*)take(sizeof(uint8_t) * nn * M);
     t.mask = (unsigned long long*)take(sizeof(unsigned long long) * nn);
     t.dpart = take(sizeof(double) * 3 * nn * M);
-    t.cell_of = (int*)take(sizeof(int) * nn);
     t.cell_cap = ccap;
     t.cell_count = (int*)take(sizeof(int) * ccap);
     t.cell_start = (int*)take(sizeof(int) * (ccap + 1));

@@ -156,7 +156,6 @@ struct Buffers {
     uint8_t* rev;
     unsigned long long* mask;
     void* dpart;
-    int* cell_of;
     int* cell_count;
     int* cell_start;
     int* cell_fill;

@@ -126,21 +126,27 @@ __device__ __forceinline__ bool block_atom(const Segs& S, int& sid, int64_t& i)
     return local < g.n;
 }
 
+// Cell (index into the cell arrays) of a wrapped position of segment g; the
+// binning, the fill and the search each evaluate it from the same position
+// and so agree on every atom's cell.
+__device__ __forceinline__ int cell_index(const Seg& g, const double4& p)
+{
+    const int cx = cell_coord(p.x, g.inv_lc[0], g.nc[0]);
+    const int cy = cell_coord(p.y, g.inv_lc[1], g.nc[1]);
+    const int cz = cell_coord(p.z, g.inv_lc[2], g.nc[2]);
+    return g.cell_off + (cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+
 __global__ void __launch_bounds__(kBlock)
-k_cell_count(Segs S, const double4* __restrict__ xw, int* __restrict__ cell_of,
-             int* __restrict__ count, double4* __restrict__ xbuild)
+k_cell_count(Segs S, const double4* __restrict__ xw, int* __restrict__ count,
+             double4* __restrict__ xbuild)
 {
     int sid;
     int64_t i;
     if (!block_atom(S, sid, i)) return;
     const Seg& g = S.seg[sid];
     const double4 p = xw[i];
-    const int cx = cell_coord(p.x, g.inv_lc[0], g.nc[0]);
-    const int cy = cell_coord(p.y, g.inv_lc[1], g.nc[1]);
-    const int cz = cell_coord(p.z, g.inv_lc[2], g.nc[2]);
-    const int c = g.cell_off + (cz * g.nc[1] + cy) * g.nc[0] + cx;
-    cell_of[i] = c;
-    atomicAdd(&count[c], 1);
+    atomicAdd(&count[cell_index(g, p)], 1);
     if (g.build) xbuild[i] = p;
 }
 
@@ -267,15 +273,15 @@ __global__ void k_fill_zero2(int* __restrict__ a, int64_t na, int* __restrict__ 
 // reads a candidate's position, index and type in one 32-byte access.  The
 // w lane is never used in arithmetic.
 __global__ void __launch_bounds__(kBlock)
-k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ cell_of,
-            const int* __restrict__ start, int* __restrict__ fill, double4* __restrict__ xcell)
+k_cell_fill(Segs S, const double4* __restrict__ xw, const int* __restrict__ start,
+            int* __restrict__ fill, double4* __restrict__ xcell)
 {
     int sid;
     int64_t i;
     if (!block_atom(S, sid, i)) return;
-    const int c = cell_of[i];
-    const int p = start[c] + atomicAdd(&fill[c], 1);
     const double4 x = xw[i];
+    const int c = cell_index(S.seg[sid], x);
+    const int p = start[c] + atomicAdd(&fill[c], 1);
     xcell[p] = make_double4(x.x, x.y, x.z, __hiloint2double((int)x.w, (int)i));
 }
 
@@ -342,7 +348,7 @@ template <bool TYPED, int LANES, int CW>
 __global__ void __launch_bounds__(kSearchBlock)
 k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, double rl2_hi,
          double rc2, ListRadii R, int M,
-         int64_t cap, const int* __restrict__ cell_of, const int* __restrict__ start,
+         int64_t cap, const int* __restrict__ start,
          int* __restrict__ nn, int* __restrict__ nl, int* __restrict__ maxnn,
          unsigned* __restrict__ status, unsigned* __restrict__ sstat)
 {
@@ -385,7 +391,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
             rl2_i = t_rl2[ti * kMaxTypes];
             for (int b = 1; b < R.nt; ++b) rl2_i = fmax(rl2_i, t_rl2[ti * kMaxTypes + b]);
         }
-        const int c = cell_of[i] - g.cell_off;
+        const int c = cell_index(g, xi) - g.cell_off;   // xi: the binned position
         const int cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
         // The stencil cells to visit, as bits k = 9 (oz + 1) + 3 (oy + 1) +
         // (ox + 1).  A cell at offset (ox, oy, oz) whose nearest point is
@@ -642,7 +648,7 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
         if (nb > 65536) nb = 65536;
         k_fill_zero2<<<(int)nb, kBlock, 0, s>>>(b.cell_count, total_cells, b.maxnn, S.nseg);
     }
-    k_cell_count<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_count, b.xbuild);
+    k_cell_count<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_count, b.xbuild);
     const int nscan = (total_cells + kScanTile - 1) / kScanTile;
     if (nscan <= kScanOneBlockTiles) {
         k_scan_one_block<<<1, kBlock, 0, s>>>(b.cell_count, total_cells, b.cell_start,
@@ -655,7 +661,7 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
         k_scan_write<<<nscan, kBlock, 0, s>>>(b.cell_count, total_cells, bsum, b.cell_start,
                                               b.cell_fill);
     }
-    k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_of, b.cell_start, b.cell_fill,
+    k_cell_fill<<<S.nblk, kBlock, 0, s>>>(S, b.xw[cur], b.cell_start, b.cell_fill,
                                           b.xcell);
     const size_t lds = sizeof(int) * (size_t)kSearchBlock * b.M;
     const double rl2 = rlist * rlist;
@@ -669,7 +675,7 @@ hipError_t launch_build_neighbors(const Buffers& b, const Segs& S, int total_cel
         constexpr bool TY = decltype(typed_tag)::value;
         constexpr int LN = decltype(lanes_tag)::value;
         k_search<TY, LN, kSearchCands><<<nsb, kSearchBlock, lds, s>>>(
-            S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_of, b.cell_start,
+            S, b.xcell, rl2, lo, hi, rcut * rcut, R, b.M, b.cap, b.cell_start,
             b.nn, b.nl, b.maxnn, b.status, b.sstat);
     };
     using T1 = std::integral_constant<int, 1>;
