@@ -309,7 +309,7 @@ __device__ __forceinline__ const auto& center_of(const TersoffArg<T, MULTI>& K,
 
 // One thread, any number of bonds (the overflow pass).  tp of bond c is the
 // table index ti * kMaxTypes + tj.
-template <class T, int MAXC, bool FIXED, bool MULTI>
+template <class T, int MAXC, bool MULTI>
 __device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, const TersoffLds<T>& L,
                                              int64_t i, int64_t cap, const double4& xi,
                                              unsigned long long msk, int cnt,
@@ -322,8 +322,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, cons
     const int ti = MULTI ? (int)xi.w : 0;
     const auto& pc = center_of<T, MULTI>(K, L, ti);
     unsigned long long rem = msk;
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+    for (int c = 0; c < cnt; ++c) {
         ux[c] = uy[c] = uz[c] = rr[c] = fc[c] = dfc[c] = zp[c] = pd[c] = T(0);
         slot[c] = 0;
         tp[c] = 0;
@@ -339,10 +338,8 @@ __device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, cons
         }
     }
     // zeta_c over unordered pairs: g(cos_ce) is shared by zeta_c and zeta_e.
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
-#pragma unroll
-        for (int e = c + 1; e < (FIXED ? MAXC : cnt); ++e) {
+    for (int c = 0; c < cnt; ++c) {
+        for (int e = c + 1; e < cnt; ++e) {
             if (e < cnt) {
                 const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
                 T g, dg;
@@ -355,8 +352,7 @@ __device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, cons
     // bond orders, site energy (accumulated in FP64), pair-derivative factor
     // pd_c and P_c
     double u_i = 0.0;
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+    for (int c = 0; c < cnt; ++c) {
         if (c < cnt) {
             const auto& pp = pair_of<T, MULTI>(K, L, tp[c]);
             T b, db;
@@ -374,13 +370,11 @@ __device__ __forceinline__ void tersoff_site(const TersoffArg<T, MULTI>& K, cons
     }
     U[i] = 0.5 * u_i;
     // partials dU_i/dr_c
-#pragma unroll
-    for (int c = 0; c < (FIXED ? MAXC : cnt); ++c) {
+    for (int c = 0; c < cnt; ++c) {
         if (c < cnt) {
             const T ir = nr_rcp(rr[c]);
             T dx = T(0.5) * pd[c] * ux[c], dy = T(0.5) * pd[c] * uy[c], dz = T(0.5) * pd[c] * uz[c];
-#pragma unroll
-            for (int e = 0; e < (FIXED ? MAXC : cnt); ++e) {
+            for (int e = 0; e < cnt; ++e) {
                 if (e != c && e < cnt) {
                     const T cs = ux[c] * ux[e] + uy[c] * uy[e] + uz[c] * uz[e];
                     T g, dg;
@@ -743,7 +737,7 @@ k_tersoff_partials_ovf(TersoffArg<T, MULTI> K, Segs S, int64_t cap, const double
         const double4 xi = xw[i];
         const Box box = S.seg[seg_of_atom(S, i)].box;
         const unsigned long long msk = mask[i];
-        tersoff_site<T, kMaxSlots, false, MULTI>(K, L, i, cap, xi, msk, __popcll(msk), nl, xw,
+        tersoff_site<T, kMaxSlots, MULTI>(K, L, i, cap, xi, msk, __popcll(msk), nl, xw,
                                                  box, U, dpart);
     }
 }
