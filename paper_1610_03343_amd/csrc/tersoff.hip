@@ -55,11 +55,22 @@ struct TPair {
 // launch.
 template <class T, bool MULTI>
 struct TersoffArg;
+// b = (1 + u)^a, a = -1/(2n), as a polynomial in w = u - u0 on
+// [kBPolyLo, kBPolyHi] (the range of u in a silicon crystal near room
+// temperature, u ~ 0.07): its Taylor series about u0 = 7/64, the coefficients
+// d_k = C(a, k) (1 + u0)^(a - k) formed on the host in extended precision.
+// With |w| <= 5/64 the first omitted term is ~2e-17 of b.  FP64
+// single-element kernels only (the one-thread overflow routine, the mixed
+// and the multi-element kernels keep the logarithm and exponential).
+constexpr int kBPolyTerms = 14;
+constexpr double kBPolyLo = 0x1p-5, kBPolyHi = 0x3p-4, kBPolyU0 = 0x7p-6;
+
 template <class T>
 struct TersoffArg<T, false> {   // the centre and pair constants of one element, flat
     T A, B, lam, mu, beta, n, inv2n, c2, c2_d2, d2, h, R, pi_sr;
     T u_series, a1, a2, a3, a4, a5;
     T S;
+    double bpoly[kBPolyTerms];   // d_0 .. d_13 (used when T is double)
 };
 template <class T>
 struct TersoffArg<T, true> {
@@ -157,6 +168,15 @@ TersoffArg<T, false> tersoff_single(const TersoffTable& tab, double* S2)
     k.a4 = c.a4;
     k.a5 = c.a5;
     k.S = p.S;
+    {
+        const long double a = -1.0L / (2.0L * (long double)tab.elem[0].n);
+        const long double v0 = 1.0L + (long double)kBPolyU0;
+        long double binom = 1.0L;   // C(a, j)
+        for (int j = 0; j < kBPolyTerms; ++j) {
+            k.bpoly[j] = (double)(binom * powl(v0, a - (long double)j));
+            binom *= (a - (long double)j) / (long double)(j + 1);
+        }
+    }
     *S2 = S * S;
     return k;
 }
@@ -261,17 +281,32 @@ __device__ __forceinline__ void angular_g(const P& p, T cs, T& g, T& dg)
 // the second form is the common one; ln(1 + u) is taken of the rounded sum,
 // whose absolute error (half an ulp of 1 + u) becomes a relative error of
 // about 1e-16 / (2n) in b for any u, so no log1p is needed.
+// bp: the polynomial's coefficients (d_0 .. d_13, then u0, lo, hi) in LDS,
+// or null: between lo and hi it replaces the logarithm and exponential.
 template <class P, class T>
-__device__ __forceinline__ void bond_order(const P& p, T zeta, T& b, T& db)
+__device__ __forceinline__ void bond_order(const P& p, T zeta, T& b, T& db,
+                                           const double* bp = nullptr)
 {
     b = T(1);
     db = T(0);
     if (zeta > T(0)) {
         const T u = t_exp(p.n * t_log(p.beta * zeta));
-        if (u < p.u_series)
+        if (u < p.u_series) {
             b = T(1) + u * (p.a1 + u * (p.a2 + u * (p.a3 + u * (p.a4 + u * p.a5))));
-        else
-            b = t_exp(-t_log<false>(T(1) + u) * p.inv2n);
+        } else {
+            bool done = false;
+            if constexpr (sizeof(T) == 8) {
+                if (bp && u >= bp[kBPolyTerms + 1] && u <= bp[kBPolyTerms + 2]) {
+                    const double w = u - bp[kBPolyTerms];
+                    double acc = bp[kBPolyTerms - 1];
+#pragma unroll
+                    for (int j = kBPolyTerms - 2; j >= 0; --j) acc = fma(acc, w, bp[j]);
+                    b = acc;
+                    done = true;
+                }
+            }
+            if (!done) b = t_exp(-t_log<false>(T(1) + u) * p.inv2n);
+        }
         db = -b * u * nr_rcp(T(2) * zeta * (T(1) + u));
     }
 }
@@ -507,11 +542,23 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
 {
     __shared__ TersoffLds<T> L;
     __shared__ int order[MULTI ? kQuadAtoms : 1];
+    constexpr bool kPoly = !MULTI && sizeof(T) == 8;   // the bond-order polynomial
+    __shared__ double bp[kPoly ? kBPolyTerms + 3 : 1];
     const int q = threadIdx.x & (kQuad - 1);
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
     if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    if constexpr (kPoly) {
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < kBPolyTerms; ++j) bp[j] = K.bpoly[j];
+            bp[kBPolyTerms] = kBPolyU0;
+            bp[kBPolyTerms + 1] = kBPolyLo;
+            bp[kBPolyTerms + 2] = kBPolyHi;
+        }
+        __syncthreads();
+    }
     const int first = (lb - g.blk_quad) * kQuadAtoms;
     int a = threadIdx.x >> 2;
     if constexpr (MULTI) {
@@ -676,7 +723,7 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
         if (c < kc) {
             const auto& pp = pair_of<T, MULTI>(K, L, tp[s]);
             T b, db;
-            bond_order(pc, zp[s], b, db);
+            bond_order(pc, zp[s], b, db, kPoly ? bp : nullptr);
             if constexpr (MULTI) {
                 b *= pp.chi;
                 db *= pp.chi;
