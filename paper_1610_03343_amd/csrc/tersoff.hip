@@ -557,7 +557,7 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
             bp[kBPolyTerms + 1] = kBPolyLo;
             bp[kBPolyTerms + 2] = kBPolyHi;
         }
-        __syncthreads();
+        // published by the barrier after the cutoff test
     }
     const int first = (lb - g.blk_quad) * kQuadAtoms;
     int a = threadIdx.x >> 2;
@@ -597,6 +597,13 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
         msk = quad_cutoff_mask_typed(xi, ti, i, cap, nnb, q, nl, xw, box, L.S2, d_first, t_first);
     else
         msk = quad_cutoff_mask<false>(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
+    if constexpr (kPoly) {
+        // The coefficients are the only LDS data written so far (an LDS-only
+        // fence); the wait sits behind the cutoff test's gathers.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
     const int cnt = __popcll(msk);
     const bool ovf = cnt > kQuad * SLOTS;
     if (valid && q == 0) {
