@@ -193,13 +193,16 @@ k_sw_site_quad(SWK<T> p, double rc2, Segs S, int M, int64_t cap,
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
-    if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    const int phase = S.phase_in[sid];
     const Box box = g.box;
     const int local = (lb - g.blk_quad) * kQuadAtoms + (threadIdx.x >> 2);
     const int64_t i = g.atom_off + local;
     const bool valid = local < g.n;
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int nnb = valid ? min(nn[i], M) : 0;
+    // a finished segment (kept for retrieval) is left as it is; the test
+    // follows the first loads (in bounds for it too) to share their wait
+    if (phase > g.nsteps) return;
     Disp d_first;
     const unsigned long long msk = quad_cutoff_mask<true>(xi, i, cap, nnb, q, nl, xw, box, rc2, d_first);
     const int cnt = __popcll(msk);

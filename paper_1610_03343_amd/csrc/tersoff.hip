@@ -548,7 +548,7 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int sid = seg_of_block(S, lb, true);
     const Seg& g = S.seg[sid];
-    if (S.phase_in[sid] > g.nsteps) return;   // finished segment, kept for retrieval
+    const int phase = S.phase_in[sid];
     if constexpr (kPoly) {
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -590,6 +590,11 @@ k_tersoff_site_quad(TersoffArg<T, MULTI> K, double rc2, Segs S, int M, int64_t c
     const double4 xi = valid ? xw[i] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int ti = MULTI ? (int)xi.w : 0;
     const int nnb = valid ? min(nn[i], M) : 0;
+    // A finished segment (kept for retrieval) is left as it is.  The test
+    // follows the first loads, which are in bounds for it too, so that they
+    // share one wait with it (block-uniform: before any barrier of the block
+    // that the others would miss).
+    if (phase > g.nsteps) return;
     Disp d_first;
     int t_first = 0;
     unsigned long long msk;
