@@ -327,10 +327,11 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 }
 
 // LANES (1, 2 or 4) lanes per atom of a segment being built: lane q walks the
-// stencil rows q, q + LANES, ... into a sorted list of its own, kept
-// in LDS (column-major over the block so that neighbouring threads hit
-// distinct banks); each lane then writes its entries at their ranks in the
-// union of the lanes' lists, slot-major.  The union's order does not depend
+// stencil rows q, q + LANES, ... into a list of its own, kept in LDS
+// (column-major over the block so that neighbouring threads hit distinct
+// banks); each lane then writes its entries at their ranks in the union of
+// the lanes' lists, slot-major (one lane sorts its list; several count the
+// smaller keys of every list of the atom).  The union's order does not depend
 // on how the offsets were split, so the list is the one a single walk
 // gives.  A search block covers kSearchBlock / LANES atoms; 256 LANES /
 // kSearchBlock of them make one 256-atom block of the other per-atom kernels.
@@ -428,7 +429,7 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         }
         // Candidate at cell-order slot p (atom i itself sits at p0) against
         // the list radius of the pair; an entry is appended to the lane's LDS
-        // list (capacity M), which is sorted by key once the walk is done.
+        // list (capacity M), ranked by key once the walk is done.
         // Past M entries (an overflow, which fails the call) an entry
         // replaces the largest key if it is smaller, so the list keeps the
         // M smallest keys.
@@ -527,16 +528,19 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
             b2 = nb2;
             e2 = ne2;
         }
-        // the lane's entries in ascending key order (keys are distinct)
-        const int w = cnt < M ? cnt : M;
-        for (int t = 1; t < w; ++t) {
-            const unsigned key = (unsigned)buf[t * kSearchBlock];
-            int pos = t;
-            while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
-                buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
-                --pos;
+        // one lane per atom: its entries in ascending key order (keys are
+        // distinct), so that an entry's position is its rank
+        if constexpr (LANES == 1) {
+            const int w = cnt < M ? cnt : M;
+            for (int t = 1; t < w; ++t) {
+                const unsigned key = (unsigned)buf[t * kSearchBlock];
+                int pos = t;
+                while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
+                    buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
+                    --pos;
+                }
+                buf[pos * kSearchBlock] = (int)key;
             }
-            buf[pos * kSearchBlock] = (int)key;
         }
     }
     // counts of the quad's other lanes (every lane of the wave takes part)
@@ -562,13 +566,21 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         const int wr[3] = {min(c1, M), min(c2, M), min(c3, M)};
         for (int p = 0; p < w; ++p) {
             const unsigned key = (unsigned)buf[p * kSearchBlock];
-            // rank in the union: own position plus the smaller keys of the
-            // other three (sorted) lists; keys are distinct
+            // rank in the union (keys are distinct): with one lane the sorted
+            // position; with several, the count of smaller keys over every
+            // lane's list of the atom, own included, read without early exits
+            // so that the reads do not wait on one another
             int rank = p;
+            if constexpr (LANES > 1) {
+                rank = 0;
+#pragma unroll 4
+                for (int t = 0; t < w; ++t) rank += (unsigned)buf[t * kSearchBlock] < key;
 #pragma unroll
-            for (int r = 1; r < LANES; ++r) {
-                const int* col = lbuf + (threadIdx.x ^ r);
-                for (int t = 0; t < wr[r - 1] && (unsigned)col[t * kSearchBlock] < key; ++t) ++rank;
+                for (int r = 1; r < LANES; ++r) {
+                    const int* col = lbuf + (threadIdx.x ^ r);
+#pragma unroll 4
+                    for (int t = 0; t < wr[r - 1]; ++t) rank += (unsigned)col[t * kSearchBlock] < key;
+                }
             }
             // (k_reverse, which always follows, writes every reverse slot)
             if (rank < M) nl[(int64_t)rank * cap + i] = (int)(key & 0x7fffffffu);
