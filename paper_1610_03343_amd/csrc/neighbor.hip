@@ -306,9 +306,6 @@ __device__ __forceinline__ int search_quad_xor(int v)
     return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, false);
 }
 
-// One thread per atom; its sorted list is kept in LDS (column-major over the
-// block so that neighbouring threads hit distinct banks), then written out
-// slot-major.
 // A cheap test (multiply by 1/L, fused arithmetic allowed) settles every
 // candidate whose squared distance is not within a relative 1e-10 of r_list^2;
 // only those near the boundary take the exact unfused test above, whose
@@ -330,8 +327,8 @@ __device__ __forceinline__ bool in_list(const double4& a, const double4& b, cons
 // stencil rows q, q + LANES, ... into a list of its own, kept in LDS
 // (column-major over the block so that neighbouring threads hit distinct
 // banks); each lane then writes its entries at their ranks in the union of
-// the lanes' lists, slot-major (one lane sorts its list; several count the
-// smaller keys of every list of the atom).  The union's order does not depend
+// the lanes' lists, slot-major, each rank the count of smaller keys over
+// every list of the atom.  The union's order does not depend
 // on how the offsets were split, so the list is the one a single walk
 // gives.  A search block covers kSearchBlock / LANES atoms; 256 LANES /
 // kSearchBlock of them make one 256-atom block of the other per-atom kernels.
@@ -528,20 +525,6 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
             b2 = nb2;
             e2 = ne2;
         }
-        // one lane per atom: its entries in ascending key order (keys are
-        // distinct), so that an entry's position is its rank
-        if constexpr (LANES == 1) {
-            const int w = cnt < M ? cnt : M;
-            for (int t = 1; t < w; ++t) {
-                const unsigned key = (unsigned)buf[t * kSearchBlock];
-                int pos = t;
-                while (pos > 0 && (unsigned)buf[(pos - 1) * kSearchBlock] > key) {
-                    buf[pos * kSearchBlock] = buf[(pos - 1) * kSearchBlock];
-                    --pos;
-                }
-                buf[pos * kSearchBlock] = (int)key;
-            }
-        }
     }
     // counts of the quad's other lanes (every lane of the wave takes part)
     int c1 = 0, c2 = 0, c3 = 0;
@@ -566,21 +549,18 @@ k_search(Segs S, const double4* __restrict__ xcell, double rl2, double rl2_lo, d
         const int wr[3] = {min(c1, M), min(c2, M), min(c3, M)};
         for (int p = 0; p < w; ++p) {
             const unsigned key = (unsigned)buf[p * kSearchBlock];
-            // rank in the union (keys are distinct): with one lane the sorted
-            // position; with several, the count of smaller keys over every
-            // lane's list of the atom, own included, read without early exits
-            // so that the reads do not wait on one another
-            int rank = p;
-            if constexpr (LANES > 1) {
-                rank = 0;
+            // rank in the union (keys are distinct): the count of smaller
+            // keys over every lane's list of the atom, own included, read
+            // without early exits so that the reads do not wait on one
+            // another (no list is sorted)
+            int rank = 0;
 #pragma unroll 4
-                for (int t = 0; t < w; ++t) rank += (unsigned)buf[t * kSearchBlock] < key;
+            for (int t = 0; t < w; ++t) rank += (unsigned)buf[t * kSearchBlock] < key;
 #pragma unroll
-                for (int r = 1; r < LANES; ++r) {
-                    const int* col = lbuf + (threadIdx.x ^ r);
+            for (int r = 1; r < LANES; ++r) {
+                const int* col = lbuf + (threadIdx.x ^ r);
 #pragma unroll 4
-                    for (int t = 0; t < wr[r - 1]; ++t) rank += (unsigned)col[t * kSearchBlock] < key;
-                }
+                for (int t = 0; t < wr[r - 1]; ++t) rank += (unsigned)col[t * kSearchBlock] < key;
             }
             // (k_reverse, which always follows, writes every reverse slot)
             if (rank < M) nl[(int64_t)rank * cap + i] = (int)(key & 0x7fffffffu);
