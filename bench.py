@@ -41,7 +41,9 @@ Also measured, as extra fields of the same line:
            with the list rebuilt every 5 steps
   serving  a Poisson request trace through the continuous-batching loop and
            through one structure per launch, p50/p99 latency to results on
-           the host, both precisions, and an HBM-capped batch
+           the host, both precisions, and an HBM-capped batch; the batched
+           loop serves the trace --serve-runs times and reports its
+           median-p99 run
   roofline the dominant kernel against its bound, timed with HIP events: the
            Tersoff site pass against the FP64 vector peak (algorithmic
            FLOPs), the pairwise pass against HBM bandwidth (algorithmic bytes)
@@ -619,14 +621,25 @@ def bench_serving(mb, wl, torch, args):
            "nve_fraction": sum(1 for j in jobs if j.n_steps) / len(jobs),
            "rebuild_every": every, "latency": "arrival to results (U, F, W, J, x, v) on the host"}
     for prec in ("fp64", "mixed"):
-        log(f"serving: batched {prec}")
-        _, sb = serving.serve_batched(c, jobs, precision=prec, rebuild_every=every,
-                                      rerun_ctx=rc)
+        # The tail of one trace moves from run to run (the host loop's timing
+        # and the GPU clock): the batched loop serves the same trace
+        # --serve-runs times, and the run with the median p99 is reported,
+        # every run's p50/p99 beside it.
+        runs = []
+        for k in range(max(1, args.serve_runs)):
+            log(f"serving: batched {prec}, run {k + 1}")
+            _, sb = serving.serve_batched(c, jobs, precision=prec, rebuild_every=every,
+                                          rerun_ctx=rc)
+            runs.append(sb.summary())
+        order = sorted(range(len(runs)), key=lambda k: runs[k]["p99_ms"])
+        sb_sum = runs[order[len(runs) // 2]]
         log(f"serving: one structure per launch {prec}")
         _, ss = serving.serve_sequential(c, jobs, precision=prec, rebuild_every=every)
-        res[prec] = {"batched": sb.summary(), "one_per_launch": ss.summary()}
-        log(f"serving {prec}: batched p50/p99 {sb.summary()['p50_ms']:.2f}/"
-            f"{sb.summary()['p99_ms']:.2f} ms; one per launch "
+        res[prec] = {"batched": sb_sum, "one_per_launch": ss.summary(),
+                     "batched_runs_p50_p99_ms": [[round(r["p50_ms"], 3), round(r["p99_ms"], 3)]
+                                                 for r in runs]}
+        log(f"serving {prec}: batched p50/p99 {sb_sum['p50_ms']:.2f}/"
+            f"{sb_sum['p99_ms']:.2f} ms (median-p99 run of {len(runs)}); one per launch "
             f"{ss.summary()['p50_ms']:.2f}/{ss.summary()['p99_ms']:.2f} ms")
     log(f"serving: batched fp64 with a {args.serve_cap_mib} MiB HBM budget")
     _, sc = serving.serve_batched(c, jobs, precision="fp64", rebuild_every=every,
@@ -765,6 +778,8 @@ def main():
     ap.add_argument("--serve-calib", type=int, default=400)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-cap-mib", type=int, default=64)
+    ap.add_argument("--serve-runs", type=int, default=3,
+                    help="batched serving runs of the same trace; the median-p99 run is reported")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed FP64 runs for median/min/max and an output check")
     ap.add_argument("--sweep-cells", default="5,10,15,20,30,40,50,60,70",
